@@ -1,0 +1,202 @@
+/*
+ * fmmg.h -- C-ABI of the MI355X (gfx950) octree fast-multipole gravity solve.
+ *
+ * The operation (arXiv:1908.03121, Sec. 4.3 "The FMM hotspot"): an adaptive
+ * octree whose nodes are 8x8x8 sub-grids of cells (Sec. 4.2) carries a mass
+ * density in its leaf cells; the solve returns the gravitational potential and
+ * acceleration of every leaf cell.  It runs the method's three steps:
+ *   1. upward pass: leaf cells are point masses m = rho h^3 at their centres;
+ *      refined cells get mass, centre of mass and multipole moments (orders
+ *      0..3) from their children, bottom-up;
+ *   2. same-level interactions: every cell interacts with the same-level
+ *      cells that the opening criterion selects (the 1074-element stencil of
+ *      Sec. 4.3), in the four classes refined/leaf target x refined/leaf
+ *      source, producing order-3 Taylor coefficients plus the correction that
+ *      conserves linear and angular momentum to round-off (Sec. 4.2);
+ *   3. downward pass: each parent's expansion is re-expanded at its
+ *      children's centres of mass and accumulated, top-down.
+ *
+ * Interaction rule (opening criterion).  Same-level cells A, B with integer
+ * coordinates cA, cB, d = cB - cA, D = floor(cB/2) - floor(cA/2):
+ *     evaluated at this level  <=>  (top level under FMMG_TOP_FULL  or |D|^2 <= 8)
+ *                                   and (|d|^2 >= 9 or A is a leaf or B is a leaf),
+ * which evaluates every ordered pair of leaf cells exactly once.
+ *
+ * Tree description.  A sub-grid at level l >= 0 with integer coordinates
+ * s >= 0 covers origin + L0 * 2^-l * [s, s+1)^3 and holds 8^3 cells of edge
+ * h = L0 / (8 * 2^l).  A sub-grid is refined iff its 8 children are listed.
+ * Every sub-grid above level 0 has its parent listed; sub-grids without a
+ * parent are at level 0 (a forest of level-0 sub-grids is allowed).
+ * Several trees (the batched form) never interact with each other.
+ *
+ * Layouts.  Leaves are numbered in the order they appear in the descriptor,
+ * trees concatenated.  rho, phi are [leaf][512] and g is [leaf][3][512]; the
+ * 512 cells of a sub-grid are ordered (i*8 + j)*8 + k for cell (i, j, k) along
+ * (x, y, z), k fastest.  All three are contiguous float64 device buffers owned
+ * by the caller; the library only reads rho and only writes phi and g.
+ *
+ * Streams.  Every call that takes hip_stream enqueues work on that stream
+ * (NULL = the null stream) and returns without waiting for it; the caller
+ * synchronises.  A plan is bound to the device that is current when it is
+ * created and must be used with that device current.  A plan is not
+ * re-entrant: two solves on one plan must not overlap in time (use two
+ * plans).  No C++ exception crosses this interface.
+ *
+ * Errors.  Every call returns an fmmg_status; on failure fmmg_last_error()
+ * returns a thread-local text that names the cause.
+ */
+#ifndef FMMG_H
+#define FMMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FMMG_VERSION 1
+
+typedef struct fmmg_plan fmmg_plan; /* opaque; owns device tables and workspaces */
+
+typedef enum {
+    FMMG_OK = 0,
+    FMMG_EINVAL = -1,        /* bad argument: null pointer, size, option value, bad density */
+    FMMG_ETREE = -2,         /* malformed tree: duplicate, missing parent, 1..7 children, ... */
+    FMMG_ENOMEM = -3,        /* device or host allocation failed                             */
+    FMMG_EHIP = -4,          /* a HIP runtime call failed                                    */
+    FMMG_EUNSUPPORTED = -5   /* no gfx950 device, or an unsupported combination               */
+} fmmg_status;
+
+typedef enum {
+    FMMG_FP64 = 0,           /* every step in FP64                                            */
+    FMMG_MIXED = 1           /* same-level pair terms in FP32 with FP32 partial sums per
+                                source plane, flushed into FP64 expansions; moments, the
+                                passes, accumulation and the correction's sums in FP64     */
+} fmmg_precision;
+
+typedef enum {
+    FMMG_TOP_FULL = 0,         /* complete solve: the top level evaluates all its pairs      */
+    FMMG_TOP_STENCIL_ONLY = 1  /* the top level uses the parent-near stencil like any other  */
+                               /* level (kernel test of one sub-grid neighbourhood)          */
+} fmmg_top_mode;
+
+typedef struct {
+    int32_t n_subgrids;       /* > 0                                                  */
+    const int32_t* level;     /* host [n_subgrids], 0 <= level <= 19                  */
+    const int32_t* coord;     /* host [n_subgrids][3], 0 <= coord < 2^19             */
+    double origin[3];         /* corner of level-0 sub-grid (0,0,0)                   */
+    double L0;                /* edge of a level-0 sub-grid, > 0                       */
+} fmmg_tree_desc;
+
+typedef struct {
+    fmmg_precision precision;   /* default FMMG_FP64                                    */
+    fmmg_top_mode top_mode;     /* default FMMG_TOP_FULL                                */
+    double G;                   /* gravitational constant, default 1.0                  */
+    int32_t angular_correction; /* 1 (default) | 0 = uncorrected result (tests only)    */
+    int32_t use_graph;          /* 1 = capture the launch sequence in a hipGraph on the
+                                   first solve and replay it (re-captured when the
+                                   rho/phi/g pointers or the stream change); 0 = eager  */
+    int32_t persistent;         /* 1 = same-level step as one persistent launch over a
+                                   work list of all classes and trees; 0 = one launch
+                                   per class                                            */
+    int32_t timing;             /* 1 = eager solves record a hipEvent at every stage
+                                   boundary on the solve's stream (fmmg_get_timings);
+                                   not allowed together with use_graph                  */
+    const char* tuning_cache;   /* JSON file of tuned launch shapes, or NULL            */
+} fmmg_options;
+
+/* Stages of one solve, in launch order. */
+typedef enum {
+    FMMG_STAGE_P2M = 0,         /* leaf cell masses                                     */
+    FMMG_STAGE_M2M = 1,         /* upward pass, all levels                              */
+    FMMG_STAGE_TOP = 2,         /* top level under the all-pairs rule (+ reduction)     */
+    FMMG_STAGE_MONO = 3,        /* leaf targets, leaf sources (class 3)                 */
+    FMMG_STAGE_MP_REFINED = 4,  /* refined targets (classes 1 and 2)                    */
+    FMMG_STAGE_MP_LEAF = 5,     /* leaf targets, refined sources (class 4)              */
+    FMMG_STAGE_DOWN = 6,        /* downward pass and leaf output                        */
+    FMMG_N_STAGES = 7
+} fmmg_stage;
+
+typedef struct {
+    double ms[FMMG_N_STAGES];   /* summed stage durations (milliseconds)                */
+    int64_t launches[FMMG_N_STAGES]; /* kernel launches per stage and solve             */
+    int64_t solves;             /* number of solves summed                              */
+} fmmg_timings;
+
+typedef struct {
+    int64_t pairs[4];      /* ordered cell pairs per class: [0] refined<-leaf,
+                              [1] refined<-refined, [2] leaf<-leaf, [3] leaf<-refined   */
+    int64_t pairs_top;     /* pairs evaluated at the top level under FMMG_TOP_FULL       */
+    int64_t launches;      /* kernel launches enqueued by the last solve                 */
+    int64_t solves;        /* solves enqueued on this plan                               */
+    double paper_flops;    /* pairs weighted 12 (leaf<-leaf) or 455 (all others) flop,
+                              the per-interaction counts of Sec. 4.3                     */
+    int64_t n_leaves;
+    int64_t n_refined;
+    int32_t max_level;
+    int32_t n_trees;
+} fmmg_stats;
+
+/* Fills *opt with the defaults listed above. */
+void fmmg_default_options(fmmg_options* opt);
+
+/* Validates the trees, builds neighbour/parent/child tables, stencil tables
+ * and work lists, and allocates device workspaces on the current device.
+ * trees: host array [n_trees], n_trees >= 1 (n_trees > 1 is the batched form).
+ * opt may be NULL (defaults).  hip_stream: stream for the table uploads.
+ * Returns FMMG_ETREE for a malformed tree, FMMG_EUNSUPPORTED if the current
+ * device is not gfx950.  On success *out owns everything it allocated. */
+fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32_t n_trees,
+                             const fmmg_options* opt, void* hip_stream);
+
+/* Number of leaf sub-grids (the leading dimension of rho, phi and g). */
+fmmg_status fmmg_plan_n_leaves(const fmmg_plan* plan, int64_t* n_leaves);
+
+/* leaf_desc_index: host [n_leaves]; entry i = descriptor index of leaf i within
+ * its own tree's descriptor. */
+fmmg_status fmmg_leaf_order(const fmmg_plan* plan, int32_t* leaf_desc_index);
+
+/* Runs the whole solve (steps 1-3) on hip_stream.
+ * rho: device float64 [n_leaves][512], finite and >= 0 (not checked here; see
+ *      fmmg_check_density);
+ * phi: device float64 [n_leaves][512]; g: device float64 [n_leaves][3][512].
+ * Asynchronous: returns once the work is enqueued. */
+fmmg_status fmmg_solve(fmmg_plan* plan, const double* rho, double* phi, double* g,
+                       void* hip_stream);
+
+/* Checks on the device that every density is finite and >= 0; synchronises
+ * hip_stream.  Returns FMMG_OK or FMMG_EINVAL (with the first bad index in
+ * the error text). */
+fmmg_status fmmg_check_density(fmmg_plan* plan, const double* rho, void* hip_stream);
+
+/* Sums the stage durations of the solves enqueued with options.timing = 1
+ * since the previous call (or plan creation), then starts a new sum.  The
+ * caller must have synchronised the solves' stream.  FMMG_EINVAL if the plan
+ * was created without timing. */
+fmmg_status fmmg_get_timings(fmmg_plan* plan, fmmg_timings* out);
+
+/* Pair counts and launch counters of the plan (host values; no device work). */
+fmmg_status fmmg_get_stats(const fmmg_plan* plan, fmmg_stats* stats);
+
+/* Releases every device and host resource of the plan; NULL is a no-op.
+ * The caller must make sure no solve on the plan is still running. */
+void fmmg_plan_destroy(fmmg_plan* plan);
+
+/* Thread-local text for the last non-OK status returned on this thread. */
+const char* fmmg_last_error(void);
+
+/* Host-only: validates the trees and counts the ordered pairs per class that
+ * a solve with this top_mode evaluates (no device is touched).  stats->pairs,
+ * pairs_top, paper_flops, n_leaves, n_refined, max_level and n_trees are
+ * filled; the launch counters are zero. */
+fmmg_status fmmg_count_pairs(const fmmg_tree_desc* trees, int32_t n_trees,
+                             fmmg_top_mode top_mode, fmmg_stats* stats);
+
+/* Version of this interface (FMMG_VERSION). */
+int32_t fmmg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMMG_H */

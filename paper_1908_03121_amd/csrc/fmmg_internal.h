@@ -1,0 +1,95 @@
+// fmmg_internal.h -- data layouts shared by the host planner, the API layer
+// and the gfx950 kernels of the octree FMM gravity solve.
+//
+// Device layouts (all float64 unless noted; "q" is the internal cell index
+// q = (z*8 + y)*8 + x inside a sub-grid, x fastest, so that a z-plane of a
+// sub-grid is 64 contiguous values):
+//   mass [n_leaf][512]            leaf cell masses m = rho h^3
+//   rec  [n_ref][16][512]         refined cells: m, COM offset from the cell
+//                                 centre (3), trace-free quadrupole (5:
+//                                 xx yy xy xz yz), trace-free octupole
+//                                 (7: xxx xxy xxz xyy xyz yyy yyz)
+//   Lr   [n_ref][19][512]         refined cells' Taylor coefficients: L0, L1
+//                                 (3), trace-free L2 (5), trace-free L3 (7) and
+//                                 the correction sum S (3); own (same-level)
+//                                 after step 2, total after step 3
+//   Lf   [n_leaf][4][512]         leaf cells' own potential and acceleration
+// Trace-free storage is exact here: every contraction of the method is with a
+// derivative tensor of 1/r, which is harmonic (trace-free), and trace parts
+// of children's moments contribute only trace parts to the parent's.
+#pragma once
+
+#include <stdint.h>
+
+namespace fmmg {
+
+constexpr int NS = 8;          // cells per sub-grid edge
+constexpr int NCELL = 512;     // cells per sub-grid
+constexpr int REACH = 5;       // max |d_i| of the stencil
+constexpr int PW = NS + 2 * REACH;  // 18: edge of the source window around a sub-grid
+constexpr int PCELLS = PW * PW;     // 324 cells in one source z-plane window
+constexpr int NREC = 16;       // record components of a refined cell
+constexpr int NLOC = 19;       // Taylor components of a refined cell
+constexpr int NLEAF = 4;       // phi, gx, gy, gz of a leaf cell
+constexpr int NDZ = 10;        // canonical dz range [-4, 5] of the parity-000 stencil
+constexpr int DZ0 = -4;
+constexpr int MAX_N2 = 76;     // |d|^2 <= 5^2*3 = 75
+
+// record component indices
+enum { R_M = 0, R_DX = 1, R_DY = 2, R_DZ = 3, R_Q = 4, R_O = 9 };
+// Taylor component indices
+enum { T_L0 = 0, T_L1 = 1, T_L2 = 4, T_L3 = 9, T_S = 16 };
+
+struct SubDev {
+    double h;          // cell edge
+    int32_t kind;      // 0 leaf, 1 refined
+    int32_t idx;       // index into the leaf or the refined arrays
+    int32_t level;
+    int32_t tree;
+    int32_t nbr[27];   // same-level neighbour sub-grid ids, -1 absent;
+                       // slot (ox+1)*9 + (oy+1)*3 + (oz+1) for offset (ox,oy,oz)
+    int32_t child[8];  // refined: child sub-grid ids, slot ex*4 + ey*2 + ez
+    int32_t coord[3];
+    int32_t flags;     // bit0: has a leaf neighbour; bit1: has a refined neighbour
+};
+
+// Canonical stencil tables (parity (0,0,0); other parities are mirror images:
+// a cell of parity p uses offset (sx*dx, sy*dy, sz*dz) with s = 1 - 2p).
+struct StencilTables {
+    // multipole kernels: entries grouped by canonical dz (DZ0..DZ0+NDZ-1),
+    // far entries first, then near ones.  entry = (dx+8) | (dy+8) << 8
+    int32_t mp_entry[743];
+    int32_t mp_far_begin[NDZ], mp_far_count[NDZ];
+    int32_t mp_near_begin[NDZ], mp_near_count[NDZ];
+    // monopole kernel: columns (dx, dy) with the contiguous dz range [lo, hi];
+    // packed (dx+8) | (dy+8) << 8 | (lo+8) << 16 | (hi+8) << 24
+    int32_t col[128];
+    int32_t n_col;
+    int32_t pad;
+    double invr[MAX_N2];     // 1/sqrt(n)
+    double invr3[MAX_N2];    // n^-3/2
+    double dzinvr3[NDZ][MAX_N2];  // dz * n^-3/2
+};
+
+// Top-level (all pairs) work item: 64 target cells (plane zt of sub-grid
+// target) against the source cells [src_begin, src_end) of the tree's
+// top-level source list; partial sums go to slot part.
+struct TopItem {
+    int32_t target;
+    int32_t zt;
+    int32_t src_begin;
+    int32_t src_end;
+    int32_t part;      // partial slot
+    int32_t src_list;  // offset of the tree's top-level source list
+    int32_t pad0, pad1;
+};
+
+// Reduction of the partial slots of one top-level target sub-grid.
+struct TopReduce {
+    int32_t target;
+    int32_t part_begin;
+    int32_t n_part;
+    int32_t pad;
+};
+
+}  // namespace fmmg

@@ -1,0 +1,313 @@
+// planner.cpp -- host-side planning of the octree FMM solve: tree validation,
+// neighbour/child tables, the canonical stencil, work lists and pair counts.
+//
+// The interaction rule (opening criterion, arXiv:1908.03121 Sec. 4.3) for
+// same-level cells cA, cB with d = cB - cA and D = floor(cB/2) - floor(cA/2):
+// evaluated iff (all-pairs top level or |D|^2 <= 8) and (|d|^2 >= 9 or one
+// side is a leaf).  Per parity of cA the parent-near set has 743 offsets
+// (651 far, 92 near); the 8 parity sets are mirror images of one another,
+// so one canonical table (parity 0,0,0) serves every cell.
+#include "planner.hpp"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <unordered_map>
+
+namespace fmmg {
+
+namespace {
+
+int floordiv(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+uint64_t key_of(int l, int x, int y, int z) {
+    return (uint64_t(l) << 57) | (uint64_t(x) << 38) | (uint64_t(y) << 19) | uint64_t(z);
+}
+
+// canonical (parity 0,0,0) parent-near offsets
+struct Canon {
+    std::vector<int> dx, dy, dz;
+    std::vector<int> far;
+};
+
+const Canon& canon() {
+    static Canon c = [] {
+        Canon k;
+        for (int dz = -REACH; dz <= REACH; ++dz)
+            for (int dx = -REACH; dx <= REACH; ++dx)
+                for (int dy = -REACH; dy <= REACH; ++dy) {
+                    if (!dx && !dy && !dz) continue;
+                    int Dx = floordiv(dx, 2), Dy = floordiv(dy, 2), Dz = floordiv(dz, 2);
+                    if (Dx * Dx + Dy * Dy + Dz * Dz > 8) continue;
+                    k.dx.push_back(dx);
+                    k.dy.push_back(dy);
+                    k.dz.push_back(dz);
+                    k.far.push_back(dx * dx + dy * dy + dz * dz >= 9);
+                }
+        return k;
+    }();
+    return c;
+}
+
+// Per neighbour slot, the number of (target cell, stencil offset) pairs whose
+// source falls into that slot, far and near separately.
+struct SlotCounts {
+    int64_t far[27], nearc[27];
+};
+
+const SlotCounts& slot_counts() {
+    static SlotCounts s = [] {
+        SlotCounts k;
+        memset(&k, 0, sizeof(k));
+        const Canon& c = canon();
+        for (int q = 0; q < NCELL; ++q) {
+            int x = q & 7, y = (q >> 3) & 7, z = q >> 6;
+            int sx = 1 - 2 * (x & 1), sy = 1 - 2 * (y & 1), sz = 1 - 2 * (z & 1);
+            for (size_t e = 0; e < c.dx.size(); ++e) {
+                int bx = x + sx * c.dx[e], by = y + sy * c.dy[e], bz = z + sz * c.dz[e];
+                int slot = (floordiv(bx, 8) + 1) * 9 + (floordiv(by, 8) + 1) * 3 + (floordiv(bz, 8) + 1);
+                if (c.far[e]) k.far[slot]++;
+                else k.nearc[slot]++;
+            }
+        }
+        return k;
+    }();
+    return s;
+}
+
+// far pairs between two refined top-level sub-grids at offset o (|o_i| <= 1)
+int64_t top_far_pairs(int ox, int oy, int oz) {
+    static int64_t tab[27];
+    static bool init = false;
+    if (!init) {
+        for (int t = 0; t < 27; ++t) {
+            int px = t / 9 - 1, py = (t / 3) % 3 - 1, pz = t % 3 - 1;
+            int64_t n = 0;
+            for (int a = 0; a < NCELL; ++a)
+                for (int b = 0; b < NCELL; ++b) {
+                    int dx = 8 * px + (b >> 6) - (a >> 6);
+                    int dy = 8 * py + ((b >> 3) & 7) - ((a >> 3) & 7);
+                    int dz = 8 * pz + (b & 7) - (a & 7);
+                    if (dx * dx + dy * dy + dz * dz >= 9) ++n;
+                }
+            tab[t] = n;
+        }
+        init = true;
+    }
+    if (ox < -1 || ox > 1 || oy < -1 || oy > 1 || oz < -1 || oz > 1) return int64_t(NCELL) * NCELL;
+    return tab[(ox + 1) * 9 + (oy + 1) * 3 + (oz + 1)];
+}
+
+}  // namespace
+
+void build_stencil_tables(StencilTables* t) {
+    memset(t, 0, sizeof(*t));
+    const Canon& c = canon();
+    int pos = 0;
+    for (int g = 0; g < NDZ; ++g) {
+        int dz = DZ0 + g;
+        for (int pass = 0; pass < 2; ++pass) {
+            int begin = pos;
+            for (size_t e = 0; e < c.dx.size(); ++e) {
+                if (c.dz[e] != dz || c.far[e] != (pass == 0)) continue;
+                t->mp_entry[pos++] = (c.dx[e] + 8) | ((c.dy[e] + 8) << 8);
+            }
+            if (pass == 0) { t->mp_far_begin[g] = begin; t->mp_far_count[g] = pos - begin; }
+            else { t->mp_near_begin[g] = begin; t->mp_near_count[g] = pos - begin; }
+        }
+    }
+    // columns: contiguous dz range per (dx, dy); the self offset is skipped by the kernel
+    int nc = 0;
+    for (int dx = -REACH; dx <= REACH; ++dx)
+        for (int dy = -REACH; dy <= REACH; ++dy) {
+            int lo = 100, hi = -100;
+            for (size_t e = 0; e < c.dx.size(); ++e)
+                if (c.dx[e] == dx && c.dy[e] == dy) { lo = std::min(lo, c.dz[e]); hi = std::max(hi, c.dz[e]); }
+            if (lo > hi) continue;
+            t->col[nc++] = (dx + 8) | ((dy + 8) << 8) | ((lo + 8) << 16) | ((hi + 8) << 24);
+        }
+    t->n_col = nc;
+    for (int n = 1; n < MAX_N2; ++n) {
+        double s = sqrt(double(n));
+        t->invr[n] = 1.0 / s;
+        t->invr3[n] = 1.0 / (double(n) * s);
+        for (int g = 0; g < NDZ; ++g) t->dzinvr3[g][n] = double(DZ0 + g) * t->invr3[n];
+    }
+}
+
+int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chunks,
+                    HostPlan* out, std::string* err) {
+    HostPlan& P = *out;
+    P = HostPlan();
+    if (!trees || n_trees < 1) { *err = "need at least one tree"; return -1; }
+    if (top_chunks < 1) top_chunks = 1;
+    P.n_trees = n_trees;
+    P.top_full = top_full;
+    int64_t total = 0;
+    for (int t = 0; t < n_trees; ++t) {
+        const TreeIn& T = trees[t];
+        if (T.n < 1 || !T.level || !T.coord) { *err = "tree " + std::to_string(t) + ": empty or null arrays"; return -1; }
+        if (!(T.L0 > 0.0) || !isfinite(T.L0)) { *err = "tree " + std::to_string(t) + ": L0 must be finite and > 0"; return -1; }
+        total += T.n;
+    }
+    if (total > (int64_t(1) << 30)) { *err = "too many sub-grids"; return -1; }
+    P.subs.resize(size_t(total));
+    std::vector<int> refined(size_t(total), 0);
+    std::vector<std::unordered_map<uint64_t, int32_t>> maps(n_trees);
+    int64_t base = 0;
+    for (int t = 0; t < n_trees; ++t) {
+        const TreeIn& T = trees[t];
+        P.sub_tree_base.push_back(int32_t(base));
+        auto& M = maps[t];
+        M.reserve(size_t(T.n) * 2);
+        for (int i = 0; i < T.n; ++i) {
+            int l = T.level[i], x = T.coord[3 * i], y = T.coord[3 * i + 1], z = T.coord[3 * i + 2];
+            if (l < 0 || l > 19 || x < 0 || y < 0 || z < 0 || x >= (1 << 19) || y >= (1 << 19) || z >= (1 << 19)) {
+                *err = "tree " + std::to_string(t) + ", sub-grid " + std::to_string(i) + ": level/coordinate out of range";
+                return -2;
+            }
+            if (!M.emplace(key_of(l, x, y, z), int32_t(base + i)).second) {
+                *err = "tree " + std::to_string(t) + ", sub-grid " + std::to_string(i) + ": duplicate";
+                return -2;
+            }
+        }
+        for (int i = 0; i < T.n; ++i) {
+            int l = T.level[i], x = T.coord[3 * i], y = T.coord[3 * i + 1], z = T.coord[3 * i + 2];
+            SubDev& S = P.subs[size_t(base + i)];
+            memset(&S, 0, sizeof(S));
+            S.level = l;
+            S.tree = t;
+            S.coord[0] = x; S.coord[1] = y; S.coord[2] = z;
+            S.h = T.L0 / (8.0 * ldexp(1.0, l));
+            if (l > 0 && !M.count(key_of(l - 1, x >> 1, y >> 1, z >> 1))) {
+                *err = "tree " + std::to_string(t) + ", sub-grid " + std::to_string(i) + ": parent missing";
+                return -2;
+            }
+            int nchild = 0;
+            for (int e = 0; e < 8; ++e) {
+                auto it = M.find(key_of(l + 1, 2 * x + (e >> 2), 2 * y + ((e >> 1) & 1), 2 * z + (e & 1)));
+                S.child[e] = it == M.end() ? -1 : it->second;
+                nchild += it != M.end();
+            }
+            if (nchild != 0 && nchild != 8) {
+                *err = "tree " + std::to_string(t) + ", sub-grid " + std::to_string(i) + ": has " +
+                       std::to_string(nchild) + " of 8 children";
+                return -2;
+            }
+            refined[size_t(base + i)] = nchild == 8;
+            if (l > P.max_level) P.max_level = l;
+            for (int o = 0; o < 27; ++o) {
+                int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
+                int nx = x + ox, ny = y + oy, nz = z + oz;
+                S.nbr[o] = -1;
+                if (nx < 0 || ny < 0 || nz < 0) continue;
+                auto it = M.find(key_of(l, nx, ny, nz));
+                if (it != M.end()) S.nbr[o] = it->second;
+            }
+        }
+        base += T.n;
+    }
+    // leaf / refined numbering in descriptor order, trees concatenated
+    for (int t = 0; t < n_trees; ++t) {
+        for (int i = 0; i < trees[t].n; ++i) {
+            int32_t s = P.sub_tree_base[t] + i;
+            SubDev& S = P.subs[size_t(s)];
+            if (refined[size_t(s)]) {
+                S.kind = 1;
+                S.idx = int32_t(P.ref_sub.size());
+                P.ref_sub.push_back(s);
+            } else {
+                S.kind = 0;
+                S.idx = int32_t(P.leaf_sub.size());
+                P.leaf_sub.push_back(s);
+                P.leaf_desc.push_back(i);
+            }
+        }
+    }
+    for (SubDev& S : P.subs) {
+        for (int o = 0; o < 27; ++o) {
+            if (o == 13 || S.nbr[o] < 0) continue;
+            S.flags |= P.subs[size_t(S.nbr[o])].kind ? 2 : 1;
+        }
+    }
+    // work lists and pair counts of the stencil step
+    const SlotCounts& sc = slot_counts();
+    for (int32_t s = 0; s < int32_t(P.subs.size()); ++s) {
+        const SubDev& S = P.subs[size_t(s)];
+        bool top = S.level == 0 && top_full;
+        if (S.level == 0 && S.kind == 0) P.top_leaf.push_back(s);
+        if (top) continue;
+        if (S.kind) P.mp_ref.push_back(s);
+        else {
+            P.mono_leaf.push_back(s);
+            if (S.flags & 2) P.mp_leaf.push_back(s);
+        }
+        for (int o = 0; o < 27; ++o) {
+            if (S.nbr[o] < 0) continue;
+            int nk = P.subs[size_t(S.nbr[o])].kind;
+            if (S.kind) {
+                if (nk) P.counts.cls[1] += sc.far[o];
+                else P.counts.cls[0] += sc.far[o] + sc.nearc[o];
+            } else {
+                if (nk) P.counts.cls[3] += sc.far[o] + sc.nearc[o];
+                else P.counts.cls[2] += sc.far[o] + sc.nearc[o];
+            }
+        }
+    }
+    P.level_ref_begin.assign(size_t(P.max_level) + 2, 0);
+    for (int l = 0; l <= P.max_level; ++l) {
+        P.level_ref_begin[size_t(l)] = int32_t(P.ref_by_level.size());
+        for (int32_t s : P.ref_sub)
+            if (P.subs[size_t(s)].level == l) P.ref_by_level.push_back(s);
+    }
+    P.level_ref_begin[size_t(P.max_level) + 1] = int32_t(P.ref_by_level.size());
+    // top level under the all-pairs rule
+    if (top_full) {
+        for (int t = 0; t < n_trees; ++t) {
+            int32_t list_off = int32_t(P.top_src.size());
+            std::vector<int32_t> tops;
+            for (int i = 0; i < trees[t].n; ++i)
+                if (trees[t].level[i] == 0) tops.push_back(P.sub_tree_base[t] + i);
+            P.top_src.insert(P.top_src.end(), tops.begin(), tops.end());
+            int64_t ncells = int64_t(tops.size()) * NCELL;
+            int nchunk = int(std::min<int64_t>(top_chunks, ncells));
+            int64_t chunk = (ncells + nchunk - 1) / nchunk;
+            nchunk = int((ncells + chunk - 1) / chunk);
+            for (int32_t T : tops) {
+                TopReduce R;
+                memset(&R, 0, sizeof(R));
+                R.target = T;
+                R.part_begin = P.n_top_parts;
+                R.n_part = nchunk;
+                for (int k = 0; k < nchunk; ++k) {
+                    for (int zt = 0; zt < NS; ++zt) {
+                        TopItem it;
+                        memset(&it, 0, sizeof(it));
+                        it.target = T;
+                        it.zt = zt;
+                        it.src_begin = int32_t(k * chunk);
+                        it.src_end = int32_t(std::min<int64_t>(ncells, (k + 1) * chunk));
+                        it.part = P.n_top_parts + k;
+                        it.src_list = list_off;
+                        P.top_items.push_back(it);
+                    }
+                }
+                P.n_top_parts += nchunk;
+                P.top_reduce.push_back(R);
+                const SubDev& ST = P.subs[size_t(T)];
+                for (int32_t Sb : tops) {
+                    const SubDev& SS = P.subs[size_t(Sb)];
+                    int64_t n;
+                    if (!ST.kind || !SS.kind) n = int64_t(NCELL) * NCELL - (Sb == T ? NCELL : 0);
+                    else n = top_far_pairs(SS.coord[0] - ST.coord[0], SS.coord[1] - ST.coord[1],
+                                           SS.coord[2] - ST.coord[2]);
+                    P.counts.top += n;
+                }
+            }
+        }
+    }
+    return 0;
+}
+
+}  // namespace fmmg

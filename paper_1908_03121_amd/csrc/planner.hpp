@@ -1,0 +1,64 @@
+// planner.hpp -- host-side planning of the octree FMM solve (no device code).
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "fmmg_internal.h"
+
+namespace fmmg {
+
+struct TreeIn {
+    int32_t n;
+    const int32_t* level;
+    const int32_t* coord;
+    double origin[3];
+    double L0;
+};
+
+struct PairCounts {
+    int64_t cls[4] = {0, 0, 0, 0};  // refined<-leaf, refined<-refined, leaf<-leaf, leaf<-refined
+    int64_t top = 0;
+    double paper_flops() const {
+        return 12.0 * double(cls[2]) + 455.0 * double(cls[0] + cls[1] + cls[3] + top);
+    }
+};
+
+struct HostPlan {
+    int n_trees = 0;
+    int top_full = 1;
+    int max_level = 0;
+    std::vector<SubDev> subs;          // all sub-grids, trees concatenated
+    std::vector<int32_t> sub_tree_base;  // first global sub id of each tree
+    std::vector<int32_t> leaf_sub;     // global leaf order -> sub id
+    std::vector<int32_t> leaf_desc;    // global leaf order -> descriptor index in its tree
+    std::vector<int32_t> ref_sub;      // refined index -> sub id
+
+    // work lists (global sub ids)
+    std::vector<int32_t> mp_ref;       // refined targets of the stencil step
+    std::vector<int32_t> mono_leaf;    // leaf targets of the stencil step
+    std::vector<int32_t> mp_leaf;      // leaf targets with a refined neighbour
+    std::vector<int32_t> level_ref_begin;  // refined sub ids sorted by level: [l, l+1)
+    std::vector<int32_t> ref_by_level;
+    std::vector<int32_t> top_leaf;     // top-level leaves (output straight from own terms)
+
+    // top level under the all-pairs rule
+    std::vector<int32_t> top_src;      // per tree, its level-0 sub ids (concatenated)
+    std::vector<TopItem> top_items;
+    std::vector<TopReduce> top_reduce;
+    int32_t n_top_parts = 0;
+
+    PairCounts counts;
+};
+
+// Validates trees and builds every host table.  Returns 0, or -1 (argument)
+// / -2 (malformed tree) with a message in *err.
+int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chunks,
+                    HostPlan* out, std::string* err);
+
+// Fills the canonical stencil tables.
+void build_stencil_tables(StencilTables* t);
+
+}  // namespace fmmg

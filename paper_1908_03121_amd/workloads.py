@@ -53,11 +53,11 @@ class TreeDesc:
         return int(self.level.shape[0])
 
     def refined_mask(self) -> np.ndarray:
-        keys = {(int(l), *map(int, c)) for l, c in zip(self.level, self.coord)}
-        out = np.zeros(self.n_subgrids, dtype=bool)
-        for i, (l, c) in enumerate(zip(self.level, self.coord)):
-            out[i] = (int(l) + 1, 2 * int(c[0]), 2 * int(c[1]), 2 * int(c[2])) in keys
-        return out
+        lv = self.level.astype(np.int64)
+        c = self.coord.astype(np.int64)
+        key = (lv << 57) | (c[:, 0] << 38) | (c[:, 1] << 19) | c[:, 2]
+        child = ((lv + 1) << 57) | ((2 * c[:, 0]) << 38) | ((2 * c[:, 1]) << 19) | (2 * c[:, 2])
+        return np.isin(child, key)
 
     def leaf_indices(self) -> np.ndarray:
         return np.nonzero(~self.refined_mask())[0].astype(np.int32)
@@ -150,12 +150,18 @@ def lane_emden(n: float = 1.5, dxi: float = 1e-4):
 
 
 def polytrope(points: np.ndarray, centre, radius: float, rho_c: float) -> np.ndarray:
-    """Density of an n = 1.5 polytrope at ``points`` [..., 3]; zero outside."""
+    """Density of an n = 1.5 polytrope at ``points`` [..., 3]; zero outside.
+    theta is interpolated linearly on the uniform RK4 grid."""
     xs, ths, xi1, _ = lane_emden()
-    r = np.sqrt(((points - np.asarray(centre)) ** 2).sum(-1))
-    xi = xi1 * r / radius
-    th = np.interp(xi, xs, ths, right=0.0)
-    return rho_c * np.clip(th, 0.0, None) ** 1.5
+    d = points - np.asarray(centre)
+    xi = np.sqrt((d * d).sum(-1)) * (xi1 / radius)
+    step = xs[2] - xs[1]
+    u = xi / step
+    i = np.minimum(u.astype(np.int64), xs.shape[0] - 2)
+    f = np.clip(u - i, 0.0, 1.0)
+    th = ths[i] * (1.0 - f) + ths[i + 1] * f
+    th = np.where(xi < xi1, np.maximum(th, 0.0), 0.0)
+    return rho_c * th * np.sqrt(th)
 
 
 def polytrope_rho_c(mass: float, radius: float) -> float:
@@ -204,23 +210,26 @@ def adaptive_tree(density: Callable[[np.ndarray], np.ndarray], max_level: int,
                   threshold: float, origin=(0.0, 0.0, 0.0), L0: float = 1.0) -> TreeDesc:
     """Refine from a single root: a sub-grid below ``max_level`` is refined iff
     the maximum of ``density`` over its own cell centres exceeds ``threshold``.
-    Sub-grids are listed level by level (breadth first)."""
+    Sub-grids are listed level by level (breadth first, sorted coordinates)."""
     subs = [(0, 0, 0, 0)]
-    frontier = [(0, (0, 0, 0))]
-    while frontier:
-        nxt = []
-        for (l, c) in frontier:
-            if l >= max_level:
-                continue
-            if float(density(_subgrid_cell_centres(l, c, origin, L0)).max()) > threshold:
-                for ex in (0, 1):
-                    for ey in (0, 1):
-                        for ez in (0, 1):
-                            cc = (2 * c[0] + ex, 2 * c[1] + ey, 2 * c[2] + ez)
-                            nxt.append((l + 1, cc))
-        nxt.sort()
-        subs.extend((l, *c) for (l, c) in nxt)
-        frontier = nxt
+    frontier = np.zeros((1, 3), dtype=np.int64)
+    ijk = np.arange(N_SUB) + 0.5
+    local = np.stack(np.meshgrid(ijk, ijk, ijk, indexing="ij"), -1).reshape(-1, 3)
+    e = np.array([(x, y, z) for x in (0, 1) for y in (0, 1) for z in (0, 1)], dtype=np.int64)
+    for l in range(max_level):
+        if frontier.shape[0] == 0:
+            break
+        h = L0 / (N_SUB * 2.0 ** l)
+        refine = np.zeros(frontier.shape[0], dtype=bool)
+        for b0 in range(0, frontier.shape[0], 4096):
+            fb = frontier[b0:b0 + 4096]
+            pts = np.asarray(origin) + (fb[:, None, :] * N_SUB + local[None]) * h
+            refine[b0:b0 + 4096] = density(pts).max(axis=1) > threshold
+        kids = (2 * frontier[refine][:, None, :] + e[None]).reshape(-1, 3)
+        order = np.lexsort((kids[:, 2], kids[:, 1], kids[:, 0]))
+        kids = kids[order]
+        subs.extend((l + 1, int(c[0]), int(c[1]), int(c[2])) for c in kids)
+        frontier = kids
     return _desc_from_list(subs, origin, L0)
 
 
@@ -261,15 +270,24 @@ def _binary_fields(q: float, a: float, r1: float, r2: float):
     return dens, max(rc1, rc2), (x1, x2)
 
 
+def binary_tree(q: float, a: float, r1: float, r2: float, max_level: int,
+                refine_frac: float = 1e-4):
+    dens, rmax, _ = _binary_fields(q, a, r1, r2)
+    return adaptive_tree(dens, max_level, refine_frac * rmax), dens, rmax
+
+
+def binary_density(tree: TreeDesc, dens, rmax: float, rng: np.random.Generator,
+                   noise: float = 0.01, floor_frac: float = 1e-10) -> np.ndarray:
+    x = tree.leaf_cell_centres()
+    u = rng.uniform(-1.0, 1.0, size=x.shape[:-1])
+    return np.ascontiguousarray(dens(x) * (1.0 + noise * u) + floor_frac * rmax)
+
+
 def binary_star(q: float, a: float, r1: float, r2: float, max_level: int,
                 rng: np.random.Generator, noise: float = 0.01,
                 refine_frac: float = 1e-4, floor_frac: float = 1e-10):
-    dens, rmax, _ = _binary_fields(q, a, r1, r2)
-    tree = adaptive_tree(dens, max_level, refine_frac * rmax)
-    x = tree.leaf_cell_centres()
-    u = rng.uniform(-1.0, 1.0, size=x.shape[:-1])
-    rho = dens(x) * (1.0 + noise * u) + floor_frac * rmax
-    return tree, np.ascontiguousarray(rho)
+    tree, dens, rmax = binary_tree(q, a, r1, r2, max_level, refine_frac)
+    return tree, binary_density(tree, dens, rmax, rng, noise, floor_frac)
 
 
 def c2(seed: int = 2, max_level: int = 5, r1: float = 0.25, r2: float = 0.10) -> Workload:
@@ -287,7 +305,8 @@ def eggleton(q: float) -> float:
 
 
 def c4_tree(t: int, base_seed: int = 4, lo: int = 500, hi: int = 8000):
-    """One binary-star tree of the batch; redrawn until lo <= leaves <= hi."""
+    """One binary-star tree of the batch; parameters are redrawn until the tree
+    has lo <= leaves <= hi, then the noise is drawn."""
     rng = np.random.default_rng(base_seed * 1000 + t)
     while True:
         q = float(rng.uniform(0.05, 0.5))
@@ -300,8 +319,9 @@ def c4_tree(t: int, base_seed: int = 4, lo: int = 500, hi: int = 8000):
             r1 *= s
             r2 *= s
         max_level = int(rng.integers(4, 7))
-        tree, rho = binary_star(q, a, r1, r2, max_level, rng)
+        tree, dens, rmax = binary_tree(q, a, r1, r2, max_level)
         if lo <= tree.n_leaves <= hi:
+            rho = binary_density(tree, dens, rmax, rng)
             return tree, rho, dict(q=q, a=a, r1=r1, r2=r2, max_level=max_level)
 
 
