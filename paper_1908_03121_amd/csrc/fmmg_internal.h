@@ -33,7 +33,8 @@ constexpr int NLOC = 19;       // Taylor components of a refined cell
 constexpr int NLEAF = 4;       // phi, gx, gy, gz of a leaf cell
 constexpr int NDZ = 10;        // canonical dz range [-4, 5] of the parity-000 stencil
 constexpr int DZ0 = -4;
-constexpr int MAX_N2 = 76;     // |d|^2 <= 5^2*3 = 75
+constexpr int MONO_COLS = 100; // canonical (dx, dy) columns
+constexpr int MONO_TAB = 3 * (52 * 10 + 32 * 6 + 16 * 2);  // 2232 kernel values
 
 // record component indices
 enum { R_M = 0, R_DX = 1, R_DY = 2, R_DZ = 3, R_Q = 4, R_O = 9 };
@@ -46,8 +47,9 @@ struct SubDev {
     int32_t idx;       // index into the leaf or the refined arrays
     int32_t level;
     int32_t tree;
-    int32_t nbr[27];   // same-level neighbour sub-grid ids, -1 absent;
-                       // slot (ox+1)*9 + (oy+1)*3 + (oz+1) for offset (ox,oy,oz)
+    int32_t nbr[27];   // same-level neighbours: -1 absent, else (idx << 1) | kind
+                       // (idx into the leaf or refined arrays); slot
+                       // (ox+1)*9 + (oy+1)*3 + (oz+1) for offset (ox,oy,oz)
     int32_t child[8];  // refined: child sub-grid ids, slot ex*4 + ey*2 + ez
     int32_t coord[3];
     int32_t flags;     // bit0: has a leaf neighbour; bit1: has a refined neighbour
@@ -61,14 +63,15 @@ struct StencilTables {
     int32_t mp_entry[743];
     int32_t mp_far_begin[NDZ], mp_far_count[NDZ];
     int32_t mp_near_begin[NDZ], mp_near_count[NDZ];
-    // monopole kernel: columns (dx, dy) with the contiguous dz range [lo, hi];
-    // packed (dx+8) | (dy+8) << 8 | (lo+8) << 16 | (hi+8) << 24
-    int32_t col[128];
-    int32_t n_col;
-    int32_t pad;
-    double invr[MAX_N2];     // 1/sqrt(n)
-    double invr3[MAX_N2];    // n^-3/2
-    double dzinvr3[NDZ][MAX_N2];  // dz * n^-3/2
+    // monopole kernel: the 100 columns (dx, dy) of the canonical stencil fall
+    // into three classes by their dz range: [-4,5] (52 columns), [-2,3] (32),
+    // [0,1] (16).  Columns are sorted by class; entry = (dx+8) | (dy+8) << 8.
+    // mono_tab holds, per column and dz of its range, 1/|d|, |d|^-3 and
+    // dz |d|^-3 (zero for d = 0, the self term).
+    int32_t mono_col[MONO_COLS];
+    int32_t mono_class_begin[4];
+    double mono_tab[MONO_TAB];
+    float mono_tabf[MONO_TAB];
 };
 
 // Top-level (all pairs) work item: 64 target cells (plane zt of sub-grid

@@ -298,7 +298,8 @@ __global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
     __shared__ unsigned char leafflag[PCELLS];
     P* sh = reinterpret_cast<P*>(smem);
 
-    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index: uniform
     const int x = lane & 7, y = lane >> 3;
     const int sid = list[blockIdx.x >> 3];
     const int zt = blockIdx.x & 7;
@@ -329,6 +330,10 @@ __global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
     Acc<double> acc;
     acc.zero();
     const P hx = P(-h * sx), hy = P(-h * sy);
+    // source cell of canonical offset (dx, dy) in the plane window:
+    // c = lbase + sx*dx + (sy*PW)*dy  (mirror signs per lane)
+    const int lbase = (y + REACH) * PW + (x + REACH);
+    const int syw = sy * PW;
 
     for (int zs = zt - REACH; zs <= zt + REACH; ++zs) {
         const int dz = zs - zt;
@@ -345,10 +350,9 @@ __global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
                 const int lx = wx - REACH, ly = wy - REACH;
                 const int ox = lx < 0 ? -1 : (lx >= NS ? 1 : 0);
                 const int oy = ly < 0 ? -1 : (ly >= NS ? 1 : 0);
-                const int nb = T.nbr[(ox + 1) * 9 + (oy + 1) * 3 + (oz + 1)];
+                const int code = T.nbr[(ox + 1) * 9 + (oy + 1) * 3 + (oz + 1)];
                 const int cq = (lz * NS + (ly - NS * oy)) * NS + (lx - NS * ox);
-                int kind = -1, nidx = 0;
-                if (nb >= 0) { kind = subs[nb].kind; nidx = subs[nb].idx; }
+                const int kind = code < 0 ? -1 : (code & 1), nidx = code >> 1;
                 if (kind == 1) {
                     const double* r = rec + size_t(nidx) * NREC * NCELL + cq;
 #pragma unroll
@@ -369,7 +373,7 @@ __global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
         auto one = [&](int e) {
             const int ent = c_tab.mp_entry[e];
             const int dxc = (ent & 255) - 8, dyc = ((ent >> 8) & 255) - 8;
-            const int c = (y + sy * dyc + REACH) * PW + (x + sx * dxc + REACH);
+            const int c = lbase + __mul24(sx, dxc) + __mul24(syw, dyc);
             P src[NREC];
 #pragma unroll
             for (int k = 0; k < NREC; ++k) src[k] = sh[k * PCELLS + c];
@@ -386,7 +390,7 @@ __global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
                 if (!LEAF_T) {
                     const int ent = c_tab.mp_entry[e];
                     const int dxc = (ent & 255) - 8, dyc = ((ent >> 8) & 255) - 8;
-                    const int c = (y + sy * dyc + REACH) * PW + (x + sx * dxc + REACH);
+                    const int c = lbase + __mul24(sx, dxc) + __mul24(syw, dyc);
                     if (!leafflag[c]) continue;
                 }
                 one(e);
@@ -435,11 +439,76 @@ __global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
 // ---------------------------------------------------------------------------
 // step 2b: monopole stencil kernel (leaf targets, leaf sources: class 3)
 // ---------------------------------------------------------------------------
-// block = 512 threads = 8 waves, wave = target plane; the 18^3 leaf-mass box
-// around the sub-grid sits in LDS; the kernel values 1/|d| and d/|d|^3 of the
-// lattice offsets come from scalar tables.
+// Cell pairs on the lattice: R = -h d, so phi = -(G/h) sum m / |d| and
+// g = (G/h^2) sum m d / |d|^3, with the kernel values of each offset taken
+// from tables.  block = 128 threads = 2 waves (one per z parity of the
+// targets); a lane owns the 4 same-parity targets of its (x, y) column,
+// z = pz + 2k.  For one stencil column (dx, dy) the lane loads its source
+// column of masses once and reuses every value for all targets it reaches;
+// the table values are shared by the 4 targets and the 64 lanes.
+template <typename P>
+__device__ __forceinline__ P mono_tab(int i);
+template <>
+__device__ __forceinline__ double mono_tab<double>(int i) { return c_tab.mono_tab[i]; }
+template <>
+__device__ __forceinline__ float mono_tab<float>(int i) { return c_tab.mono_tabf[i]; }
+
+template <int PZ, int LO, int N, typename P>
+__device__ __forceinline__ void mono_class(const P* __restrict__ box, int cbeg, int cend, int tab0,
+                                           int lbase, int sx, int syw, int sy,
+                                           double (&phi)[4], double (&gx)[4], double (&gy)[4],
+                                           double (&gz)[4]) {
+    constexpr int SZ = 1 - 2 * PZ;
+    constexpr int ZMIN = SZ > 0 ? PZ + LO : PZ - (LO + N - 1);  // lowest source z
+    constexpr int NSRC = N + 6;
+    for (int c = cbeg; c < cend; ++c) {
+        const int pk = c_tab.mono_col[c];
+        const int dx = (pk & 255) - 8, dy = ((pk >> 8) & 255) - 8;
+        const P* col = box + lbase + __mul24(sx, dx) + __mul24(syw, dy)
+                       + (ZMIN + REACH) * (PW * PW);
+        P m[NSRC];
+#pragma unroll
+        for (int j = 0; j < NSRC; ++j) m[j] = col[j * (PW * PW)];
+        const int t0 = tab0 + (c - cbeg) * (3 * N);
+        P s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            const P a = mono_tab<P>(t0 + 3 * i), b = mono_tab<P>(t0 + 3 * i + 1),
+                    cz = mono_tab<P>(t0 + 3 * i + 2);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                // target z = PZ + 2k, source z = PZ + 2k + SZ*(LO + i)
+                const P mm = m[PZ + 2 * k + SZ * (LO + i) - ZMIN];
+                s0[k] += mm * a;
+                s1[k] += mm * b;
+                s2[k] += mm * cz;
+            }
+        }
+        const double fx = double(sx * dx), fy = double(sy * dy);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            phi[k] += double(s0[k]);
+            gx[k] += fx * double(s1[k]);
+            gy[k] += fy * double(s1[k]);
+            gz[k] += double(SZ) * double(s2[k]);
+        }
+    }
+}
+
+template <int PZ, typename P>
+__device__ __forceinline__ void mono_all(const P* box, int lbase, int sx, int syw, int sy,
+                                         double (&phi)[4], double (&gx)[4], double (&gy)[4],
+                                         double (&gz)[4]) {
+    const int b0 = c_tab.mono_class_begin[0], b1 = c_tab.mono_class_begin[1];
+    const int b2 = c_tab.mono_class_begin[2], b3 = c_tab.mono_class_begin[3];
+    const int t1 = (b1 - b0) * 30, t2 = t1 + (b2 - b1) * 18;
+    mono_class<PZ, -4, 10, P>(box, b0, b1, 0, lbase, sx, syw, sy, phi, gx, gy, gz);
+    mono_class<PZ, -2, 6, P>(box, b1, b2, t1, lbase, sx, syw, sy, phi, gx, gy, gz);
+    mono_class<PZ, 0, 2, P>(box, b2, b3, t2, lbase, sx, syw, sy, phi, gx, gy, gz);
+}
+
 template <bool MIXED>
-__global__ __launch_bounds__(512) void k_mono(const SubDev* __restrict__ subs,
+__global__ __launch_bounds__(128) void k_mono(const SubDev* __restrict__ subs,
                                               const int32_t* __restrict__ list,
                                               const double* __restrict__ mass,
                                               double* __restrict__ Lf, double G) {
@@ -447,54 +516,39 @@ __global__ __launch_bounds__(512) void k_mono(const SubDev* __restrict__ subs,
     __shared__ P box[PW * PW * PW];
     const int t = threadIdx.x;
     const SubDev& T = subs[list[blockIdx.x]];
-    for (int c = t; c < PW * PW * PW; c += 512) {
+    for (int c = t; c < PW * PW * PW; c += 128) {
         const int wx = c % PW, wy = (c / PW) % PW, wz = c / (PW * PW);
         const int lx = wx - REACH, ly = wy - REACH, lz = wz - REACH;
         const int ox = lx < 0 ? -1 : (lx >= NS ? 1 : 0);
         const int oy = ly < 0 ? -1 : (ly >= NS ? 1 : 0);
         const int oz = lz < 0 ? -1 : (lz >= NS ? 1 : 0);
-        const int nb = T.nbr[(ox + 1) * 9 + (oy + 1) * 3 + (oz + 1)];
+        const int code = T.nbr[(ox + 1) * 9 + (oy + 1) * 3 + (oz + 1)];
         P mm = 0;
-        if (nb >= 0 && subs[nb].kind == 0) {
+        if (code >= 0 && (code & 1) == 0) {
             const int cq = ((lz - NS * oz) * NS + (ly - NS * oy)) * NS + (lx - NS * ox);
-            mm = P(mass[size_t(subs[nb].idx) * NCELL + cq]);
+            mm = P(mass[size_t(code >> 1) * NCELL + cq]);
         }
         box[c] = mm;
     }
     __syncthreads();
-    const int zt = t >> 6, lane = t & 63, x = lane & 7, y = lane >> 3;
-    const int sx = 1 - 2 * (x & 1), sy = 1 - 2 * (y & 1), sz = 1 - 2 * (zt & 1);
-    double phi = 0, gx = 0, gy = 0, gz = 0;
-    const int ncol = c_tab.n_col;
-    for (int ci = 0; ci < ncol; ++ci) {
-        const int pk = c_tab.col[ci];
-        const int dxc = (pk & 255) - 8, dyc = ((pk >> 8) & 255) - 8;
-        const int lo = ((pk >> 16) & 255) - 8, hi = ((pk >> 24) & 255) - 8;
-        const int base = (y + sy * dyc + REACH) * PW + (x + sx * dxc + REACH);
-        const int n2xy = dxc * dxc + dyc * dyc;
-        P s0 = 0, s1 = 0, s2 = 0;
-        for (int dzc = lo; dzc <= hi; ++dzc) {
-            const int n2 = n2xy + dzc * dzc;
-            if (n2 == 0) continue;
-            const P m = box[(zt + sz * dzc + REACH) * (PW * PW) + base];
-            s0 += m * P(c_tab.invr[n2]);
-            s1 += m * P(c_tab.invr3[n2]);
-            s2 += m * P(c_tab.dzinvr3[dzc - DZ0][n2]);
-        }
-        phi += double(s0);
-        gx += double(sx * dxc) * double(s1);
-        gy += double(sy * dyc) * double(s1);
-        gz += double(sz) * double(s2);
-    }
-    // phi = -G sum m/(h|d|);  g = -G sum m R/r^3 with R = -h d  ->  (G/h^2) sum m d/|d|^3
-    const double h = T.h;
-    const int q = zt * 64 + lane;
+    const int pz = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int lane = t & 63, x = lane & 7, y = lane >> 3;
+    const int sx = 1 - 2 * (x & 1), sy = 1 - 2 * (y & 1);
+    const int lbase = (y + REACH) * PW + (x + REACH);
+    const int syw = sy * PW;
+    double phi[4] = {0, 0, 0, 0}, gx[4] = {0, 0, 0, 0}, gy[4] = {0, 0, 0, 0}, gz[4] = {0, 0, 0, 0};
+    if (pz == 0) mono_all<0, P>(box, lbase, sx, syw, sy, phi, gx, gy, gz);
+    else mono_all<1, P>(box, lbase, sx, syw, sy, phi, gx, gy, gz);
+    const double h = T.h, gh = G / (h * h), gp = -G / h;
     double* out = Lf + size_t(T.idx) * NLEAF * NCELL;
-    out[0 * NCELL + q] = -G / h * phi;
-    const double gh = G / (h * h);
-    out[1 * NCELL + q] = gh * gx;
-    out[2 * NCELL + q] = gh * gy;
-    out[3 * NCELL + q] = gh * gz;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int q = (pz + 2 * k) * 64 + lane;
+        out[0 * NCELL + q] = gp * phi[k];
+        out[1 * NCELL + q] = gh * gx[k];
+        out[2 * NCELL + q] = gh * gy[k];
+        out[3 * NCELL + q] = gh * gz[k];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -747,8 +801,8 @@ void launch_mp(const Launch& a, const int32_t* list, int n, bool leaf_targets) {
 
 void launch_mono(const Launch& a, const int32_t* list, int n) {
     if (n <= 0) return;
-    if (a.mixed) hipLaunchKernelGGL((k_mono<true>), dim3(n), dim3(512), 0, a.st, a.subs, list, a.mass, a.Lf, a.G);
-    else hipLaunchKernelGGL((k_mono<false>), dim3(n), dim3(512), 0, a.st, a.subs, list, a.mass, a.Lf, a.G);
+    if (a.mixed) hipLaunchKernelGGL((k_mono<true>), dim3(n), dim3(128), 0, a.st, a.subs, list, a.mass, a.Lf, a.G);
+    else hipLaunchKernelGGL((k_mono<false>), dim3(n), dim3(128), 0, a.st, a.subs, list, a.mass, a.Lf, a.G);
 }
 
 void launch_top(const Launch& a, const TopItem* items, int n_items, const int32_t* top_src,

@@ -117,23 +117,36 @@ void build_stencil_tables(StencilTables* t) {
             else { t->mp_near_begin[g] = begin; t->mp_near_count[g] = pos - begin; }
         }
     }
-    // columns: contiguous dz range per (dx, dy); the self offset is skipped by the kernel
-    int nc = 0;
-    for (int dx = -REACH; dx <= REACH; ++dx)
-        for (int dy = -REACH; dy <= REACH; ++dy) {
-            int lo = 100, hi = -100;
-            for (size_t e = 0; e < c.dx.size(); ++e)
-                if (c.dx[e] == dx && c.dy[e] == dy) { lo = std::min(lo, c.dz[e]); hi = std::max(hi, c.dz[e]); }
-            if (lo > hi) continue;
-            t->col[nc++] = (dx + 8) | ((dy + 8) << 8) | ((lo + 8) << 16) | ((hi + 8) << 24);
-        }
-    t->n_col = nc;
-    for (int n = 1; n < MAX_N2; ++n) {
-        double s = sqrt(double(n));
-        t->invr[n] = 1.0 / s;
-        t->invr3[n] = 1.0 / (double(n) * s);
-        for (int g = 0; g < NDZ; ++g) t->dzinvr3[g][n] = double(DZ0 + g) * t->invr3[n];
+    // monopole columns by dz-range class: [-4,5], [-2,3], [0,1]
+    const int lo_of[3] = {-4, -2, 0}, n_of[3] = {10, 6, 2};
+    int nc = 0, pos_t = 0;
+    for (int cls = 0; cls < 3; ++cls) {
+        t->mono_class_begin[cls] = nc;
+        for (int dx = -REACH; dx <= REACH; ++dx)
+            for (int dy = -REACH; dy <= REACH; ++dy) {
+                int lo = 100, hi = -100;
+                for (size_t e = 0; e < c.dx.size(); ++e)
+                    if (c.dx[e] == dx && c.dy[e] == dy) { lo = std::min(lo, c.dz[e]); hi = std::max(hi, c.dz[e]); }
+                if (dx == 0 && dy == 0) { lo = -4; hi = 5; }  // the self offset sits inside this column
+                if (lo > hi || lo != lo_of[cls] || hi != lo_of[cls] + n_of[cls] - 1) continue;
+                t->mono_col[nc++] = (dx + 8) | ((dy + 8) << 8);
+                for (int i = 0; i < n_of[cls]; ++i) {
+                    int dz = lo + i, n2 = dx * dx + dy * dy + dz * dz;
+                    double a = 0, b = 0;
+                    if (n2 > 0) {
+                        a = 1.0 / sqrt(double(n2));
+                        b = 1.0 / (double(n2) * sqrt(double(n2)));
+                    }
+                    double v[3] = {a, b, dz * b};
+                    for (int k = 0; k < 3; ++k) {
+                        t->mono_tab[pos_t] = v[k];
+                        t->mono_tabf[pos_t] = float(v[k]);
+                        ++pos_t;
+                    }
+                }
+            }
     }
+    t->mono_class_begin[3] = nc;
 }
 
 int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chunks,
@@ -153,6 +166,7 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
     }
     if (total > (int64_t(1) << 30)) { *err = "too many sub-grids"; return -1; }
     P.subs.resize(size_t(total));
+    P.nbr_sub.assign(size_t(total) * 27, -1);
     std::vector<int> refined(size_t(total), 0);
     std::vector<std::unordered_map<uint64_t, int32_t>> maps(n_trees);
     int64_t base = 0;
@@ -200,10 +214,12 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
             for (int o = 0; o < 27; ++o) {
                 int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
                 int nx = x + ox, ny = y + oy, nz = z + oz;
-                S.nbr[o] = -1;
-                if (nx < 0 || ny < 0 || nz < 0) continue;
-                auto it = M.find(key_of(l, nx, ny, nz));
-                if (it != M.end()) S.nbr[o] = it->second;
+                int32_t id = -1;
+                if (nx >= 0 && ny >= 0 && nz >= 0) {
+                    auto it = M.find(key_of(l, nx, ny, nz));
+                    if (it != M.end()) id = it->second;
+                }
+                P.nbr_sub[size_t(base + i) * 27 + size_t(o)] = id;
             }
         }
         base += T.n;
@@ -225,10 +241,14 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
             }
         }
     }
-    for (SubDev& S : P.subs) {
+    for (size_t s = 0; s < P.subs.size(); ++s) {
+        SubDev& S = P.subs[s];
         for (int o = 0; o < 27; ++o) {
-            if (o == 13 || S.nbr[o] < 0) continue;
-            S.flags |= P.subs[size_t(S.nbr[o])].kind ? 2 : 1;
+            int32_t id = P.nbr_sub[s * 27 + size_t(o)];
+            if (id < 0) { S.nbr[o] = -1; continue; }
+            const SubDev& N = P.subs[size_t(id)];
+            S.nbr[o] = (N.idx << 1) | N.kind;
+            if (o != 13) S.flags |= N.kind ? 2 : 1;
         }
     }
     // work lists and pair counts of the stencil step
@@ -244,8 +264,9 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
             if (S.flags & 2) P.mp_leaf.push_back(s);
         }
         for (int o = 0; o < 27; ++o) {
-            if (S.nbr[o] < 0) continue;
-            int nk = P.subs[size_t(S.nbr[o])].kind;
+            int32_t id = P.nbr_sub[size_t(s) * 27 + size_t(o)];
+            if (id < 0) continue;
+            int nk = P.subs[size_t(id)].kind;
             if (S.kind) {
                 if (nk) P.counts.cls[1] += sc.far[o];
                 else P.counts.cls[0] += sc.far[o] + sc.nearc[o];

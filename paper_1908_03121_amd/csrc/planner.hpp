@@ -35,6 +35,7 @@ struct HostPlan {
     std::vector<int32_t> leaf_sub;     // global leaf order -> sub id
     std::vector<int32_t> leaf_desc;    // global leaf order -> descriptor index in its tree
     std::vector<int32_t> ref_sub;      // refined index -> sub id
+    std::vector<int32_t> nbr_sub;      // [n_sub][27] neighbour sub ids (-1 absent)
 
     // work lists (global sub ids)
     std::vector<int32_t> mp_ref;       // refined targets of the stencil step
