@@ -45,11 +45,18 @@ def algorithmic_flops(st):
             + FLOP_PAIR_LEAF_MP * p[3])
 
 
+TUNE_CACHE = os.path.join(os.environ.get("TMPDIR", "/tmp"), "fmmg_tuning.json")
+
+
 def time_form(fm, torch, trees, rho_np, precision, steps, warmup, use_graph=True):
+    """Plans with the launch-shape tuner (its timing runs happen in the first,
+    untimed solve), then times `steps` graph replays."""
     dev = torch.device("cuda:0")
     rho = torch.tensor(rho_np, dtype=torch.float64, device=dev)
-    with fm.Plan(trees, precision=precision, use_graph=use_graph) as plan:
+    with fm.Plan(trees, precision=precision, use_graph=use_graph, autotune=True,
+                 tuning_cache=TUNE_CACHE) as plan:
         phi, g = plan.solve(rho)
+        shape = plan.launch_shape()
         for _ in range(warmup):
             plan.solve(rho, phi, g)
         torch.cuda.synchronize()
@@ -65,17 +72,19 @@ def time_form(fm, torch, trees, rho_np, precision, steps, warmup, use_graph=True
            "paper_convention_gflops": st["paper_flops"] / dt / 1e9,
            "algorithmic_tflops": algorithmic_flops(st) / dt / 1e12,
            "launches_per_step": st["launches"], "n_leaves": st["n_leaves"],
-           "n_trees": st["n_trees"]}
+           "n_trees": st["n_trees"], "launch_shape": shape}
     peak = PEAK_FP64 if precision == "fp64" else PEAK_FP32
     out["frac_peak"] = algorithmic_flops(st) / dt / peak
     return out, phi.cpu().numpy(), g.cpu().numpy(), st
 
 
-def stage_times(fm, torch, trees, rho_np, precision, steps, warmup):
-    """Eager solves with HIP events at every stage boundary on the solve's stream."""
+def stage_times(fm, torch, trees, rho_np, precision, steps, warmup, shape):
+    """Eager solves in the given launch shape with HIP events at every stage
+    boundary on the solve's stream."""
     dev = torch.device("cuda:0")
     rho = torch.tensor(rho_np, dtype=torch.float64, device=dev)
-    with fm.Plan(trees, precision=precision, timing=True) as plan:
+    with fm.Plan(trees, precision=precision, timing=True, persistent=bool(shape["persistent"]),
+                 plane_groups=shape["plane_groups"], blocks_per_cu=shape["blocks_per_cu"]) as plan:
         phi, g = plan.solve(rho)
         for _ in range(warmup):
             plan.solve(rho, phi, g)
@@ -165,22 +174,36 @@ def main():
     log("c1 fp64 (graph)")
     head, phi64, g64, st64 = time_form(fm, torch, c1.trees, c1.rho, "fp64", K, W)
     log(f"  {head['ms_per_step']:.3f} ms/step, {head['cell_interactions_per_s']:.4e} pairs/s")
-    log("c1 fp64 stage timing (eager, HIP events)")
-    stages, launches, eager_ms, st_e = stage_times(fm, torch, c1.trees, c1.rho, "fp64", K, W)
+    shape = head["launch_shape"]
+    log(f"c1 fp64 stage timing (eager, HIP events), shape {shape}")
+    stages, launches, eager_ms, st_e = stage_times(fm, torch, c1.trees, c1.rho, "fp64", K, W, shape)
     log(f"  stages {stages}")
-    k1_pairs = st_e["pairs"][0] + st_e["pairs"][1]
-    k1_ms = stages["mp_refined"] / max(1, launches["mp_refined"])
-    achieved = k1_pairs * FLOP_PAIR_REFINED / (k1_ms * 1e-3)
-    traffic = traffic_entry("k_mp_refined_fp64_c1")
+    p = st_e["pairs"]
+    if shape["persistent"]:
+        # one persistent launch evaluates every same-level class
+        kname = "k_persist<fp64> (all same-level classes, one launch)"
+        flops = algorithmic_flops(st_e)
+        kms = stages["fused"]  # one persistent launch per solve (+ counter reset, top reduction)
+        units = sum(p) + st_e["pairs_top"]
+        tkey = "k_persist_fp64_c1"
+    else:
+        kname = "k_class<refined-target multipole, fp64> (classes 1+2)"
+        flops = (p[0] + p[1]) * FLOP_PAIR_REFINED
+        kms = stages["mp_refined"] / max(1, launches["mp_refined"])
+        units = p[0] + p[1]
+        tkey = "k_class_mp_ref_fp64_c1"
+    achieved = flops / (kms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic,
-                "kernel": "k_mp<refined target, fp64> (classes 1+2)",
-                "launch_ms": k1_ms, "flop_per_pair": FLOP_PAIR_REFINED, "pairs_per_launch": k1_pairs}
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic_entry(tkey),
+                "kernel": kname, "launch_ms": kms, "pairs_per_launch": units,
+                "flop_per_pair": {"refined_target": FLOP_PAIR_REFINED, "leaf_multipole": FLOP_PAIR_LEAF_MP,
+                                  "leaf_leaf": FLOP_PAIR_MONO}}
     mono_ms = stages["mono"]
     forms = {"c1_fp64": head}
     forms["c1_fp64"]["stages_ms"] = stages
     forms["c1_fp64"]["eager_ms_per_step"] = eager_ms
-    forms["c1_fp64"]["mono_kernel_tflops"] = st_e["pairs"][2] * FLOP_PAIR_MONO / (mono_ms * 1e-3) / 1e12
+    if mono_ms > 0 and not shape["persistent"]:
+        forms["c1_fp64"]["mono_kernel_tflops"] = p[2] * FLOP_PAIR_MONO / (mono_ms * 1e-3) / 1e12
     forms["c1_fp64"]["residual_force_torque"] = residuals(np, c1.trees, c1.rho, g64)
 
     log("c1 mixed (graph)")
@@ -243,7 +266,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "uniform level-3 octree: 585 sub-grids of 8^3 cells, 64^3 leaf "
                                "cells, n=1.5 polytrope r=0.3 + 1e-10 floor",
-                   "precision": "fp64", "launch": "hipGraph", "pairs_per_step": head["pairs_per_step"],
+                   "precision": "fp64", "launch": "hipGraph", "launch_shape": shape,
+                   "pairs_per_step": head["pairs_per_step"],
                    "frac_fp64_peak_whole_solve": head["frac_peak"]},
         "roofline": roofline,
         "cpu_baseline": cpu,

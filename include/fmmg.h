@@ -102,6 +102,16 @@ typedef struct {
     int32_t timing;             /* 1 = eager solves record a hipEvent at every stage
                                    boundary on the solve's stream (fmmg_get_timings);
                                    not allowed together with use_graph                  */
+    int32_t plane_groups;       /* source-plane groups per refined-target item: 1 or 2
+                                   (each group writes its own partial sums); 0 = 2      */
+    int32_t blocks_per_cu;      /* persistent launch: resident blocks per compute unit;
+                                   0 = the occupancy limit                              */
+    int32_t autotune;           /* 1 = the first solve times the candidate launch shapes
+                                   (per-class or persistent, plane groups, blocks per
+                                   CU) on the caller's data, keeps the fastest, and
+                                   records it in tuning_cache; that solve synchronises
+                                   the stream.  A cached entry for the same plan
+                                   signature is used without timing.                    */
     const char* tuning_cache;   /* JSON file of tuned launch shapes, or NULL            */
 } fmmg_options;
 
@@ -109,12 +119,13 @@ typedef struct {
 typedef enum {
     FMMG_STAGE_P2M = 0,         /* leaf cell masses                                     */
     FMMG_STAGE_M2M = 1,         /* upward pass, all levels                              */
-    FMMG_STAGE_TOP = 2,         /* top level under the all-pairs rule (+ reduction)     */
+    FMMG_STAGE_TOP = 2,         /* top level under the all-pairs rule; its reduction    */
     FMMG_STAGE_MONO = 3,        /* leaf targets, leaf sources (class 3)                 */
     FMMG_STAGE_MP_REFINED = 4,  /* refined targets (classes 1 and 2)                    */
     FMMG_STAGE_MP_LEAF = 5,     /* leaf targets, refined sources (class 4)              */
-    FMMG_STAGE_DOWN = 6,        /* downward pass and leaf output                        */
-    FMMG_N_STAGES = 7
+    FMMG_STAGE_FUSED = 6,       /* the persistent launch of all same-level classes      */
+    FMMG_STAGE_DOWN = 7,        /* downward pass and leaf output                        */
+    FMMG_N_STAGES = 8
 } fmmg_stage;
 
 typedef struct {
@@ -122,6 +133,15 @@ typedef struct {
     int64_t launches[FMMG_N_STAGES]; /* kernel launches per stage and solve             */
     int64_t solves;             /* number of solves summed                              */
 } fmmg_timings;
+
+/* Launch shape in use (after tuning, if any). */
+typedef struct {
+    int32_t persistent;
+    int32_t plane_groups;
+    int32_t blocks_per_cu;
+    int32_t from_cache;         /* 1 if the shape came from the tuning cache           */
+    double tuned_ms;            /* best solve time measured by the tuner, or 0         */
+} fmmg_launch_shape;
 
 typedef struct {
     int64_t pairs[4];      /* ordered cell pairs per class: [0] refined<-leaf,
@@ -174,6 +194,9 @@ fmmg_status fmmg_check_density(fmmg_plan* plan, const double* rho, void* hip_str
  * caller must have synchronised the solves' stream.  FMMG_EINVAL if the plan
  * was created without timing. */
 fmmg_status fmmg_get_timings(fmmg_plan* plan, fmmg_timings* out);
+
+/* The launch shape the plan uses. */
+fmmg_status fmmg_get_launch_shape(const fmmg_plan* plan, fmmg_launch_shape* out);
 
 /* Pair counts and launch counters of the plan (host values; no device work). */
 fmmg_status fmmg_get_stats(const fmmg_plan* plan, fmmg_stats* stats);

@@ -27,9 +27,10 @@ _STATUS = {0: "FMMG_OK", -1: "FMMG_EINVAL", -2: "FMMG_ETREE", -3: "FMMG_ENOMEM",
            -5: "FMMG_EUNSUPPORTED"}
 
 EXPORTED = ["fmmg_default_options", "fmmg_plan_create", "fmmg_plan_n_leaves", "fmmg_leaf_order",
-            "fmmg_solve", "fmmg_check_density", "fmmg_get_timings", "fmmg_get_stats",
-            "fmmg_plan_destroy", "fmmg_last_error", "fmmg_count_pairs", "fmmg_version"]
-STAGES = ["p2m", "m2m", "top", "mono", "mp_refined", "mp_leaf", "down"]
+            "fmmg_solve", "fmmg_check_density", "fmmg_get_timings", "fmmg_get_launch_shape",
+            "fmmg_get_stats", "fmmg_plan_destroy", "fmmg_last_error", "fmmg_count_pairs",
+            "fmmg_version"]
+STAGES = ["p2m", "m2m", "top", "mono", "mp_refined", "mp_leaf", "fused", "down"]
 
 
 class FmmgError(RuntimeError):
@@ -46,11 +47,22 @@ class fmmg_tree_desc(C.Structure):
 class fmmg_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("top_mode", C.c_int), ("G", C.c_double),
                 ("angular_correction", C.c_int32), ("use_graph", C.c_int32),
-                ("persistent", C.c_int32), ("timing", C.c_int32), ("tuning_cache", C.c_char_p)]
+                ("persistent", C.c_int32), ("timing", C.c_int32), ("plane_groups", C.c_int32),
+                ("blocks_per_cu", C.c_int32), ("autotune", C.c_int32), ("tuning_cache", C.c_char_p)]
 
 
 class fmmg_timings(C.Structure):
-    _fields_ = [("ms", C.c_double * 7), ("launches", C.c_int64 * 7), ("solves", C.c_int64)]
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8), ("solves", C.c_int64)]
+
+
+class fmmg_launch_shape(C.Structure):
+    _fields_ = [("persistent", C.c_int32), ("plane_groups", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("from_cache", C.c_int32), ("tuned_ms", C.c_double)]
+
+    def as_dict(self):
+        return {"persistent": int(self.persistent), "plane_groups": int(self.plane_groups),
+                "blocks_per_cu": int(self.blocks_per_cu), "from_cache": int(self.from_cache),
+                "tuned_ms": float(self.tuned_ms)}
 
 
 class fmmg_stats(C.Structure):
@@ -88,6 +100,7 @@ def lib() -> C.CDLL:
         L.fmmg_check_density.argtypes = [vp, vp, vp]
         L.fmmg_get_stats.argtypes = [vp, C.POINTER(fmmg_stats)]
         L.fmmg_get_timings.argtypes = [vp, C.POINTER(fmmg_timings)]
+        L.fmmg_get_launch_shape.argtypes = [vp, C.POINTER(fmmg_launch_shape)]
         L.fmmg_plan_destroy.argtypes = [vp]
         L.fmmg_plan_destroy.restype = None
         L.fmmg_last_error.argtypes = []
@@ -97,7 +110,8 @@ def lib() -> C.CDLL:
         L.fmmg_version.argtypes = []
         L.fmmg_version.restype = C.c_int32
         for name in ("fmmg_plan_create", "fmmg_plan_n_leaves", "fmmg_leaf_order", "fmmg_solve",
-                     "fmmg_check_density", "fmmg_get_stats", "fmmg_count_pairs", "fmmg_get_timings"):
+                     "fmmg_check_density", "fmmg_get_stats", "fmmg_count_pairs", "fmmg_get_timings",
+                     "fmmg_get_launch_shape"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -212,6 +226,12 @@ def fmmg_get_timings(plan) -> dict:
             "launches": dict(zip(STAGES, list(t.launches)))}
 
 
+def fmmg_get_launch_shape(plan) -> dict:
+    sh = fmmg_launch_shape()
+    _check(lib().fmmg_get_launch_shape(plan, C.byref(sh)))
+    return sh.as_dict()
+
+
 def fmmg_plan_destroy(plan) -> None:
     if plan:
         lib().fmmg_plan_destroy(plan)
@@ -222,7 +242,9 @@ class Plan:
 
     def __init__(self, trees: Sequence, precision: str = "fp64", top_mode: str = "full",
                  G: float = 1.0, angular_correction: bool = True, use_graph: bool = False,
-                 persistent: bool = False, timing: bool = False, stream=None):
+                 persistent: bool = False, timing: bool = False, plane_groups: int = 0,
+                 blocks_per_cu: int = 0, autotune: bool = False, tuning_cache: str | None = None,
+                 stream=None):
         opt = fmmg_default_options()
         opt.precision = {"fp64": FMMG_FP64, "mixed": FMMG_MIXED}[precision]
         opt.top_mode = {"full": FMMG_TOP_FULL, "stencil": FMMG_TOP_STENCIL_ONLY}[top_mode]
@@ -231,6 +253,11 @@ class Plan:
         opt.use_graph = int(bool(use_graph))
         opt.persistent = int(bool(persistent))
         opt.timing = int(bool(timing))
+        opt.plane_groups = int(plane_groups)
+        opt.blocks_per_cu = int(blocks_per_cu)
+        opt.autotune = int(bool(autotune))
+        self._cache = tuning_cache.encode() if tuning_cache else None
+        opt.tuning_cache = self._cache
         self._h = fmmg_plan_create(trees, opt, stream)
         self.n_leaves = fmmg_plan_n_leaves(self._h)
 
@@ -251,6 +278,9 @@ class Plan:
 
     def timings(self) -> dict:
         return fmmg_get_timings(self._h)
+
+    def launch_shape(self) -> dict:
+        return fmmg_get_launch_shape(self._h)
 
     def leaf_order(self) -> np.ndarray:
         return fmmg_leaf_order(self._h)

@@ -1,12 +1,17 @@
 // fmmg_api.cpp -- the C-ABI declared in include/fmmg.h: plan creation (host
-// planning, device tables and workspaces), the solve's launch sequence, hipGraph
-// capture/replay, statistics and error reporting.
+// planning, device tables and workspaces), the solve's launch sequence in its
+// two shapes (one launch per class, or one persistent launch over all work
+// items), hipGraph capture/replay, the launch-shape tuner, statistics and
+// error reporting.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
 #include <array>
+#include <cstdio>
+#include <fstream>
 #include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
 #include <vector>
 
@@ -14,7 +19,6 @@
 #include "fmmg_internal.h"
 #include "launch.h"
 #include "planner.hpp"
-
 
 using namespace fmmg;
 
@@ -31,23 +35,27 @@ fmmg_status hip_fail(hipError_t e, const char* what) {
     return fail(FMMG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(call, what)                       \
-    do {                                          \
-        hipError_t e_ = (call);                   \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
+#define HIP_TRY(call, what)                                  \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, what);     \
     } while (0)
 
 std::mutex g_tab_mutex;
 bool g_tab_uploaded[64] = {false};
 
 template <typename T>
-fmmg_status dev_upload(T** dst, const std::vector<T>& src, hipStream_t st, const char* what) {
+fmmg_status dev_upload(T** dst, const std::vector<T>& src, size_t capacity, hipStream_t st,
+                       const char* what) {
     *dst = nullptr;
-    if (src.empty()) return FMMG_OK;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), src.size() * sizeof(T));
+    size_t n = capacity > src.size() ? capacity : src.size();
+    if (n == 0) return FMMG_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), n * sizeof(T));
     if (e != hipSuccess) return fail(FMMG_ENOMEM, std::string("hipMalloc ") + what + ": " + hipGetErrorString(e));
-    e = hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, what);
+    if (!src.empty()) {
+        e = hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, what);
+    }
     return FMMG_OK;
 }
 
@@ -77,26 +85,35 @@ constexpr int TOP_CHUNKS = 32;
 
 struct fmmg_plan {
     int device = -1;
+    int n_cu = 0;
+    int max_bpc = 0;
     fmmg_options opt;
     HostPlan hp;
     hipStream_t capture_stream = nullptr;
     SubDev* d_subs = nullptr;
     int32_t* d_leaf_sub = nullptr;
-    int32_t* d_mp_ref = nullptr;
-    int32_t* d_mono_leaf = nullptr;
-    int32_t* d_mp_leaf = nullptr;
     int32_t* d_ref_by_level = nullptr;
     int32_t* d_top_leaf = nullptr;
+    int32_t* d_top_ref_stencil = nullptr;
     int32_t* d_top_src = nullptr;
     TopItem* d_top_items = nullptr;
     TopReduce* d_top_reduce = nullptr;
+    Item* d_items_class = nullptr;
+    Item* d_items_lpt = nullptr;
+    size_t items_capacity = 0;
+    int* d_counter = nullptr;
     double* d_mass = nullptr;
     double* d_rec = nullptr;
+    double* d_Lp = nullptr;
     double* d_Lr = nullptr;
     double* d_Lf = nullptr;
+    double* d_Lf3 = nullptr;
     double* d_part = nullptr;
     unsigned long long* d_bad = nullptr;
     unsigned long long* h_bad = nullptr;
+    // launch shape
+    fmmg_launch_shape shape;
+    bool tuned = false;
     // graph cache
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -108,18 +125,25 @@ struct fmmg_plan {
     // stage timing (eager solves with options.timing)
     std::vector<std::array<hipEvent_t, FMMG_N_STAGES + 1>> events;
     size_t n_timed = 0;
-    int64_t stage_launches[FMMG_N_STAGES] = {0, 0, 0, 0, 0, 0, 0};
+    int64_t stage_launches[FMMG_N_STAGES] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
 
-void release(fmmg_plan* p) {
-    if (!p) return;
+void drop_graph(fmmg_plan* p) {
     if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
-    void* bufs[] = {p->d_subs, p->d_leaf_sub, p->d_mp_ref, p->d_mono_leaf, p->d_mp_leaf,
-                    p->d_ref_by_level, p->d_top_leaf, p->d_top_src, p->d_top_items, p->d_top_reduce,
-                    p->d_mass, p->d_rec, p->d_Lr, p->d_Lf, p->d_part, p->d_bad};
+    p->graph_exec = nullptr;
+    p->graph = nullptr;
+}
+
+void release(fmmg_plan* p) {
+    if (!p) return;
+    drop_graph(p);
+    void* bufs[] = {p->d_subs, p->d_leaf_sub, p->d_ref_by_level, p->d_top_leaf, p->d_top_ref_stencil,
+                    p->d_top_src, p->d_top_items, p->d_top_reduce, p->d_items_class, p->d_items_lpt,
+                    p->d_counter, p->d_mass, p->d_rec, p->d_Lp, p->d_Lr, p->d_Lf, p->d_Lf3, p->d_part,
+                    p->d_bad};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->h_bad) (void)hipHostFree(p->h_bad);
@@ -130,20 +154,50 @@ void release(fmmg_plan* p) {
     delete p;
 }
 
-Launch make_launch(const fmmg_plan* p, hipStream_t st) {
-    Launch a;
+Ctx make_ctx(const fmmg_plan* p, hipStream_t st) {
+    Ctx a;
     a.subs = p->d_subs;
     a.leaf_sub = p->d_leaf_sub;
     a.mass = p->d_mass;
     a.rec = p->d_rec;
+    a.Lp = p->d_Lp;
     a.Lr = p->d_Lr;
     a.Lf = p->d_Lf;
+    a.Lf3 = p->d_Lf3;
     a.part = p->d_part;
+    a.top_items = p->d_top_items;
+    a.top_src = p->d_top_src;
+    a.part_stride = int64_t(p->hp.ref_sub.size()) * NLOC * NCELL;
     a.G = p->opt.G;
     a.corr = p->opt.angular_correction ? 1 : 0;
     a.mixed = p->opt.precision == FMMG_MIXED ? 1 : 0;
+    a.ngroups = p->hp.ngroups;
     a.st = st;
     return a;
+}
+
+// Rebuilds and uploads the work items for a launch shape.
+fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, hipStream_t st) {
+    if (groups < 1 || groups > MAX_GROUPS) return fail(FMMG_EINVAL, "plane_groups must be 1 or 2");
+    if (bpc < 0) return fail(FMMG_EINVAL, "blocks_per_cu must be >= 0");
+    if (bpc == 0 || bpc > p->max_bpc) bpc = p->max_bpc;
+    if (groups != p->hp.ngroups) {
+        build_items(&p->hp, groups);
+        if (p->hp.items_class.size() > p->items_capacity) return fail(FMMG_EINVAL, "work-item capacity exceeded");
+        if (!p->hp.items_class.empty()) {
+            HIP_TRY(hipMemcpyAsync(p->d_items_class, p->hp.items_class.data(),
+                                   p->hp.items_class.size() * sizeof(Item), hipMemcpyHostToDevice, st), "item upload");
+            HIP_TRY(hipMemcpyAsync(p->d_items_lpt, p->hp.items_lpt.data(),
+                                   p->hp.items_lpt.size() * sizeof(Item), hipMemcpyHostToDevice, st), "item upload");
+        }
+        HIP_TRY(hipStreamSynchronize(st), "item upload");
+    }
+    if (p->shape.persistent != persistent || p->shape.plane_groups != groups || p->shape.blocks_per_cu != bpc)
+        drop_graph(p);
+    p->shape.persistent = persistent;
+    p->shape.plane_groups = groups;
+    p->shape.blocks_per_cu = bpc;
+    return FMMG_OK;
 }
 
 // The solve's launch sequence; returns the number of launches.  ev (may be
@@ -151,50 +205,193 @@ Launch make_launch(const fmmg_plan* p, hipStream_t st) {
 int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, hipStream_t st,
                       const hipEvent_t* ev) {
     const HostPlan& hp = p->hp;
-    Launch a = make_launch(p, st);
-    int64_t n = 0;
-    int64_t per[FMMG_N_STAGES] = {0, 0, 0, 0, 0, 0, 0};
-    auto mark = [&](int stage) { if (ev) (void)hipEventRecord(ev[stage], st); };
-    auto cnt = [&](int stage, int items) { if (items > 0) { ++n; ++per[stage]; } };
+    Ctx a = make_ctx(p, st);
+    int64_t per[FMMG_N_STAGES] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int stage = 0;
+    auto mark = [&](int s) {
+        stage = s;
+        if (ev) (void)hipEventRecord(ev[s], st);
+    };
+    auto cnt = [&](int items, int launches = 1) { if (items > 0) per[stage] += launches; };
     // step 1: leaf masses, then moments bottom-up
     mark(FMMG_STAGE_P2M);
     launch_p2m(a, rho, int(hp.leaf_sub.size()));
-    cnt(FMMG_STAGE_P2M, int(hp.leaf_sub.size()));
+    cnt(int(hp.leaf_sub.size()));
     mark(FMMG_STAGE_M2M);
     for (int l = hp.max_level - 1; l >= 0; --l) {
         int b = hp.level_ref_begin[size_t(l)], e = hp.level_ref_begin[size_t(l) + 1];
         launch_m2m(a, p->d_ref_by_level + b, e - b);
-        cnt(FMMG_STAGE_M2M, e - b);
+        cnt(e - b);
     }
     // step 2: same-level interactions
+    const int* cb = hp.class_begin;
+    const int n_top_red = int(hp.top_reduce.size());
     mark(FMMG_STAGE_TOP);
-    if (!hp.top_items.empty()) {
-        launch_top(a, p->d_top_items, int(hp.top_items.size()), p->d_top_src, p->d_top_reduce,
-                   int(hp.top_reduce.size()));
-        n += 2;
-        per[FMMG_STAGE_TOP] += 2;
+    if (!p->shape.persistent) {
+        launch_class(a, IT_TOP, p->d_items_class + cb[IT_TOP], cb[IT_TOP + 1] - cb[IT_TOP]);
+        cnt(cb[IT_TOP + 1] - cb[IT_TOP]);
+        launch_top_reduce(a, p->d_top_reduce, n_top_red);
+        cnt(n_top_red, 2);
     }
     mark(FMMG_STAGE_MONO);
-    launch_mono(a, p->d_mono_leaf, int(hp.mono_leaf.size()));
-    cnt(FMMG_STAGE_MONO, int(hp.mono_leaf.size()));
+    if (!p->shape.persistent) {
+        launch_class(a, IT_MONO, p->d_items_class + cb[IT_MONO], cb[IT_MONO + 1] - cb[IT_MONO]);
+        cnt(cb[IT_MONO + 1] - cb[IT_MONO]);
+    }
     mark(FMMG_STAGE_MP_REFINED);
-    launch_mp(a, p->d_mp_ref, int(hp.mp_ref.size()), false);
-    cnt(FMMG_STAGE_MP_REFINED, int(hp.mp_ref.size()));
+    if (!p->shape.persistent) {
+        launch_class(a, IT_MP_REF, p->d_items_class + cb[IT_MP_REF], cb[IT_MP_REF + 1] - cb[IT_MP_REF]);
+        cnt(cb[IT_MP_REF + 1] - cb[IT_MP_REF]);
+    }
     mark(FMMG_STAGE_MP_LEAF);
-    launch_mp(a, p->d_mp_leaf, int(hp.mp_leaf.size()), true);
-    cnt(FMMG_STAGE_MP_LEAF, int(hp.mp_leaf.size()));
-    // step 3: leaves without parents, then top-down re-expansion
+    if (!p->shape.persistent) {
+        launch_class(a, IT_MP_LEAF, p->d_items_class + cb[IT_MP_LEAF], cb[IT_MP_LEAF + 1] - cb[IT_MP_LEAF]);
+        cnt(cb[IT_MP_LEAF + 1] - cb[IT_MP_LEAF]);
+    }
+    mark(FMMG_STAGE_FUSED);
+    if (p->shape.persistent) {
+        const int n = int(hp.items_lpt.size());
+        const int grid = p->shape.blocks_per_cu * p->n_cu;
+        launch_persist(a, p->d_items_lpt, n, p->d_counter, grid < n ? grid : n);
+        cnt(n, 2);
+        launch_top_reduce(a, p->d_top_reduce, n_top_red);
+        cnt(n_top_red, 2);
+    }
+    // step 3: totals of stencil-mode top refined cells, leaves without
+    // parents, then top-down re-expansion
     mark(FMMG_STAGE_DOWN);
+    launch_sum_parts(a, p->d_top_ref_stencil, int(hp.top_ref_stencil.size()));
+    cnt(int(hp.top_ref_stencil.size()));
     launch_leaf_out(a, p->d_top_leaf, int(hp.top_leaf.size()), phi, g);
-    cnt(FMMG_STAGE_DOWN, int(hp.top_leaf.size()));
+    cnt(int(hp.top_leaf.size()));
     for (int l = 0; l < hp.max_level; ++l) {
         int b = hp.level_ref_begin[size_t(l)], e = hp.level_ref_begin[size_t(l) + 1];
         launch_l2l(a, p->d_ref_by_level + b, e - b, phi, g);
-        cnt(FMMG_STAGE_DOWN, e - b);
+        cnt(e - b);
     }
-    mark(FMMG_N_STAGES);
-    for (int s = 0; s < FMMG_N_STAGES; ++s) p->stage_launches[s] = per[s];
+    if (ev) (void)hipEventRecord(ev[FMMG_N_STAGES], st);
+    int64_t n = 0;
+    for (int s = 0; s < FMMG_N_STAGES; ++s) {
+        p->stage_launches[s] = per[s];
+        n += per[s];
+    }
     return n;
+}
+
+// ---------------------------------------------------------------------------
+// launch-shape tuner
+// ---------------------------------------------------------------------------
+std::string signature(const fmmg_plan* p) {
+    std::ostringstream o;
+    const HostPlan& hp = p->hp;
+    o << "fmmg1 trees=" << hp.n_trees << " sub=" << hp.subs.size() << " ref=" << hp.ref_sub.size()
+      << " leaf=" << hp.leaf_sub.size() << " lev=" << hp.max_level << " k3=" << hp.n_slot3
+      << " top=" << (p->opt.top_mode == FMMG_TOP_FULL ? "full" : "stencil")
+      << " prec=" << (p->opt.precision == FMMG_MIXED ? "mixed" : "fp64") << " cu=" << p->n_cu;
+    return o.str();
+}
+
+// Cache file: a JSON object, one entry per line:
+//   "signature": {"persistent": P, "plane_groups": G, "blocks_per_cu": B, "ms": T},
+bool cache_lookup(const char* path, const std::string& sig, int* pers, int* groups, int* bpc) {
+    if (!path) return false;
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line, key = "\"" + sig + "\":";
+    while (std::getline(f, line)) {
+        size_t at = line.find(key);
+        if (at == std::string::npos) continue;
+        int a = -1, b = -1, c = -1;
+        const char* s = line.c_str() + at + key.size();
+        if (std::sscanf(s, " {\"persistent\": %d, \"plane_groups\": %d, \"blocks_per_cu\": %d", &a, &b, &c) == 3 &&
+            (a == 0 || a == 1) && b >= 1 && b <= MAX_GROUPS && c >= 0) {
+            *pers = a;
+            *groups = b;
+            *bpc = c;
+            return true;
+        }
+    }
+    return false;
+}
+
+void cache_store(const char* path, const std::string& sig, int pers, int groups, int bpc, double ms) {
+    if (!path) return;
+    std::vector<std::string> keep;
+    {
+        std::ifstream f(path);
+        std::string line;
+        while (std::getline(f, line)) {
+            if (line.find("\": {\"persistent\"") == std::string::npos) continue;
+            if (line.find("\"" + sig + "\":") != std::string::npos) continue;
+            while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
+            keep.push_back(line);
+        }
+    }
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "  \"%s\": {\"persistent\": %d, \"plane_groups\": %d, \"blocks_per_cu\": %d, \"ms\": %.6f}",
+                  sig.c_str(), pers, groups, bpc, ms);
+    keep.push_back(buf);
+    std::string tmp = std::string(path) + ".tmp";
+    {
+        std::ofstream o(tmp);
+        if (!o) return;
+        o << "{\n";
+        for (size_t i = 0; i < keep.size(); ++i) o << keep[i] << (i + 1 < keep.size() ? ",\n" : "\n");
+        o << "}\n";
+    }
+    std::rename(tmp.c_str(), path);
+}
+
+fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStream_t st) {
+    int pers = 0, groups = 0, bpc = 0;
+    const std::string sig = signature(p);
+    if (cache_lookup(p->opt.tuning_cache, sig, &pers, &groups, &bpc)) {
+        fmmg_status s = apply_shape(p, pers, groups, bpc, st);
+        if (s != FMMG_OK) return s;
+        p->shape.from_cache = 1;
+        p->tuned = true;
+        return FMMG_OK;
+    }
+    struct Cand { int pers, groups, bpc; };
+    std::vector<Cand> cands;
+    for (int gr = 1; gr <= MAX_GROUPS; ++gr) {
+        cands.push_back({0, gr, 0});
+        for (int b = 1; b <= p->max_bpc; ++b) cands.push_back({1, gr, b});
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(FMMG_EHIP, "hipEventCreate"); }
+    double best = 1e300;
+    Cand bc = cands[0];
+    fmmg_status status = FMMG_OK;
+    for (const Cand& c : cands) {
+        status = apply_shape(p, c.pers, c.groups, c.bpc, st);
+        if (status != FMMG_OK) break;
+        enqueue_solve(p, rho, phi, g, st, nullptr);  // warm
+        double t = 1e300;
+        for (int r = 0; r < 3; ++r) {
+            (void)hipEventRecord(e0, st);
+            enqueue_solve(p, rho, phi, g, st, nullptr);
+            (void)hipEventRecord(e1, st);
+            hipError_t e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { status = hip_fail(e, "tuning run"); break; }
+            if (ms < t) t = ms;
+        }
+        if (status != FMMG_OK) break;
+        if (t < best) { best = t; bc = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != FMMG_OK) return status;
+    status = apply_shape(p, bc.pers, bc.groups, bc.bpc, st);
+    if (status != FMMG_OK) return status;
+    p->shape.from_cache = 0;
+    p->shape.tuned_ms = best;
+    p->tuned = true;
+    cache_store(p->opt.tuning_cache, sig, bc.pers, bc.groups, p->shape.blocks_per_cu, best);
+    return FMMG_OK;
 }
 
 }  // namespace
@@ -215,6 +412,9 @@ void fmmg_default_options(fmmg_options* opt) {
     opt->use_graph = 0;
     opt->persistent = 0;
     opt->timing = 0;
+    opt->plane_groups = 0;
+    opt->blocks_per_cu = 0;
+    opt->autotune = 0;
     opt->tuning_cache = nullptr;
 }
 
@@ -255,18 +455,15 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         p = new fmmg_plan();
         if (opt) p->opt = *opt;
         else fmmg_default_options(&p->opt);
-        if (p->opt.precision != FMMG_FP64 && p->opt.precision != FMMG_MIXED) {
-            release(p);
-            return fail(FMMG_EINVAL, "bad precision");
-        }
-        if (p->opt.top_mode != FMMG_TOP_FULL && p->opt.top_mode != FMMG_TOP_STENCIL_ONLY) {
-            release(p);
-            return fail(FMMG_EINVAL, "bad top_mode");
-        }
-        if (p->opt.timing && p->opt.use_graph) {
-            release(p);
-            return fail(FMMG_EINVAL, "timing needs eager launches (use_graph = 0)");
-        }
+        const fmmg_options& o = p->opt;
+        std::string bad;
+        if (o.precision != FMMG_FP64 && o.precision != FMMG_MIXED) bad = "bad precision";
+        else if (o.top_mode != FMMG_TOP_FULL && o.top_mode != FMMG_TOP_STENCIL_ONLY) bad = "bad top_mode";
+        else if (o.timing && o.use_graph) bad = "timing needs eager launches (use_graph = 0)";
+        else if (o.timing && o.autotune) bad = "timing and autotune cannot be combined";
+        else if (o.plane_groups < 0 || o.plane_groups > MAX_GROUPS) bad = "plane_groups must be 0, 1 or 2";
+        else if (o.blocks_per_cu < 0) bad = "blocks_per_cu must be >= 0";
+        if (!bad.empty()) { release(p); return fail(FMMG_EINVAL, bad); }
         hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
         hipError_t e = hipGetDevice(&p->device);
         if (e != hipSuccess) { release(p); return fail(FMMG_EUNSUPPORTED, std::string("no HIP device: ") + hipGetErrorString(e)); }
@@ -277,32 +474,42 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
             release(p);
             return fail(FMMG_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
         }
+        p->n_cu = prop.multiProcessorCount;
+        p->max_bpc = persist_blocks_per_cu(o.precision == FMMG_MIXED);
+        if (p->max_bpc < 1) p->max_bpc = 1;
         std::vector<TreeIn> tv = to_trees(trees, n_trees);
         std::string err;
-        int rc = build_host_plan(tv.data(), n_trees, p->opt.top_mode == FMMG_TOP_FULL, TOP_CHUNKS, &p->hp, &err);
+        int rc = build_host_plan(tv.data(), n_trees, o.top_mode == FMMG_TOP_FULL, TOP_CHUNKS, &p->hp, &err);
         if (rc) { release(p); return fail(rc == -2 ? FMMG_ETREE : FMMG_EINVAL, err); }
-        const HostPlan& hp = p->hp;
+        HostPlan& hp = p->hp;
+        // item capacity: the largest list over the plane-group choices
+        build_items(&hp, MAX_GROUPS);
+        p->items_capacity = hp.items_class.size();
         fmmg_status s;
-#define UP(dst, src, what) if ((s = dev_upload(&(dst), (src), st, what)) != FMMG_OK) { release(p); return s; }
-        UP(p->d_subs, hp.subs, "sub-grid table");
-        UP(p->d_leaf_sub, hp.leaf_sub, "leaf list");
-        UP(p->d_mp_ref, hp.mp_ref, "refined target list");
-        UP(p->d_mono_leaf, hp.mono_leaf, "leaf target list");
-        UP(p->d_mp_leaf, hp.mp_leaf, "leaf multipole target list");
-        UP(p->d_ref_by_level, hp.ref_by_level, "level lists");
-        UP(p->d_top_leaf, hp.top_leaf, "top leaf list");
-        UP(p->d_top_src, hp.top_src, "top source list");
-        UP(p->d_top_items, hp.top_items, "top items");
-        UP(p->d_top_reduce, hp.top_reduce, "top reductions");
+#define UP(dst, src, cap, what) if ((s = dev_upload(&(dst), (src), (cap), st, what)) != FMMG_OK) { release(p); return s; }
+        UP(p->d_subs, hp.subs, 0, "sub-grid table");
+        UP(p->d_leaf_sub, hp.leaf_sub, 0, "leaf list");
+        UP(p->d_ref_by_level, hp.ref_by_level, 0, "level lists");
+        UP(p->d_top_leaf, hp.top_leaf, 0, "top leaf list");
+        UP(p->d_top_ref_stencil, hp.top_ref_stencil, 0, "top refined list");
+        UP(p->d_top_src, hp.top_src, 0, "top source list");
+        UP(p->d_top_items, hp.top_items, 0, "top items");
+        UP(p->d_top_reduce, hp.top_reduce, 0, "top reductions");
+        UP(p->d_items_class, std::vector<Item>(), p->items_capacity, "work items");
+        UP(p->d_items_lpt, std::vector<Item>(), p->items_capacity, "work items");
 #undef UP
         size_t nl = hp.leaf_sub.size(), nr = hp.ref_sub.size();
 #define AL(dst, n, what) if ((s = dev_alloc(&(dst), (n), what)) != FMMG_OK) { release(p); return s; }
         AL(p->d_mass, nl * NCELL, "leaf masses");
         AL(p->d_rec, nr * NREC * NCELL, "multipole records");
+        AL(p->d_Lp, size_t(MAX_GROUPS) * nr * NLOC * NCELL, "refined own terms");
         AL(p->d_Lr, nr * NLOC * NCELL, "refined expansions");
         AL(p->d_Lf, nl * NLEAF * NCELL, "leaf terms");
+        AL(p->d_Lf3, size_t(hp.n_slot3) * NLEAF * NCELL, "leaf terms from refined sources");
         AL(p->d_part, size_t(hp.n_top_parts) * NLOC * NCELL, "top partial sums");
 #undef AL
+        e = hipMalloc(reinterpret_cast<void**>(&p->d_counter), sizeof(int));
+        if (e != hipSuccess) { release(p); return fail(FMMG_ENOMEM, "hipMalloc counter"); }
         e = hipMalloc(reinterpret_cast<void**>(&p->d_bad), sizeof(unsigned long long));
         if (e != hipSuccess) { release(p); return fail(FMMG_ENOMEM, "hipMalloc flag"); }
         e = hipHostMalloc(reinterpret_cast<void**>(&p->h_bad), sizeof(unsigned long long), hipHostMallocDefault);
@@ -319,6 +526,10 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
                 g_tab_uploaded[p->device] = true;
             }
         }
+        p->hp.ngroups = 0;  // force the first item upload
+        memset(&p->shape, 0, sizeof(p->shape));
+        s = apply_shape(p, o.persistent ? 1 : 0, o.plane_groups ? o.plane_groups : MAX_GROUPS, o.blocks_per_cu, st);
+        if (s != FMMG_OK) { release(p); return s; }
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) { release(p); return hip_fail(e, "plan upload"); }
         *out = p;
@@ -344,6 +555,12 @@ fmmg_status fmmg_leaf_order(const fmmg_plan* p, int32_t* idx) {
     return FMMG_OK;
 }
 
+fmmg_status fmmg_get_launch_shape(const fmmg_plan* p, fmmg_launch_shape* out) {
+    if (!p || !out) return fail(FMMG_EINVAL, "null argument");
+    *out = p->shape;
+    return FMMG_OK;
+}
+
 fmmg_status fmmg_solve(fmmg_plan* p, const double* rho, double* phi, double* g, void* hip_stream) {
     if (!p) return fail(FMMG_EINVAL, "fmmg_solve: plan is NULL");
     if (!p->hp.leaf_sub.empty() && (!rho || !phi || !g)) return fail(FMMG_EINVAL, "fmmg_solve: null buffer");
@@ -352,17 +569,23 @@ fmmg_status fmmg_solve(fmmg_plan* p, const double* rho, double* phi, double* g, 
     if (dev != p->device) return fail(FMMG_EINVAL, "fmmg_solve: plan belongs to another device");
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     try {
+        if (p->opt.autotune && !p->tuned) {
+            fmmg_status s = tune(p, rho, phi, g, st);
+            if (s != FMMG_OK) return s;
+        }
         if (!p->opt.use_graph) {
             const hipEvent_t* ev = nullptr;
             if (p->opt.timing) {
                 if (p->n_timed == p->events.size()) {
-                    if (p->events.size() >= 100000) return fail(FMMG_EINVAL, "fmmg_solve: call fmmg_get_timings at least every 100000 solves");
+                    if (p->events.size() >= 100000)
+                        return fail(FMMG_EINVAL, "fmmg_solve: call fmmg_get_timings at least every 100000 solves");
                     std::array<hipEvent_t, FMMG_N_STAGES + 1> set;
                     set.fill(nullptr);
                     for (auto& e : set) {
                         hipError_t ee = hipEventCreate(&e);
                         if (ee != hipSuccess) {
-                            for (auto& d : set) if (d) (void)hipEventDestroy(d);
+                            for (auto& d : set)
+                                if (d) (void)hipEventDestroy(d);
                             return hip_fail(ee, "hipEventCreate");
                         }
                     }
@@ -374,8 +597,7 @@ fmmg_status fmmg_solve(fmmg_plan* p, const double* rho, double* phi, double* g, 
             HIP_TRY(hipGetLastError(), "kernel launch");
         } else {
             if (!p->graph_exec || p->g_rho != rho || p->g_phi != phi || p->g_g != g) {
-                if (p->graph_exec) { (void)hipGraphExecDestroy(p->graph_exec); p->graph_exec = nullptr; }
-                if (p->graph) { (void)hipGraphDestroy(p->graph); p->graph = nullptr; }
+                drop_graph(p);
                 if (!p->capture_stream)
                     HIP_TRY(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
                 HIP_TRY(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");

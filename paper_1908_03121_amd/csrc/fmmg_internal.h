@@ -9,11 +9,15 @@
 //                                 centre (3), trace-free quadrupole (5:
 //                                 xx yy xy xz yz), trace-free octupole
 //                                 (7: xxx xxy xxz xyy xyz yyy yyz)
-//   Lr   [n_ref][19][512]         refined cells' Taylor coefficients: L0, L1
-//                                 (3), trace-free L2 (5), trace-free L3 (7) and
-//                                 the correction sum S (3); own (same-level)
-//                                 after step 2, total after step 3
+//   Lp   [groups][n_ref][19][512] refined cells' own (same-level) Taylor
+//                                 coefficients, one partial per group of
+//                                 source planes: L0, L1 (3), trace-free L2 (5),
+//                                 trace-free L3 (7), correction dg (3)
+//   Lr   [n_ref][19][512]         refined cells' total coefficients (step 3)
 //   Lf   [n_leaf][4][512]         leaf cells' own potential and acceleration
+//                                 from leaf sources (or the top level)
+//   Lf3  [n_slot3][4][512]        the same from refined sources, for leaves
+//                                 that have refined neighbours
 // Trace-free storage is exact here: every contraction of the method is with a
 // derivative tensor of 1/r, which is harmonic (trace-free), and trace parts
 // of children's moments contribute only trace parts to the parent's.
@@ -53,6 +57,17 @@ struct SubDev {
     int32_t child[8];  // refined: child sub-grid ids, slot ex*4 + ey*2 + ez
     int32_t coord[3];
     int32_t flags;     // bit0: has a leaf neighbour; bit1: has a refined neighbour
+    int32_t slot3;     // leaf with refined neighbours: its Lf3 slot, else -1
+};
+
+// Same-level work items.  A block of 256 threads (4 waves) runs one item.
+enum { IT_MP_REF = 0, IT_MP_LEAF = 1, IT_MONO = 2, IT_TOP = 3, IT_KINDS = 4 };
+constexpr int MAX_GROUPS = 2;   // source-plane groups of a refined-target item
+struct Item {
+    int32_t kind;
+    int32_t sub;   // target sub-grid (IT_TOP: index into the top items)
+    int32_t a;     // IT_MP_*: target plane zt
+    int32_t b;     // IT_MP_REF: plane group
 };
 
 // Canonical stencil tables (parity (0,0,0); other parities are mirror images:
@@ -74,9 +89,9 @@ struct StencilTables {
     float mono_tabf[MONO_TAB];
 };
 
-// Top-level (all pairs) work item: 64 target cells (plane zt of sub-grid
-// target) against the source cells [src_begin, src_end) of the tree's
-// top-level source list; partial sums go to slot part.
+// Top-level (all pairs) tile: 64 target cells (plane zt of sub-grid target)
+// against the source cells [src_begin, src_end) of the tree's top-level
+// source list; partial sums go to slot part.
 struct TopItem {
     int32_t target;
     int32_t zt;

@@ -276,34 +276,36 @@ __global__ __launch_bounds__(512) void k_m2m(const SubDev* __restrict__ subs,
 }
 
 // ---------------------------------------------------------------------------
-// step 2a: multipole stencil kernel (refined targets: classes 1+2; leaf
-// targets with refined neighbours: class 4)
+// step 2: same-level interactions as work items of 256 threads (4 waves)
 // ---------------------------------------------------------------------------
-// block = 256 threads = 4 waves; work item = (target sub-grid, target plane zt);
-// all 4 waves hold the same 64 targets and split each plane's entry list.
-// Refined targets: every existing source over the far entries, leaf sources
-// also over the near entries.  Leaf targets: refined sources over all entries.
+// LDS of one item block: the largest of the multipole plane window (16
+// records x 324 cells + leaf flags), the monopole mass box (18^3) and the
+// 4-wave reduction buffer (doubles).
+template <typename P>
+struct Smem {
+    static constexpr int PLANE = NREC * PCELLS * int(sizeof(P)) + PCELLS;
+    static constexpr int BOX = PW * PW * PW * int(sizeof(P));
+    static constexpr int RED = 4 * NLOC * 64 * 8;
+    static constexpr int A = PLANE > BOX ? PLANE : BOX;
+    static constexpr int BYTES = ((A > RED ? A : RED) + 15) & ~15;
+};
+
+// Multipole item: 64 target cells (plane zt of sub-grid sid) against the
+// source planes of one group of canonical dz.  All 4 waves hold the same 64
+// targets and split each plane's entry list.  Refined targets: every existing
+// source over the far entries, leaf sources also over the near entries
+// (classes 1 + 2).  Leaf targets: refined sources over all entries (class 4).
 template <bool LEAF_T, bool MIXED>
-__global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
-                                            const int32_t* __restrict__ list,
-                                            const double* __restrict__ mass,
-                                            const double* __restrict__ rec,
-                                            double* __restrict__ Lr, double* __restrict__ Lf,
-                                            double G, int corr) {
+__device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int group,
+                                        unsigned char* smem) {
     using P = typename std::conditional<MIXED, float, double>::type;
-    constexpr int PLANE_BYTES = NREC * PCELLS * int(sizeof(P));
-    constexpr int RED_BYTES = 4 * NLOC * 64 * 8;
-    constexpr int SH_BYTES = PLANE_BYTES > RED_BYTES ? PLANE_BYTES : RED_BYTES;
-    __shared__ __attribute__((aligned(16))) unsigned char smem[SH_BYTES];
-    __shared__ unsigned char leafflag[PCELLS];
     P* sh = reinterpret_cast<P*>(smem);
+    unsigned char* leafflag = smem + NREC * PCELLS * sizeof(P);
 
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index: uniform
     const int x = lane & 7, y = lane >> 3;
-    const int sid = list[blockIdx.x >> 3];
-    const int zt = blockIdx.x & 7;
-    const SubDev& T = subs[sid];
+    const SubDev& T = cx.subs[sid];
     const double h = T.h;
     const int tidx = T.idx;
     const int q = zt * 64 + lane;
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
     double mA, dAx = 0, dAy = 0, dAz = 0;
     P oa[7] = {0, 0, 0, 0, 0, 0, 0};
     if (!LEAF_T) {
-        const double* r = rec + size_t(tidx) * NREC * NCELL;
+        const double* r = cx.rec + size_t(tidx) * NREC * NCELL;
         mA = r[R_M * NCELL + q];
         dAx = r[R_DX * NCELL + q];
         dAy = r[R_DY * NCELL + q];
@@ -321,11 +323,13 @@ __global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
 #pragma unroll
         for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q]);
     } else {
-        mA = mass[size_t(tidx) * NCELL + q];
+        mA = cx.mass[size_t(tidx) * NCELL + q];
     }
     const P inv_ma = mA > 0 ? P(1.0 / mA) : P(0);
-    const bool use_corr = corr != 0;
+    const bool use_corr = cx.corr != 0;
     const bool do_near = LEAF_T ? true : ((T.flags & 1) != 0);
+    const int ng = LEAF_T ? 1 : cx.ngroups;
+    const int i0 = group * NDZ / ng, i1 = (group + 1) * NDZ / ng;
 
     Acc<double> acc;
     acc.zero();
@@ -335,11 +339,9 @@ __global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
     const int lbase = (y + REACH) * PW + (x + REACH);
     const int syw = sy * PW;
 
-    for (int zs = zt - REACH; zs <= zt + REACH; ++zs) {
-        const int dz = zs - zt;
-        const int dzc = sz * dz;
-        if (dzc < DZ0 || dzc >= DZ0 + NDZ) continue;
-        const int g = dzc - DZ0;
+    for (int gi = i0; gi < i1; ++gi) {
+        const int dz = sz * (DZ0 + gi);
+        const int zs = zt + dz;
         __syncthreads();
         // stage the 18x18 source window of plane zs
         {
@@ -354,11 +356,11 @@ __global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
                 const int cq = (lz * NS + (ly - NS * oy)) * NS + (lx - NS * ox);
                 const int kind = code < 0 ? -1 : (code & 1), nidx = code >> 1;
                 if (kind == 1) {
-                    const double* r = rec + size_t(nidx) * NREC * NCELL + cq;
+                    const double* r = cx.rec + size_t(nidx) * NREC * NCELL + cq;
 #pragma unroll
                     for (int k = 0; k < NREC; ++k) sh[k * PCELLS + c] = P(r[k * NCELL]);
                 } else {
-                    P mm = (kind == 0 && !LEAF_T) ? P(mass[size_t(nidx) * NCELL + cq]) : P(0);
+                    P mm = (kind == 0 && !LEAF_T) ? P(cx.mass[size_t(nidx) * NCELL + cq]) : P(0);
                     sh[c] = mm;
 #pragma unroll
                     for (int k = 1; k < NREC; ++k) sh[k * PCELLS + c] = P(0);
@@ -368,8 +370,11 @@ __global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
         }
         __syncthreads();
         const P zoff = P(-h * dz);
-        Acc<P> part;
-        part.zero();
+        // mixed form: FP32 partial sums per source plane, flushed into the FP64
+        // accumulators after the plane; FP64 form: accumulate directly
+        Acc<P> part_store;
+        Acc<P>& part = MIXED ? part_store : *reinterpret_cast<Acc<P>*>(&acc);
+        if (MIXED) part.zero();
         auto one = [&](int e) {
             const int ent = c_tab.mp_entry[e];
             const int dxc = (ent & 255) - 8, dyc = ((ent >> 8) & 255) - 8;
@@ -382,10 +387,10 @@ __global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
             const P Z = zoff + (P(dAz) - src[R_DZ]);
             pair_terms<!LEAF_T, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], inv_ma, oa, use_corr, part);
         };
-        const int fb = c_tab.mp_far_begin[g], fe = fb + c_tab.mp_far_count[g];
+        const int fb = c_tab.mp_far_begin[gi], fe = fb + c_tab.mp_far_count[gi];
         for (int e = fb + w; e < fe; e += 4) one(e);
         if (do_near) {
-            const int nbg = c_tab.mp_near_begin[g], ne = nbg + c_tab.mp_near_count[g];
+            const int nbg = c_tab.mp_near_begin[gi], ne = nbg + c_tab.mp_near_count[gi];
             for (int e = nbg + w; e < ne; e += 4) {
                 if (!LEAF_T) {
                     const int ent = c_tab.mp_entry[e];
@@ -396,7 +401,7 @@ __global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
                 one(e);
             }
         }
-        acc.add(part, !LEAF_T);
+        if (MIXED) acc.add(part, !LEAF_T);
     }
 
     // combine the 4 waves' partial sums in a fixed order
@@ -413,39 +418,36 @@ __global__ __launch_bounds__(256) void k_mp(const SubDev* __restrict__ subs,
         for (int k = 0; k < NLOC; ++k) red[(w * NLOC + k) * 64 + lane] = v[k];
     }
     __syncthreads();
+    const double G = cx.G;
     const double gs = use_corr ? -G / 6.0 : 0.0;
+    auto sum4 = [&](int k, int l) {
+        return red[(0 * NLOC + k) * 64 + l] + red[(1 * NLOC + k) * 64 + l] +
+               red[(2 * NLOC + k) * 64 + l] + red[(3 * NLOC + k) * 64 + l];
+    };
     if (!LEAF_T) {
-        double* out = Lr + size_t(tidx) * NLOC * NCELL + zt * 64;
+        double* out = cx.Lp + size_t(group) * size_t(cx.part_stride) + size_t(tidx) * NLOC * NCELL + zt * 64;
         for (int i = t; i < NLOC * 64; i += 256) {
             const int k = i >> 6, l = i & 63;
-            double s = red[(0 * NLOC + k) * 64 + l] + red[(1 * NLOC + k) * 64 + l] +
-                       red[(2 * NLOC + k) * 64 + l] + red[(3 * NLOC + k) * 64 + l];
-            out[k * NCELL + l] = (k >= T_S ? gs : -G) * s;
+            out[k * NCELL + l] = (k >= T_S ? gs : -G) * sum4(k, l);
         }
     } else {
-        // leaf own terms: phi += -G L0;  g += G L1 + (-G/6) S
-        double* out = Lf + size_t(tidx) * NLEAF * NCELL + zt * 64;
+        // own terms from refined sources: phi = -G L0;  g = G L1 + (-G/6) S
+        double* out = cx.Lf3 + size_t(T.slot3) * NLEAF * NCELL + zt * 64;
         if (t < 64) {
-            auto sum = [&](int k) {
-                return red[(0 * NLOC + k) * 64 + t] + red[(1 * NLOC + k) * 64 + t] +
-                       red[(2 * NLOC + k) * 64 + t] + red[(3 * NLOC + k) * 64 + t];
-            };
-            out[0 * NCELL + t] += -G * sum(0);
-            for (int a = 0; a < 3; ++a) out[(1 + a) * NCELL + t] += G * sum(T_L1 + a) + gs * sum(T_S + a);
+            out[0 * NCELL + t] = -G * sum4(0, t);
+            for (int a = 0; a < 3; ++a) out[(1 + a) * NCELL + t] = G * sum4(T_L1 + a, t) + gs * sum4(T_S + a, t);
         }
     }
 }
 
-// ---------------------------------------------------------------------------
-// step 2b: monopole stencil kernel (leaf targets, leaf sources: class 3)
-// ---------------------------------------------------------------------------
-// Cell pairs on the lattice: R = -h d, so phi = -(G/h) sum m / |d| and
-// g = (G/h^2) sum m d / |d|^3, with the kernel values of each offset taken
-// from tables.  block = 128 threads = 2 waves (one per z parity of the
-// targets); a lane owns the 4 same-parity targets of its (x, y) column,
-// z = pz + 2k.  For one stencil column (dx, dy) the lane loads its source
-// column of masses once and reuses every value for all targets it reaches;
-// the table values are shared by the 4 targets and the 64 lanes.
+// Monopole item: leaf targets of one sub-grid against leaf sources (class 3).
+// Cell pairs lie on the lattice: R = -h d, so phi = -(G/h) sum m/|d| and
+// g = (G/h^2) sum m d/|d|^3 with per-offset kernel values from tables.  The
+// 18^3 box of leaf masses around the sub-grid sits in LDS.  Wave w takes the
+// targets of z parity pz = w & 1 (a lane owns the 4 targets z = pz + 2k of
+// its (x, y) column) and every second stencil column (w >> 1); the two
+// column halves are added in a fixed order.
+
 template <typename P>
 __device__ __forceinline__ P mono_tab(int i);
 template <>
@@ -455,13 +457,13 @@ __device__ __forceinline__ float mono_tab<float>(int i) { return c_tab.mono_tabf
 
 template <int PZ, int LO, int N, typename P>
 __device__ __forceinline__ void mono_class(const P* __restrict__ box, int cbeg, int cend, int tab0,
-                                           int lbase, int sx, int syw, int sy,
+                                           int cstart, int cstep, int lbase, int sx, int syw, int sy,
                                            double (&phi)[4], double (&gx)[4], double (&gy)[4],
                                            double (&gz)[4]) {
     constexpr int SZ = 1 - 2 * PZ;
     constexpr int ZMIN = SZ > 0 ? PZ + LO : PZ - (LO + N - 1);  // lowest source z
     constexpr int NSRC = N + 6;
-    for (int c = cbeg; c < cend; ++c) {
+    for (int c = cbeg + cstart; c < cend; c += cstep) {
         const int pk = c_tab.mono_col[c];
         const int dx = (pk & 255) - 8, dy = ((pk >> 8) & 255) - 8;
         const P* col = box + lbase + __mul24(sx, dx) + __mul24(syw, dy)
@@ -496,27 +498,26 @@ __device__ __forceinline__ void mono_class(const P* __restrict__ box, int cbeg, 
 }
 
 template <int PZ, typename P>
-__device__ __forceinline__ void mono_all(const P* box, int lbase, int sx, int syw, int sy,
-                                         double (&phi)[4], double (&gx)[4], double (&gy)[4],
-                                         double (&gz)[4]) {
+__device__ __forceinline__ void mono_all(const P* box, int cstart, int cstep, int lbase, int sx,
+                                         int syw, int sy, double (&phi)[4], double (&gx)[4],
+                                         double (&gy)[4], double (&gz)[4]) {
     const int b0 = c_tab.mono_class_begin[0], b1 = c_tab.mono_class_begin[1];
     const int b2 = c_tab.mono_class_begin[2], b3 = c_tab.mono_class_begin[3];
     const int t1 = (b1 - b0) * 30, t2 = t1 + (b2 - b1) * 18;
-    mono_class<PZ, -4, 10, P>(box, b0, b1, 0, lbase, sx, syw, sy, phi, gx, gy, gz);
-    mono_class<PZ, -2, 6, P>(box, b1, b2, t1, lbase, sx, syw, sy, phi, gx, gy, gz);
-    mono_class<PZ, 0, 2, P>(box, b2, b3, t2, lbase, sx, syw, sy, phi, gx, gy, gz);
+    mono_class<PZ, -4, 10, P>(box, b0, b1, 0, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
+    mono_class<PZ, -2, 6, P>(box, b1, b2, t1, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
+    mono_class<PZ, 0, 2, P>(box, b2, b3, t2, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
 }
 
+
 template <bool MIXED>
-__global__ __launch_bounds__(128) void k_mono(const SubDev* __restrict__ subs,
-                                              const int32_t* __restrict__ list,
-                                              const double* __restrict__ mass,
-                                              double* __restrict__ Lf, double G) {
+__device__ __forceinline__ void mono_item(const Ctx& cx, int sid, unsigned char* smem) {
     using P = typename std::conditional<MIXED, float, double>::type;
-    __shared__ P box[PW * PW * PW];
+    P* box = reinterpret_cast<P*>(smem);
     const int t = threadIdx.x;
-    const SubDev& T = subs[list[blockIdx.x]];
-    for (int c = t; c < PW * PW * PW; c += 128) {
+    const SubDev& T = cx.subs[sid];
+    __syncthreads();
+    for (int c = t; c < PW * PW * PW; c += 256) {
         const int wx = c % PW, wy = (c / PW) % PW, wz = c / (PW * PW);
         const int lx = wx - REACH, ly = wy - REACH, lz = wz - REACH;
         const int ox = lx < 0 ? -1 : (lx >= NS ? 1 : 0);
@@ -526,47 +527,57 @@ __global__ __launch_bounds__(128) void k_mono(const SubDev* __restrict__ subs,
         P mm = 0;
         if (code >= 0 && (code & 1) == 0) {
             const int cq = ((lz - NS * oz) * NS + (ly - NS * oy)) * NS + (lx - NS * ox);
-            mm = P(mass[size_t(code >> 1) * NCELL + cq]);
+            mm = P(cx.mass[size_t(code >> 1) * NCELL + cq]);
         }
         box[c] = mm;
     }
     __syncthreads();
-    const int pz = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int pz = w & 1, half = w >> 1;
     const int lane = t & 63, x = lane & 7, y = lane >> 3;
     const int sx = 1 - 2 * (x & 1), sy = 1 - 2 * (y & 1);
     const int lbase = (y + REACH) * PW + (x + REACH);
     const int syw = sy * PW;
     double phi[4] = {0, 0, 0, 0}, gx[4] = {0, 0, 0, 0}, gy[4] = {0, 0, 0, 0}, gz[4] = {0, 0, 0, 0};
-    if (pz == 0) mono_all<0, P>(box, lbase, sx, syw, sy, phi, gx, gy, gz);
-    else mono_all<1, P>(box, lbase, sx, syw, sy, phi, gx, gy, gz);
-    const double h = T.h, gh = G / (h * h), gp = -G / h;
-    double* out = Lf + size_t(T.idx) * NLEAF * NCELL;
+    if (pz == 0) mono_all<0, P>(box, half, 2, lbase, sx, syw, sy, phi, gx, gy, gz);
+    else mono_all<1, P>(box, half, 2, lbase, sx, syw, sy, phi, gx, gy, gz);
+    // column half 1 hands its partial sums to half 0 through LDS
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(smem);
+    if (half == 1) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int q = (pz + 2 * k) * 64 + lane;
-        out[0 * NCELL + q] = gp * phi[k];
-        out[1 * NCELL + q] = gh * gx[k];
-        out[2 * NCELL + q] = gh * gy[k];
-        out[3 * NCELL + q] = gh * gz[k];
+        for (int k = 0; k < 4; ++k) {
+            red[((pz * 16) + 4 * k + 0) * 64 + lane] = phi[k];
+            red[((pz * 16) + 4 * k + 1) * 64 + lane] = gx[k];
+            red[((pz * 16) + 4 * k + 2) * 64 + lane] = gy[k];
+            red[((pz * 16) + 4 * k + 3) * 64 + lane] = gz[k];
+        }
+    }
+    __syncthreads();
+    if (half == 0) {
+        const double h = T.h, G = cx.G, gh = G / (h * h), gp = -G / h;
+        double* out = cx.Lf + size_t(T.idx) * NLEAF * NCELL;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int q = (pz + 2 * k) * 64 + lane;
+            out[0 * NCELL + q] = gp * (phi[k] + red[((pz * 16) + 4 * k + 0) * 64 + lane]);
+            out[1 * NCELL + q] = gh * (gx[k] + red[((pz * 16) + 4 * k + 1) * 64 + lane]);
+            out[2 * NCELL + q] = gh * (gy[k] + red[((pz * 16) + 4 * k + 2) * 64 + lane]);
+            out[3 * NCELL + q] = gh * (gz[k] + red[((pz * 16) + 4 * k + 3) * 64 + lane]);
+        }
     }
 }
 
-// ---------------------------------------------------------------------------
-// step 2c: top level under the all-pairs rule
-// ---------------------------------------------------------------------------
-// block = 64 threads (one target plane); the source loop is uniform across
-// the wave so source data come through scalar loads.
+// Top-level tile (all-pairs rule): 64 targets (one plane of a top-level
+// sub-grid) against a chunk of the tree's top-level cells; the 4 waves take
+// every fourth source and their sums are added in a fixed order.  The source
+// index is uniform across a wave, so source data come through scalar loads.
 template <bool MIXED>
-__global__ __launch_bounds__(64) void k_top(const SubDev* __restrict__ subs,
-                                            const TopItem* __restrict__ items,
-                                            const int32_t* __restrict__ top_src,
-                                            const double* __restrict__ mass,
-                                            const double* __restrict__ rec,
-                                            double* __restrict__ part, int corr) {
+__device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsigned char* smem) {
     using P = typename std::conditional<MIXED, float, double>::type;
-    const TopItem it = items[blockIdx.x];
-    const SubDev& T = subs[it.target];
-    const int lane = threadIdx.x, x = lane & 7, y = lane >> 3;
+    const SubDev& T = cx.subs[it.target];
+    const int t = threadIdx.x, lane = t & 63, x = lane & 7, y = lane >> 3;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int q = it.zt * 64 + lane;
     const bool tref = T.kind == 1;
     const double h = T.h;
@@ -574,21 +585,21 @@ __global__ __launch_bounds__(64) void k_top(const SubDev* __restrict__ subs,
     double mA, dAx = 0, dAy = 0, dAz = 0;
     P oa[7] = {0, 0, 0, 0, 0, 0, 0};
     if (tref) {
-        const double* r = rec + size_t(T.idx) * NREC * NCELL;
+        const double* r = cx.rec + size_t(T.idx) * NREC * NCELL;
         mA = r[R_M * NCELL + q];
         dAx = r[R_DX * NCELL + q];
         dAy = r[R_DY * NCELL + q];
         dAz = r[R_DZ * NCELL + q];
         for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q]);
     } else {
-        mA = mass[size_t(T.idx) * NCELL + q];
+        mA = cx.mass[size_t(T.idx) * NCELL + q];
     }
     const P inv_ma = mA > 0 ? P(1.0 / mA) : P(0);
-    const bool use_corr = corr != 0;
+    const bool use_corr = cx.corr != 0;
     Acc<P> acc;
     acc.zero();
-    for (int j = it.src_begin; j < it.src_end; ++j) {
-        const SubDev& S = subs[top_src[it.src_list + (j >> 9)]];
+    for (int j = it.src_begin + w; j < it.src_end; j += 4) {
+        const SubDev& S = cx.subs[cx.top_src[it.src_list + (j >> 9)]];
         const int cq = j & 511;
         const int dx = NS * S.coord[0] + (cq & 7) - cax;
         const int dy = NS * S.coord[1] + ((cq >> 3) & 7) - cay;
@@ -598,10 +609,10 @@ __global__ __launch_bounds__(64) void k_top(const SubDev* __restrict__ subs,
         if (d2 == 0 || (d2 < 9 && tref && sref)) continue;
         P src[NREC];
         if (sref) {
-            const double* r = rec + size_t(S.idx) * NREC * NCELL + cq;
+            const double* r = cx.rec + size_t(S.idx) * NREC * NCELL + cq;
             for (int k = 0; k < NREC; ++k) src[k] = P(r[k * NCELL]);
         } else {
-            src[0] = P(mass[size_t(S.idx) * NCELL + cq]);
+            src[0] = P(cx.mass[size_t(S.idx) * NCELL + cq]);
             for (int k = 1; k < NREC; ++k) src[k] = P(0);
         }
         const P X = P(-h * dx) + (P(dAx) - src[R_DX]);
@@ -612,38 +623,116 @@ __global__ __launch_bounds__(64) void k_top(const SubDev* __restrict__ subs,
         else
             pair_terms<false, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], inv_ma, oa, use_corr, acc);
     }
-    double* out = part + size_t(it.part) * NLOC * NCELL + q;
-    out[0] = double(acc.l0);
-    for (int i = 0; i < 3; ++i) out[(T_L1 + i) * NCELL] = double(acc.l1[i]);
-    for (int i = 0; i < 5; ++i) out[(T_L2 + i) * NCELL] = double(acc.l2[i]);
-    for (int i = 0; i < 7; ++i) out[(T_L3 + i) * NCELL] = double(acc.l3[i]);
-    for (int i = 0; i < 3; ++i) out[(T_S + i) * NCELL] = double(acc.s[i]);
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(smem);
+    {
+        double v[NLOC];
+        v[0] = double(acc.l0);
+        for (int i = 0; i < 3; ++i) v[T_L1 + i] = double(acc.l1[i]);
+        for (int i = 0; i < 5; ++i) v[T_L2 + i] = double(acc.l2[i]);
+        for (int i = 0; i < 7; ++i) v[T_L3 + i] = double(acc.l3[i]);
+        for (int i = 0; i < 3; ++i) v[T_S + i] = double(acc.s[i]);
+#pragma unroll
+        for (int k = 0; k < NLOC; ++k) red[(w * NLOC + k) * 64 + lane] = v[k];
+    }
+    __syncthreads();
+    double* out = cx.part + size_t(it.part) * NLOC * NCELL + it.zt * 64;
+    for (int i = t; i < NLOC * 64; i += 256) {
+        const int k = i >> 6, l = i & 63;
+        out[k * NCELL + l] = red[(0 * NLOC + k) * 64 + l] + red[(1 * NLOC + k) * 64 + l] +
+                             red[(2 * NLOC + k) * 64 + l] + red[(3 * NLOC + k) * 64 + l];
+    }
 }
 
+template <bool MIXED>
+__device__ __forceinline__ void run_item(const Ctx& cx, const Item& it, unsigned char* smem) {
+    switch (it.kind) {
+        case IT_MP_REF: mp_item<false, MIXED>(cx, it.sub, it.a, it.b, smem); break;
+        case IT_MP_LEAF: mp_item<true, MIXED>(cx, it.sub, it.a, 0, smem); break;
+        case IT_MONO: mono_item<MIXED>(cx, it.sub, smem); break;
+        default: top_item<MIXED>(cx, cx.top_items[it.sub], smem); break;
+    }
+}
+
+// One launch per class: one block per item of that class.
+template <int KIND, bool MIXED>
+__global__ __launch_bounds__(256) void k_class(Ctx cx, const Item* __restrict__ items) {
+    using P = typename std::conditional<MIXED, float, double>::type;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P>::BYTES];
+    const Item it = items[blockIdx.x];
+    if (KIND == IT_MP_REF) mp_item<false, MIXED>(cx, it.sub, it.a, it.b, smem);
+    else if (KIND == IT_MP_LEAF) mp_item<true, MIXED>(cx, it.sub, it.a, 0, smem);
+    else if (KIND == IT_MONO) mono_item<MIXED>(cx, it.sub, smem);
+    else top_item<MIXED>(cx, cx.top_items[it.sub], smem);
+}
+
+// Persistent launch of every class and tree: each block takes the next item
+// of the (largest-first) list from a device counter until the list is
+// exhausted, so every block exits once all items are taken.
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_persist(Ctx cx, const Item* __restrict__ items, int n,
+                                                 int* __restrict__ counter) {
+    using P = typename std::conditional<MIXED, float, double>::type;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P>::BYTES];
+    __shared__ int s_it;
+    for (;;) {
+        if (threadIdx.x == 0) s_it = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = s_it;
+        __syncthreads();
+        if (it >= n) break;
+        run_item<MIXED>(cx, items[it], smem);
+    }
+}
+
+__global__ void k_reset_counter(int* counter) { *counter = 0; }
+
 // Sum a top-level target's partial slots in a fixed order and scale.
-__global__ __launch_bounds__(512) void k_top_reduce(const SubDev* __restrict__ subs,
-                                                    const TopReduce* __restrict__ reds,
-                                                    const double* __restrict__ part,
-                                                    double* __restrict__ Lr, double* __restrict__ Lf,
-                                                    double G, int corr) {
-    const TopReduce R = reds[blockIdx.x];
-    const SubDev& T = subs[R.target];
+// grid: (reductions x 19 components), 512 threads (cells).
+__global__ __launch_bounds__(512) void k_top_reduce(Ctx cx, const TopReduce* __restrict__ reds) {
+    const TopReduce R = reds[blockIdx.x / NLOC];
+    const int k = blockIdx.x % NLOC;
+    const SubDev& T = cx.subs[R.target];
     const int q = threadIdx.x;
-    double v[NLOC];
-    for (int k = 0; k < NLOC; ++k) v[k] = 0;
-    for (int p = 0; p < R.n_part; ++p) {
-        const double* src = part + size_t(R.part_begin + p) * NLOC * NCELL + q;
-        for (int k = 0; k < NLOC; ++k) v[k] += src[k * NCELL];
-    }
-    const double gs = corr ? -G / 6.0 : 0.0;
+    double v = 0;
+    for (int p = 0; p < R.n_part; ++p) v += cx.part[(size_t(R.part_begin + p) * NLOC + k) * NCELL + q];
+    const double G = cx.G, gs = cx.corr ? -G / 6.0 : 0.0;
     if (T.kind == 1) {
-        double* out = Lr + size_t(T.idx) * NLOC * NCELL + q;
-        for (int k = 0; k < NLOC; ++k) out[k * NCELL] = (k >= T_S ? gs : -G) * v[k];
+        cx.Lr[(size_t(T.idx) * NLOC + k) * NCELL + q] = (k >= T_S ? gs : -G) * v;
     } else {
-        double* out = Lf + size_t(T.idx) * NLEAF * NCELL + q;
-        out[0] = -G * v[0];
-        for (int a = 0; a < 3; ++a) out[(1 + a) * NCELL] = G * v[T_L1 + a] + gs * v[T_S + a];
+        // leaf target: phi from L0, g = G L1 + gs S, accumulated into Lf
+        double* out = cx.Lf + size_t(T.idx) * NLEAF * NCELL + q;
+        if (k == 0) out[0] = -G * v;
+        else if (k >= T_L1 && k < T_L1 + 3) out[(1 + k - T_L1) * NCELL] = G * v;
     }
+    (void)gs;
+}
+
+// The correction part of a top-level leaf target (kept apart from the L1
+// part so that each output is written by one block).
+__global__ __launch_bounds__(512) void k_top_reduce_leaf_dg(Ctx cx, const TopReduce* __restrict__ reds) {
+    const TopReduce R = reds[blockIdx.x];
+    const SubDev& T = cx.subs[R.target];
+    if (T.kind == 1 || !cx.corr) return;
+    const int q = threadIdx.x;
+    const double gs = -cx.G / 6.0;
+    double* out = cx.Lf + size_t(T.idx) * NLEAF * NCELL + q;
+    for (int a = 0; a < 3; ++a) {
+        double v = 0;
+        for (int p = 0; p < R.n_part; ++p) v += cx.part[(size_t(R.part_begin + p) * NLOC + T_S + a) * NCELL + q];
+        out[(1 + a) * NCELL] += gs * v;
+    }
+}
+
+// Level-0 refined sub-grids in the stencil-only mode: total = own.
+// grid: (sub-grids x 19 components), 512 threads.
+__global__ __launch_bounds__(512) void k_sum_parts(Ctx cx, const int32_t* __restrict__ list) {
+    const SubDev& T = cx.subs[list[blockIdx.x / NLOC]];
+    const int k = blockIdx.x % NLOC, q = threadIdx.x;
+    double v = 0;
+    for (int g = 0; g < cx.ngroups; ++g)
+        v += cx.Lp[size_t(g) * size_t(cx.part_stride) + (size_t(T.idx) * NLOC + k) * NCELL + q];
+    cx.Lr[(size_t(T.idx) * NLOC + k) * NCELL + q] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -653,24 +742,21 @@ __global__ __launch_bounds__(512) void k_top_reduce(const SubDev* __restrict__ s
 // the child COM, r = X_child - X_parent:
 //   o0 = L0 + L1.r + 1/2 r.L2.r + 1/6 L3:rrr,  o1 = L1 + L2.r + 1/2 L3:rr,
 //   o2 = L2 + L3.r,  o3 = L3,  dg passed unchanged.
-// Refined children accumulate into Lr; leaf children produce phi and g.
+// Refined children: total = own (sum of plane groups) + shifted parent.
+// Leaf children: phi = own + o0,  g = own - o1 + dg.
 // grid: (refined parents at level l) x 8 child sub-grids, 512 threads.
-__global__ __launch_bounds__(512) void k_l2l(const SubDev* __restrict__ subs,
-                                             const int32_t* __restrict__ list,
-                                             const double* __restrict__ rec,
-                                             double* __restrict__ Lr,
-                                             const double* __restrict__ Lf,
+__global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__ list,
                                              double* __restrict__ phi, double* __restrict__ gout) {
     __shared__ double obuf[4][NCELL];
-    const SubDev& Ps = subs[list[blockIdx.x >> 3]];
+    const SubDev& Ps = cx.subs[list[blockIdx.x >> 3]];
     const int e = blockIdx.x & 7;
-    const SubDev& Cs = subs[Ps.child[e]];
+    const SubDev& Cs = cx.subs[Ps.child[e]];
     const int q = threadIdx.x;
     const int x = q & 7, y = (q >> 3) & 7, z = q >> 6;
     const int px = (x >> 1) + 4 * (e >> 2), py = (y >> 1) + 4 * ((e >> 1) & 1), pz = (z >> 1) + 4 * (e & 1);
     const int pq = (pz * NS + py) * NS + px;
-    const double* L = Lr + size_t(Ps.idx) * NLOC * NCELL + pq;
-    const double* pr = rec + size_t(Ps.idx) * NREC * NCELL + pq;
+    const double* L = cx.Lr + size_t(Ps.idx) * NLOC * NCELL + pq;
+    const double* pr = cx.rec + size_t(Ps.idx) * NREC * NCELL + pq;
     double l0 = L[0];
     double l1x = L[1 * NCELL], l1y = L[2 * NCELL], l1z = L[3 * NCELL];
     double qxx = L[4 * NCELL], qyy = L[5 * NCELL], qxy = L[6 * NCELL], qxz = L[7 * NCELL], qyz = L[8 * NCELL];
@@ -682,7 +768,7 @@ __global__ __launch_bounds__(512) void k_l2l(const SubDev* __restrict__ subs,
     double cdx = 0, cdy = 0, cdz = 0;
     const bool cref = Cs.kind == 1;
     if (cref) {
-        const double* cr = rec + size_t(Cs.idx) * NREC * NCELL + q;
+        const double* cr = cx.rec + size_t(Cs.idx) * NREC * NCELL + q;
         cdx = cr[R_DX * NCELL];
         cdy = cr[R_DY * NCELL];
         cdz = cr[R_DZ * NCELL];
@@ -690,7 +776,6 @@ __global__ __launch_bounds__(512) void k_l2l(const SubDev* __restrict__ subs,
     const double rx = ((x & 1) - 0.5) * hc + cdx - pr[R_DX * NCELL];
     const double ry = ((y & 1) - 0.5) * hc + cdy - pr[R_DY * NCELL];
     const double rz = ((z & 1) - 0.5) * hc + cdz - pr[R_DZ * NCELL];
-    // L3:rr (vector) and L3:rrr
     double w[3];
     oct_rr<double>(o, rx * rx, ry * ry, rz * rz, rx * ry, rx * rz, ry * rz, w);
     const double l3rrr = rx * w[0] + ry * w[1] + rz * w[2];
@@ -703,34 +788,42 @@ __global__ __launch_bounds__(512) void k_l2l(const SubDev* __restrict__ subs,
     const double o1y = l1y + vy + 0.5 * w[1];
     const double o1z = l1z + vz + 0.5 * w[2];
     if (cref) {
-        double* C = Lr + size_t(Cs.idx) * NLOC * NCELL + q;
-        // o2 = L2 + L3.r (trace-free)
         const double oxzz = -o[0] - o[3], oyzz = -o[1] - o[5];
-        const double o2xx = qxx + o[0] * rx + o[1] * ry + o[2] * rz;
-        const double o2yy = qyy + o[3] * rx + o[5] * ry + o[6] * rz;
-        const double o2xy = qxy + o[1] * rx + o[3] * ry + o[4] * rz;
-        const double o2xz = qxz + o[2] * rx + o[4] * ry + oxzz * rz;
-        const double o2yz = qyz + o[4] * rx + o[6] * ry + oyzz * rz;
-        C[0] += o0;
-        C[1 * NCELL] += o1x;
-        C[2 * NCELL] += o1y;
-        C[3 * NCELL] += o1z;
-        C[4 * NCELL] += o2xx;
-        C[5 * NCELL] += o2yy;
-        C[6 * NCELL] += o2xy;
-        C[7 * NCELL] += o2xz;
-        C[8 * NCELL] += o2yz;
-        for (int k = 0; k < 7; ++k) C[(T_L3 + k) * NCELL] += o[k];
-        C[16 * NCELL] += sgx;
-        C[17 * NCELL] += sgy;
-        C[18 * NCELL] += sgz;
+        double sh[NLOC];
+        sh[0] = o0;
+        sh[1] = o1x;
+        sh[2] = o1y;
+        sh[3] = o1z;
+        sh[4] = qxx + o[0] * rx + o[1] * ry + o[2] * rz;
+        sh[5] = qyy + o[3] * rx + o[5] * ry + o[6] * rz;
+        sh[6] = qxy + o[1] * rx + o[3] * ry + o[4] * rz;
+        sh[7] = qxz + o[2] * rx + o[4] * ry + oxzz * rz;
+        sh[8] = qyz + o[4] * rx + o[6] * ry + oyzz * rz;
+        for (int k = 0; k < 7; ++k) sh[T_L3 + k] = o[k];
+        sh[16] = sgx;
+        sh[17] = sgy;
+        sh[18] = sgz;
+        const size_t base = size_t(Cs.idx) * NLOC * NCELL + q;
+        for (int k = 0; k < NLOC; ++k) {
+            double own = 0;
+            for (int g = 0; g < cx.ngroups; ++g) own += cx.Lp[size_t(g) * size_t(cx.part_stride) + base + k * NCELL];
+            cx.Lr[base + k * NCELL] = own + sh[k];
+        }
     } else {
-        const double* F = Lf + size_t(Cs.idx) * NLEAF * NCELL + q;
+        const double* F = cx.Lf + size_t(Cs.idx) * NLEAF * NCELL + q;
+        double f0 = F[0], f1 = F[1 * NCELL], f2 = F[2 * NCELL], f3 = F[3 * NCELL];
+        if (Cs.slot3 >= 0) {
+            const double* F3 = cx.Lf3 + size_t(Cs.slot3) * NLEAF * NCELL + q;
+            f0 += F3[0];
+            f1 += F3[1 * NCELL];
+            f2 += F3[2 * NCELL];
+            f3 += F3[3 * NCELL];
+        }
         const int io = io_index(q);
-        obuf[0][io] = F[0] + o0;
-        obuf[1][io] = F[1 * NCELL] - o1x + sgx;
-        obuf[2][io] = F[2 * NCELL] - o1y + sgy;
-        obuf[3][io] = F[3 * NCELL] - o1z + sgz;
+        obuf[0][io] = f0 + o0;
+        obuf[1][io] = f1 - o1x + sgx;
+        obuf[2][io] = f2 - o1y + sgy;
+        obuf[3][io] = f3 - o1z + sgz;
     }
     if (!cref) {
         __syncthreads();
@@ -743,16 +836,18 @@ __global__ __launch_bounds__(512) void k_l2l(const SubDev* __restrict__ subs,
 }
 
 // Leaves without a parent: output their own terms.  grid: one block per leaf.
-__global__ __launch_bounds__(512) void k_leaf_out(const SubDev* __restrict__ subs,
-                                                  const int32_t* __restrict__ list,
-                                                  const double* __restrict__ Lf,
+__global__ __launch_bounds__(512) void k_leaf_out(Ctx cx, const int32_t* __restrict__ list,
                                                   double* __restrict__ phi, double* __restrict__ gout) {
     __shared__ double obuf[4][NCELL];
-    const SubDev& S = subs[list[blockIdx.x]];
+    const SubDev& S = cx.subs[list[blockIdx.x]];
     const int q = threadIdx.x;
-    const double* F = Lf + size_t(S.idx) * NLEAF * NCELL + q;
+    const double* F = cx.Lf + size_t(S.idx) * NLEAF * NCELL + q;
     const int io = io_index(q);
-    for (int k = 0; k < 4; ++k) obuf[k][io] = F[k * NCELL];
+    for (int k = 0; k < 4; ++k) {
+        double v = F[k * NCELL];
+        if (S.slot3 >= 0) v += cx.Lf3[size_t(S.slot3) * NLEAF * NCELL + k * NCELL + q];
+        obuf[k][io] = v;
+    }
     __syncthreads();
     phi[size_t(S.idx) * NCELL + q] = obuf[0][q];
     for (int a = 0; a < 3; ++a) gout[(size_t(S.idx) * 3 + a) * NCELL + q] = obuf[1 + a][q];
@@ -773,52 +868,65 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v) { *p = v
 // ---------------------------------------------------------------------------
 // launchers (host)
 // ---------------------------------------------------------------------------
-
 hipError_t upload_tables(const StencilTables* t, hipStream_t st) {
     return hipMemcpyToSymbolAsync(HIP_SYMBOL(c_tab), t, sizeof(StencilTables), 0,
                                   hipMemcpyHostToDevice, st);
 }
 
-void launch_p2m(const Launch& a, const double* rho, int n_leaf) {
+void launch_p2m(const Ctx& a, const double* rho, int n_leaf) {
     if (n_leaf > 0) hipLaunchKernelGGL(k_p2m, dim3(n_leaf), dim3(512), 0, a.st, rho, a.subs, a.leaf_sub, a.mass);
 }
 
-void launch_m2m(const Launch& a, const int32_t* list, int n) {
+void launch_m2m(const Ctx& a, const int32_t* list, int n) {
     if (n > 0) hipLaunchKernelGGL(k_m2m, dim3(n), dim3(512), 0, a.st, a.subs, list, a.mass, a.rec);
 }
 
-void launch_mp(const Launch& a, const int32_t* list, int n, bool leaf_targets) {
+template <int K>
+static void launch_class_k(const Ctx& a, const Item* items, int n) {
+    if (a.mixed) hipLaunchKernelGGL((k_class<K, true>), dim3(n), dim3(256), 0, a.st, a, items);
+    else hipLaunchKernelGGL((k_class<K, false>), dim3(n), dim3(256), 0, a.st, a, items);
+}
+
+void launch_class(const Ctx& a, int kind, const Item* items, int n) {
     if (n <= 0) return;
-    dim3 grid(n * 8), block(256);
-    if (leaf_targets) {
-        if (a.mixed) hipLaunchKernelGGL((k_mp<true, true>), grid, block, 0, a.st, a.subs, list, a.mass, a.rec, a.Lr, a.Lf, a.G, a.corr);
-        else hipLaunchKernelGGL((k_mp<true, false>), grid, block, 0, a.st, a.subs, list, a.mass, a.rec, a.Lr, a.Lf, a.G, a.corr);
-    } else {
-        if (a.mixed) hipLaunchKernelGGL((k_mp<false, true>), grid, block, 0, a.st, a.subs, list, a.mass, a.rec, a.Lr, a.Lf, a.G, a.corr);
-        else hipLaunchKernelGGL((k_mp<false, false>), grid, block, 0, a.st, a.subs, list, a.mass, a.rec, a.Lr, a.Lf, a.G, a.corr);
+    switch (kind) {
+        case IT_MP_REF: launch_class_k<IT_MP_REF>(a, items, n); break;
+        case IT_MP_LEAF: launch_class_k<IT_MP_LEAF>(a, items, n); break;
+        case IT_MONO: launch_class_k<IT_MONO>(a, items, n); break;
+        default: launch_class_k<IT_TOP>(a, items, n); break;
     }
 }
 
-void launch_mono(const Launch& a, const int32_t* list, int n) {
+void launch_persist(const Ctx& a, const Item* items, int n, int* counter, int grid) {
+    if (n <= 0 || grid <= 0) return;
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, a.st, counter);
+    if (a.mixed) hipLaunchKernelGGL((k_persist<true>), dim3(grid), dim3(256), 0, a.st, a, items, n, counter);
+    else hipLaunchKernelGGL((k_persist<false>), dim3(grid), dim3(256), 0, a.st, a, items, n, counter);
+}
+
+int persist_blocks_per_cu(int mixed) {
+    int nb = 0;
+    hipError_t e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<true>, 256, 0)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<false>, 256, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
+void launch_top_reduce(const Ctx& a, const TopReduce* reds, int n) {
     if (n <= 0) return;
-    if (a.mixed) hipLaunchKernelGGL((k_mono<true>), dim3(n), dim3(128), 0, a.st, a.subs, list, a.mass, a.Lf, a.G);
-    else hipLaunchKernelGGL((k_mono<false>), dim3(n), dim3(128), 0, a.st, a.subs, list, a.mass, a.Lf, a.G);
+    hipLaunchKernelGGL(k_top_reduce, dim3(n * NLOC), dim3(512), 0, a.st, a, reds);
+    hipLaunchKernelGGL(k_top_reduce_leaf_dg, dim3(n), dim3(512), 0, a.st, a, reds);
 }
 
-void launch_top(const Launch& a, const TopItem* items, int n_items, const int32_t* top_src,
-                const TopReduce* reds, int n_red) {
-    if (n_items <= 0) return;
-    if (a.mixed) hipLaunchKernelGGL((k_top<true>), dim3(n_items), dim3(64), 0, a.st, a.subs, items, top_src, a.mass, a.rec, a.part, a.corr);
-    else hipLaunchKernelGGL((k_top<false>), dim3(n_items), dim3(64), 0, a.st, a.subs, items, top_src, a.mass, a.rec, a.part, a.corr);
-    hipLaunchKernelGGL(k_top_reduce, dim3(n_red), dim3(512), 0, a.st, a.subs, reds, a.part, a.Lr, a.Lf, a.G, a.corr);
+void launch_sum_parts(const Ctx& a, const int32_t* list, int n) {
+    if (n > 0) hipLaunchKernelGGL(k_sum_parts, dim3(n * NLOC), dim3(512), 0, a.st, a, list);
 }
 
-void launch_l2l(const Launch& a, const int32_t* list, int n, double* phi, double* g) {
-    if (n > 0) hipLaunchKernelGGL(k_l2l, dim3(n * 8), dim3(512), 0, a.st, a.subs, list, a.rec, a.Lr, a.Lf, phi, g);
+void launch_l2l(const Ctx& a, const int32_t* list, int n, double* phi, double* g) {
+    if (n > 0) hipLaunchKernelGGL(k_l2l, dim3(n * 8), dim3(512), 0, a.st, a, list, phi, g);
 }
 
-void launch_leaf_out(const Launch& a, const int32_t* list, int n, double* phi, double* g) {
-    if (n > 0) hipLaunchKernelGGL(k_leaf_out, dim3(n), dim3(512), 0, a.st, a.subs, list, a.Lf, phi, g);
+void launch_leaf_out(const Ctx& a, const int32_t* list, int n, double* phi, double* g) {
+    if (n > 0) hipLaunchKernelGGL(k_leaf_out, dim3(n), dim3(512), 0, a.st, a, list, phi, g);
 }
 
 void launch_check_density(const double* rho, int64_t n, unsigned long long* bad, hipStream_t st) {

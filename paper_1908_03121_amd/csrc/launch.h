@@ -8,30 +8,37 @@
 
 namespace fmmg {
 
-// Device buffers and scalars shared by every launch of one solve.
-struct Launch {
+// Device buffers and scalars of one solve, passed by value to the kernels.
+struct Ctx {
     const SubDev* subs;
     const int32_t* leaf_sub;
     double* mass;
     double* rec;
-    double* Lr;
-    double* Lf;
-    double* part;
+    double* Lp;             // [MAX_GROUPS][n_ref][19][512] own terms per plane group
+    double* Lr;             // [n_ref][19][512] totals
+    double* Lf;             // [n_leaf][4][512]
+    double* Lf3;            // [n_slot3][4][512]
+    double* part;           // top-level partial sums
+    const TopItem* top_items;
+    const int32_t* top_src;
+    int64_t part_stride;    // elements between plane groups of Lp
     double G;
     int corr;
     int mixed;
+    int ngroups;
     hipStream_t st;
 };
 
 hipError_t upload_tables(const StencilTables* t, hipStream_t st);
-void launch_p2m(const Launch& a, const double* rho, int n_leaf);
-void launch_m2m(const Launch& a, const int32_t* list, int n);
-void launch_mp(const Launch& a, const int32_t* list, int n, bool leaf_targets);
-void launch_mono(const Launch& a, const int32_t* list, int n);
-void launch_top(const Launch& a, const TopItem* items, int n_items, const int32_t* top_src,
-                const TopReduce* reds, int n_red);
-void launch_l2l(const Launch& a, const int32_t* list, int n, double* phi, double* g);
-void launch_leaf_out(const Launch& a, const int32_t* list, int n, double* phi, double* g);
+void launch_p2m(const Ctx& a, const double* rho, int n_leaf);
+void launch_m2m(const Ctx& a, const int32_t* list, int n);
+void launch_class(const Ctx& a, int kind, const Item* items, int n);
+void launch_persist(const Ctx& a, const Item* items, int n, int* counter, int grid);
+int persist_blocks_per_cu(int mixed);
+void launch_top_reduce(const Ctx& a, const TopReduce* reds, int n);
+void launch_sum_parts(const Ctx& a, const int32_t* list, int n);
+void launch_l2l(const Ctx& a, const int32_t* list, int n, double* phi, double* g);
+void launch_leaf_out(const Ctx& a, const int32_t* list, int n, double* phi, double* g);
 void launch_check_density(const double* rho, int64_t n, unsigned long long* bad, hipStream_t st);
 
 }  // namespace fmmg

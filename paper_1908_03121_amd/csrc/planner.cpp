@@ -190,6 +190,7 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
             int l = T.level[i], x = T.coord[3 * i], y = T.coord[3 * i + 1], z = T.coord[3 * i + 2];
             SubDev& S = P.subs[size_t(base + i)];
             memset(&S, 0, sizeof(S));
+            S.slot3 = -1;
             S.level = l;
             S.tree = t;
             S.coord[0] = x; S.coord[1] = y; S.coord[2] = z;
@@ -276,6 +277,11 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
             }
         }
     }
+    for (size_t k = 0; k < P.mp_leaf.size(); ++k) P.subs[size_t(P.mp_leaf[k])].slot3 = int32_t(k);
+    P.n_slot3 = int32_t(P.mp_leaf.size());
+    if (!top_full)
+        for (int32_t sidx : P.ref_sub)
+            if (P.subs[size_t(sidx)].level == 0) P.top_ref_stencil.push_back(sidx);
     P.level_ref_begin.assign(size_t(P.max_level) + 2, 0);
     for (int l = 0; l <= P.max_level; ++l) {
         P.level_ref_begin[size_t(l)] = int32_t(P.ref_by_level.size());
@@ -328,7 +334,50 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
             }
         }
     }
+    build_items(&P, 1);
     return 0;
+}
+
+void build_items(HostPlan* Pp, int ngroups) {
+    HostPlan& P = *Pp;
+    if (ngroups < 1) ngroups = 1;
+    if (ngroups > MAX_GROUPS) ngroups = MAX_GROUPS;
+    P.ngroups = ngroups;
+    StencilTables tab;
+    build_stencil_tables(&tab);
+    // estimated cost of an item, in refined-pair units
+    struct Costed { Item it; double cost; };
+    std::vector<Costed> all;
+    P.items_class.clear();
+    auto add = [&](const Item& it, double cost) {
+        P.items_class.push_back(it);
+        all.push_back({it, cost});
+    };
+    P.class_begin[IT_MP_REF] = 0;
+    for (int32_t s : P.mp_ref) {
+        const bool nearc = (P.subs[size_t(s)].flags & 1) != 0;
+        for (int zt = 0; zt < NS; ++zt)
+            for (int g = 0; g < ngroups; ++g) {
+                int i0 = g * NDZ / ngroups, i1 = (g + 1) * NDZ / ngroups;
+                double n = 0;
+                for (int i = i0; i < i1; ++i) n += tab.mp_far_count[i] + (nearc ? tab.mp_near_count[i] : 0);
+                add(Item{IT_MP_REF, s, zt, g}, 64.0 * n + 2000.0);
+            }
+    }
+    P.class_begin[IT_MP_LEAF] = int32_t(P.items_class.size());
+    for (int32_t s : P.mp_leaf)
+        for (int zt = 0; zt < NS; ++zt) add(Item{IT_MP_LEAF, s, zt, 0}, 64.0 * 743.0 * 0.63 + 2000.0);
+    P.class_begin[IT_MONO] = int32_t(P.items_class.size());
+    for (int32_t s : P.mono_leaf) add(Item{IT_MONO, s, 0, 0}, 512.0 * 743.0 * 0.1 + 4000.0);
+    P.class_begin[IT_TOP] = int32_t(P.items_class.size());
+    for (size_t k = 0; k < P.top_items.size(); ++k) {
+        const TopItem& ti = P.top_items[k];
+        add(Item{IT_TOP, int32_t(k), 0, 0}, 64.0 * double(ti.src_end - ti.src_begin) + 1000.0);
+    }
+    P.class_begin[IT_KINDS] = int32_t(P.items_class.size());
+    std::stable_sort(all.begin(), all.end(), [](const Costed& a, const Costed& b) { return a.cost > b.cost; });
+    P.items_lpt.clear();
+    for (const Costed& c : all) P.items_lpt.push_back(c.it);
 }
 
 }  // namespace fmmg

@@ -44,6 +44,15 @@ struct HostPlan {
     std::vector<int32_t> level_ref_begin;  // refined sub ids sorted by level: [l, l+1)
     std::vector<int32_t> ref_by_level;
     std::vector<int32_t> top_leaf;     // top-level leaves (output straight from own terms)
+    std::vector<int32_t> top_ref_stencil;  // level-0 refined sub-grids when the top level
+                                           // uses the stencil (their total = own terms)
+    int32_t n_slot3 = 0;               // leaves with refined neighbours (Lf3 slots)
+
+    // same-level work items for a given number of plane groups
+    int ngroups = 1;
+    std::vector<Item> items_class;     // grouped by kind, in list order
+    int32_t class_begin[IT_KINDS + 1] = {0, 0, 0, 0, 0};
+    std::vector<Item> items_lpt;       // all items, largest estimated cost first
 
     // top level under the all-pairs rule
     std::vector<int32_t> top_src;      // per tree, its level-0 sub ids (concatenated)
@@ -58,6 +67,10 @@ struct HostPlan {
 // / -2 (malformed tree) with a message in *err.
 int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chunks,
                     HostPlan* out, std::string* err);
+
+// (Re)builds the work-item lists with ngroups (1..MAX_GROUPS) plane groups
+// per refined-target plane item.
+void build_items(HostPlan* P, int ngroups);
 
 // Fills the canonical stencil tables.
 void build_stencil_tables(StencilTables* t);

@@ -68,12 +68,18 @@ def test_c0_forest_all_pairs_fp64():
     assert st["pairs_top"] == 13824 * 13823
 
 
+SHAPES = {"per_class_g1": dict(plane_groups=1), "per_class_g2": dict(plane_groups=2),
+          "persistent_g2": dict(persistent=True, plane_groups=2),
+          "persistent_g1_bpc1": dict(persistent=True, plane_groups=1, blocks_per_cu=1)}
+
+
+@pytest.mark.parametrize("shape", list(SHAPES))
 @pytest.mark.parametrize("seed", [1, 2, 3, 5])
-def test_random_amr_fp64(seed):
+def test_random_amr_fp64(seed, shape):
     """All four classes, coarse-fine boundaries, absent neighbours."""
     W = wl.small_amr(seed)
     t = W.trees[0]
-    phi, g, st = run([t], W.rho)
+    phi, g, st = run([t], W.rho, **SHAPES[shape])
     pr, gr, ost = oracle.solve(t, W.rho, with_stats=True)
     errs = field_errors(phi, g, pr, gr)
     print("  errors", errs, flush=True)
@@ -83,12 +89,27 @@ def test_random_amr_fp64(seed):
     assert f < 1e-13 and tq < 1e-13
 
 
-def test_random_amr_deeper_fp64():
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
+def test_random_amr_deeper_fp64(shape):
     W = wl.small_amr(11, max_level=3, p_refine=0.3)
     t = W.trees[0]
-    phi, g, _ = run([t], W.rho)
+    phi, g, _ = run([t], W.rho, **SHAPES[shape])
     pr, gr = oracle.solve(t, W.rho)
     assert max(field_errors(phi, g, pr, gr)) < TOL64
+
+
+@pytest.mark.parametrize("shape", ["per_class_g1", "persistent_g2"])
+def test_stencil_mode_refined_top_level(shape):
+    """A refined level-0 forest under the stencil-only top rule (its totals
+    are its own terms) with random densities."""
+    subs = [(0, x, y, z) for x in range(2) for y in range(2) for z in range(2)]
+    subs += [(1, 2 * 0 + a, b, c) for a in (0, 1) for b in (0, 1) for c in (0, 1)]
+    t = wl._desc_from_list(subs, (0, 0, 0), 1.0)
+    rho = np.random.default_rng(4).lognormal(0, 1, (t.n_leaves, 8, 8, 8))
+    phi, g, st = run([t], rho, top_mode="stencil", **SHAPES[shape])
+    pr, gr, ost = oracle.solve(t, rho, top_all_pairs=False, with_stats=True)
+    assert max(field_errors(phi, g, pr, gr)) < TOL64
+    assert st["pairs"] == ost["cls"]
 
 
 def test_correction_off_matches_uncorrected_oracle():
@@ -123,12 +144,13 @@ def test_single_leaf_and_single_refined_root():
     assert max(field_errors(phi, g, pr, gr)) < TOL64
 
 
-def test_c1_full_size_fp64_graph():
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
+def test_c1_full_size_fp64_graph(shape):
     """Uniform level-3 polytrope (64^3 leaf cells), in the launch
-    configuration that the benchmark times (captured graph)."""
+    configurations the benchmark may time (captured graph)."""
     W = wl.c1()
     t = W.trees[0]
-    phi, g, st = run([t], W.rho, use_graph=True)
+    phi, g, st = run([t], W.rho, use_graph=True, **SHAPES[shape])
     pr, gr = oracle.solve(t, W.rho)
     errs = field_errors(phi, g, pr, gr)
     print("  c1 errors", errs, flush=True)
@@ -136,11 +158,12 @@ def test_c1_full_size_fp64_graph():
     assert st["pairs"] == [0, 1705080 + 17246904, 176804352, 0] and st["pairs_top"] == 230616
 
 
-def test_c2_full_size_fp64_sampled():
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
+def test_c2_full_size_fp64_sampled(shape):
     """Binary-star AMR field (3,816 leaves), sampled against the oracle."""
     W = wl.c2()
     t = W.trees[0]
-    phi, g, st = run([t], W.rho, use_graph=True)
+    phi, g, st = run([t], W.rho, use_graph=True, **SHAPES[shape])
     rng = np.random.default_rng(0)
     li = rng.integers(0, t.n_leaves, 1500).astype(np.int32)
     ci = rng.integers(0, 512, 1500).astype(np.int32)
@@ -159,11 +182,12 @@ def test_c2_full_size_fp64_sampled():
     assert f < 1e-12 and tq < 1e-12
 
 
-def test_batched_trees_equal_each_tree_alone():
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
+def test_batched_trees_equal_each_tree_alone(shape):
     Ws = [wl.small_amr(s) for s in (1, 2, 3)] + [wl.c1(max_level=2)]
     trees = [W.trees[0] for W in Ws]
     rho = np.concatenate([W.rho for W in Ws])
-    phi, g, st = run(trees, rho, use_graph=True)
+    phi, g, st = run(trees, rho, use_graph=True, **SHAPES[shape])
     off = 0
     for W in Ws:
         n = W.n_leaves
@@ -173,17 +197,18 @@ def test_batched_trees_equal_each_tree_alone():
     assert st["n_trees"] == 4
 
 
-def test_graph_replays_match_eager():
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
+def test_graph_replays_match_eager(shape):
     W = wl.small_amr(5)
     t = W.trees[0]
     r = torch.tensor(W.rho, dtype=torch.float64, device=DEV)
-    with fm.Plan([t]) as pe:
+    with fm.Plan([t], **SHAPES[shape]) as pe:
         pe_phi, pe_g = pe.solve(r)
     torch.cuda.synchronize()
     ref_phi, ref_g = pe_phi.clone(), pe_g.clone()
     phi = torch.empty_like(ref_phi)
     g = torch.empty_like(ref_g)
-    with fm.Plan([t], use_graph=True) as pg:
+    with fm.Plan([t], use_graph=True, **SHAPES[shape]) as pg:
         for rep in range(4):
             phi.fill_(float("nan"))
             g.fill_(float("nan"))
@@ -195,10 +220,13 @@ def test_graph_replays_match_eager():
         assert pg.stats()["solves"] == 4
 
 
-def test_repeat_solves_are_bitwise_deterministic():
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
+def test_repeat_solves_are_bitwise_deterministic(shape):
+    """Every output is written by one work item in a fixed order, so even the
+    dynamically scheduled persistent launch is bitwise reproducible."""
     W = wl.small_amr(2)
     r = torch.tensor(W.rho, dtype=torch.float64, device=DEV)
-    with fm.Plan([W.trees[0]]) as p:
+    with fm.Plan([W.trees[0]], **SHAPES[shape]) as p:
         a = [t.clone() for t in p.solve(r)]
         b = p.solve(r)
         torch.cuda.synchronize()
@@ -208,10 +236,11 @@ def test_repeat_solves_are_bitwise_deterministic():
 # ---------------------------------------------------------------------------
 # mixed precision
 # ---------------------------------------------------------------------------
-def test_mixed_c1_error_bounds():
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
+def test_mixed_c1_error_bounds(shape):
     W = wl.c1()
     t = W.trees[0]
-    phi, g, _ = run([t], W.rho, precision="mixed", use_graph=True)
+    phi, g, _ = run([t], W.rho, precision="mixed", use_graph=True, **SHAPES[shape])
     pr, gr = oracle.solve(t, W.rho)
     errs = field_errors(phi, g, pr, gr)
     f, tq = residuals(t, W.rho, g)
@@ -220,10 +249,11 @@ def test_mixed_c1_error_bounds():
     assert f < 1e-6
 
 
-def test_mixed_amr_error_bounds():
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
+def test_mixed_amr_error_bounds(shape):
     W = wl.small_amr(3)
     t = W.trees[0]
-    phi, g, _ = run([t], W.rho, precision="mixed")
+    phi, g, _ = run([t], W.rho, precision="mixed", **SHAPES[shape])
     pr, gr = oracle.solve(t, W.rho)
     errs = field_errors(phi, g, pr, gr)
     f, tq = residuals(t, W.rho, g)
@@ -252,3 +282,46 @@ def test_density_check_and_argument_errors():
             p.solve(r[:-1].contiguous())
         with pytest.raises(ValueError):
             p.solve(r.float())
+
+
+def test_autotune_picks_a_shape_and_caches_it(tmp_path):
+    W = wl.small_amr(1)
+    t = W.trees[0]
+    cache = str(tmp_path / "tune.json")
+    r = torch.tensor(W.rho, dtype=torch.float64, device=DEV)
+    pr, gr = oracle.solve(t, W.rho)
+    with fm.Plan([t], autotune=True, tuning_cache=cache, use_graph=True) as p:
+        phi, g = p.solve(r)
+        torch.cuda.synchronize()
+        sh = p.launch_shape()
+    assert sh["from_cache"] == 0 and sh["tuned_ms"] > 0
+    assert max(field_errors(phi.cpu().numpy(), g.cpu().numpy(), pr, gr)) < TOL64
+    import json
+    with open(cache) as f:
+        tab = json.load(f)
+    assert len(tab) == 1
+    with fm.Plan([t], autotune=True, tuning_cache=cache) as p2:
+        phi2, g2 = p2.solve(r)
+        torch.cuda.synchronize()
+        sh2 = p2.launch_shape()
+    assert sh2["from_cache"] == 1
+    for k in ("persistent", "plane_groups", "blocks_per_cu"):
+        assert sh2[k] == sh[k]
+    assert max(field_errors(phi2.cpu().numpy(), g2.cpu().numpy(), pr, gr)) < TOL64
+
+
+def test_stage_timing_counts_launches():
+    W = wl.small_amr(2)
+    r = torch.tensor(W.rho, dtype=torch.float64, device=DEV)
+    for pers in (False, True):
+        with fm.Plan([W.trees[0]], timing=True, persistent=pers) as p:
+            for _ in range(3):
+                p.solve(r)
+            torch.cuda.synchronize()
+            tm = p.timings()
+        assert tm["solves"] == 3
+        assert all(v >= 0 for v in tm["ms"].values())
+        if pers:
+            assert tm["launches"]["fused"] >= 2 and tm["launches"]["mp_refined"] == 0
+        else:
+            assert tm["launches"]["mp_refined"] == 1 and tm["launches"]["fused"] == 0
