@@ -67,6 +67,9 @@ def lib():
         L.oracle_same_level_subset.restype = C.c_int64
         L.oracle_direct_sum.argtypes = tree + [_f64p, C.c_double, _f64p, _f64p]
         L.oracle_direct_sum.restype = C.c_int
+        L.oracle_direct_sum_sampled.argtypes = tree + [_f64p, C.c_double, C.c_int, _i32p, _i32p,
+                                                       _f64p, _f64p]
+        L.oracle_direct_sum_sampled.restype = C.c_int
         L.oracle_pair_coverage.argtypes = [C.c_int, _i32p, _i32p, C.c_int, _u8p]
         L.oracle_pair_coverage.restype = C.c_int
         _lib = L
@@ -181,6 +184,19 @@ def direct_sum(tree, rho, G=1.0):
                                  float(G), phi, g)
     _check(rc, "oracle_direct_sum")
     return phi.reshape(nl, 512), g.reshape(nl, 3, 512)
+
+
+def direct_sum_sampled(tree, rho, leaf_idx, cell_idx, G=1.0):
+    """Newton's sum over every leaf cell, at the sampled cells only."""
+    leaf_idx = np.ascontiguousarray(leaf_idx, dtype=np.int32)
+    cell_idx = np.ascontiguousarray(cell_idx, dtype=np.int32)
+    ns = leaf_idx.shape[0]
+    phi = np.zeros(ns)
+    g = np.zeros(ns * 3)
+    rc = lib().oracle_direct_sum_sampled(*_tree_args(tree), np.ascontiguousarray(rho, np.float64),
+                                         float(G), ns, leaf_idx, cell_idx, phi, g)
+    _check(rc, "oracle_direct_sum_sampled")
+    return phi, g.reshape(ns, 3)
 
 
 def pair_coverage(tree, top_all_pairs=True):

@@ -700,6 +700,48 @@ int64_t oracle_same_level_subset(int n, const int32_t* level, const int32_t* coo
 /* ------------------------------------------------------------------------ */
 /* phi_a = -G sum_{b != a} m_b / |x_a - x_b|,
  * g_a   = -G sum_{b != a} m_b (x_a - x_b) / |x_a - x_b|^3,  leaf cells as point masses. */
+
+/* leaf cells as point masses: centres x[3N] and masses m[N], N = 512 * leaves,
+ * in leaf order and the caller's cell order */
+static int point_masses(const tree_t* t, const double* rho, double** xo, double** mo) {
+    size_t N = (size_t)t->nleaf * NCELL;
+    double* x = (double*)malloc(sizeof(double) * 3 * N);
+    double* m = (double*)malloc(sizeof(double) * N);
+    if (!x || !m) { free(x); free(m); return -3; }
+    for (int li = 0; li < t->nleaf; ++li) {
+        int s = t->leaves[li];
+        int l = t->level[s];
+        double h = cell_size(t, l);
+        for (int q = 0; q < NCELL; ++q) {
+            int c[3];
+            cell_coords(t, s, q, c);
+            size_t i = (size_t)li * NCELL + q;
+            cell_centre(t, l, c, &x[3 * i]);
+            m[i] = rho[i] * h * h * h;
+        }
+    }
+    *xo = x;
+    *mo = m;
+    return 0;
+}
+
+/* Newton's sum at point a over every other point */
+static void newton_at(size_t N, const double* x, const double* m, size_t a, double G,
+                      double* phi, double g[3]) {
+    double p = 0.0, ga[3] = {0, 0, 0};
+    for (size_t b = 0; b < N; ++b) {
+        if (b == a) continue;
+        double R[3] = {x[3 * a] - x[3 * b], x[3 * a + 1] - x[3 * b + 1], x[3 * a + 2] - x[3 * b + 2]};
+        double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
+        double r = sqrt(r2);
+        p += m[b] / r;
+        double w = m[b] / (r2 * r);
+        for (int k = 0; k < 3; ++k) ga[k] += w * R[k];
+    }
+    *phi = -G * p;
+    for (int k = 0; k < 3; ++k) g[k] = -G * ga[k];
+}
+
 int oracle_direct_sum(int n, const int32_t* level, const int32_t* coord, const double origin[3],
                       double L0, const double* rho, double G, double* phi, double* g) {
     tree_t t;
@@ -707,36 +749,45 @@ int oracle_direct_sum(int n, const int32_t* level, const int32_t* coord, const d
     if (rc) return rc;
     if (check_rho(&t, rho) || !phi || !g) { tree_free(&t); return -1; }
     size_t N = (size_t)t.nleaf * NCELL;
-    double* x = (double*)malloc(sizeof(double) * 3 * N);
-    double* m = (double*)malloc(sizeof(double) * N);
-    if (!x || !m) { free(x); free(m); tree_free(&t); return -3; }
-    for (int li = 0; li < t.nleaf; ++li) {
-        int s = t.leaves[li];
-        int l = t.level[s];
-        double h = cell_size(&t, l);
-        for (int q = 0; q < NCELL; ++q) {
-            int c[3];
-            cell_coords(&t, s, q, c);
-            size_t i = (size_t)li * NCELL + q;
-            cell_centre(&t, l, c, &x[3 * i]);
-            m[i] = rho[i] * h * h * h;
-        }
-    }
+    double *x, *m;
+    if (point_masses(&t, rho, &x, &m)) { tree_free(&t); return -3; }
     #pragma omp parallel for schedule(dynamic, 64)
     for (long long a = 0; a < (long long)N; ++a) {
-        double p = 0.0, ga[3] = {0, 0, 0};
-        for (size_t b = 0; b < N; ++b) {
-            if ((long long)b == a) continue;
-            double R[3] = {x[3 * a] - x[3 * b], x[3 * a + 1] - x[3 * b + 1], x[3 * a + 2] - x[3 * b + 2]};
-            double r2 = R[0] * R[0] + R[1] * R[1] + R[2] * R[2];
-            double r = sqrt(r2);
-            p += m[b] / r;
-            double w = m[b] / (r2 * r);
-            for (int k = 0; k < 3; ++k) ga[k] += w * R[k];
-        }
+        double ga[3];
         size_t li = (size_t)a / NCELL, q = (size_t)a % NCELL;
-        phi[a] = -G * p;
-        for (int k = 0; k < 3; ++k) g[(li * 3 + k) * NCELL + q] = -G * ga[k];
+        newton_at(N, x, m, (size_t)a, G, &phi[a], ga);
+        for (int k = 0; k < 3; ++k) g[(li * 3 + k) * NCELL + q] = ga[k];
+    }
+    free(x);
+    free(m);
+    tree_free(&t);
+    return 0;
+}
+
+int oracle_direct_sum_sampled(int n, const int32_t* level, const int32_t* coord,
+                              const double origin[3], double L0, const double* rho, double G,
+                              int n_sample, const int32_t* sample_leaf,
+                              const int32_t* sample_cell, double* phi, double* g) {
+    tree_t t;
+    int rc = tree_build(&t, n, level, coord, origin, L0);
+    if (rc) return rc;
+    if (check_rho(&t, rho) || n_sample < 0 || (n_sample > 0 && (!sample_leaf || !sample_cell || !phi || !g))) {
+        tree_free(&t);
+        return -1;
+    }
+    for (int i = 0; i < n_sample; ++i) {
+        if (sample_leaf[i] < 0 || sample_leaf[i] >= t.nleaf || sample_cell[i] < 0 || sample_cell[i] >= NCELL) {
+            tree_free(&t);
+            return -1;
+        }
+    }
+    size_t N = (size_t)t.nleaf * NCELL;
+    double *x, *m;
+    if (point_masses(&t, rho, &x, &m)) { tree_free(&t); return -3; }
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < n_sample; ++i) {
+        size_t a = (size_t)sample_leaf[i] * NCELL + (size_t)sample_cell[i];
+        newton_at(N, x, m, a, G, &phi[i], &g[3 * (size_t)i]);
     }
     free(x);
     free(m);

@@ -92,6 +92,13 @@ int64_t oracle_same_level_subset(int n, const int32_t* level, const int32_t* coo
 int oracle_direct_sum(int n, const int32_t* level, const int32_t* coord, const double origin[3],
                       double L0, const double* rho, double G, double* phi, double* g);
 
+/* The same plain sum at sampled leaf cells only: phi[i], g[3 i .. 3 i + 2] for
+ * leaf sample_leaf[i] (leaf order), cell sample_cell[i] (caller's cell order). */
+int oracle_direct_sum_sampled(int n, const int32_t* level, const int32_t* coord,
+                              const double origin[3], double L0, const double* rho, double G,
+                              int n_sample, const int32_t* sample_leaf,
+                              const int32_t* sample_cell, double* phi, double* g);
+
 /* Exact-once check: cover[a * nleafcells + b] counts how many evaluated pairs
  * (A, B) have leaf cell a below (or equal to) A and b below (or equal to) B.
  * nleafcells = 512 * number of leaves.  uint8 saturates at 255. */
