@@ -30,7 +30,7 @@ PEAK_FP32 = 157.3e12     # MI355X FP32 vector (packed), FLOP/s
 PEAK_HBM = 8.0e12        # bytes/s
 
 # Arithmetic of one ordered pair in the kernels' formulation (FMA = 2 flop):
-FLOP_PAIR_REFINED = 229  # refined target: L0..L3 (order 3) + correction
+FLOP_PAIR_REFINED = 213  # refined target: L0..L3 (order 3) + correction
 FLOP_PAIR_LEAF_MP = 144  # leaf target, multipole source: L0, L1 + correction
 FLOP_PAIR_MONO = 6       # leaf <- leaf monopole, lattice kernel tables: 3 FMA
 
@@ -152,6 +152,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--forms", default="all", choices=["all", "c1"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for hardware counters: 3 eager c1 FP64 solves in the launch "
+                         "shape --shape, then a 256 MiB device-to-device copy whose byte "
+                         "counters calibrate the ones of the solve kernels")
+    ap.add_argument("--shape", default="per_class_g2",
+                    choices=["per_class_g1", "per_class_g2", "persistent_g1", "persistent_g2"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
@@ -168,6 +174,27 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     fm.lib()
     K, W = args.steps, args.warmup
+
+    if args.profile:
+        c1 = wl.c1()
+        dev = torch.device("cuda:0")
+        rho = torch.tensor(c1.rho, dtype=torch.float64, device=dev)
+        pers, groups = args.shape.split("_g")
+        with fm.Plan(c1.trees, persistent=pers == "persistent", plane_groups=int(groups)) as plan:
+            phi, g = plan.solve(rho)
+            for _ in range(2):
+                plan.solve(rho, phi, g)
+            torch.cuda.synchronize()
+            st = plan.stats()
+        n = 256 * 2 ** 20 // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": "c1_fp64", "shape": args.shape, "solves": 3, "pairs": st["pairs"],
+                          "pairs_top": st["pairs_top"], "copy_bytes_each_way": n * 8}), flush=True)
+        return
 
     log("generating c1 (uniform level-3 octree, 64^3 leaf cells)")
     c1 = wl.c1()

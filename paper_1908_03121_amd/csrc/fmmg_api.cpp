@@ -79,7 +79,7 @@ std::vector<TreeIn> to_trees(const fmmg_tree_desc* trees, int32_t n_trees) {
     return v;
 }
 
-constexpr int TOP_CHUNKS = 32;
+constexpr int TOP_CHUNKS = MAX_TOP_PARTS;
 
 }  // namespace
 
@@ -94,7 +94,6 @@ struct fmmg_plan {
     int32_t* d_leaf_sub = nullptr;
     int32_t* d_ref_by_level = nullptr;
     int32_t* d_top_leaf = nullptr;
-    int32_t* d_top_ref_stencil = nullptr;
     int32_t* d_top_src = nullptr;
     TopItem* d_top_items = nullptr;
     TopReduce* d_top_reduce = nullptr;
@@ -140,7 +139,7 @@ void drop_graph(fmmg_plan* p) {
 void release(fmmg_plan* p) {
     if (!p) return;
     drop_graph(p);
-    void* bufs[] = {p->d_subs, p->d_leaf_sub, p->d_ref_by_level, p->d_top_leaf, p->d_top_ref_stencil,
+    void* bufs[] = {p->d_subs, p->d_leaf_sub, p->d_ref_by_level, p->d_top_leaf,
                     p->d_top_src, p->d_top_items, p->d_top_reduce, p->d_items_class, p->d_items_lpt,
                     p->d_counter, p->d_mass, p->d_rec, p->d_Lp, p->d_Lr, p->d_Lf, p->d_Lf3, p->d_part,
                     p->d_bad};
@@ -167,6 +166,9 @@ Ctx make_ctx(const fmmg_plan* p, hipStream_t st) {
     a.part = p->d_part;
     a.top_items = p->d_top_items;
     a.top_src = p->d_top_src;
+    a.top_reds = p->d_top_reduce;
+    a.rho = nullptr;
+    a.counter = p->d_counter;
     a.part_stride = int64_t(p->hp.ref_sub.size()) * NLOC * NCELL;
     a.G = p->opt.G;
     a.corr = p->opt.angular_correction ? 1 : 0;
@@ -206,6 +208,7 @@ int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, h
                       const hipEvent_t* ev) {
     const HostPlan& hp = p->hp;
     Ctx a = make_ctx(p, st);
+    a.rho = rho;
     int64_t per[FMMG_N_STAGES] = {0, 0, 0, 0, 0, 0, 0, 0};
     int stage = 0;
     auto mark = [&](int s) {
@@ -213,25 +216,28 @@ int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, h
         if (ev) (void)hipEventRecord(ev[s], st);
     };
     auto cnt = [&](int items, int launches = 1) { if (items > 0) per[stage] += launches; };
-    // step 1: leaf masses, then moments bottom-up
+    // the first kernel of the solve clears the persistent launch's counter
+    bool reset = p->shape.persistent != 0;
+    // step 1: masses of leaves without parents, then moments bottom-up (each
+    // level also stores the masses of its leaf children)
     mark(FMMG_STAGE_P2M);
-    launch_p2m(a, rho, int(hp.leaf_sub.size()));
-    cnt(int(hp.leaf_sub.size()));
+    const int n_tl = int(hp.top_leaf.size());
+    launch_p2m_top(a, p->d_top_leaf, n_tl, reset);
+    if (n_tl > 0) reset = false;
+    cnt(n_tl);
     mark(FMMG_STAGE_M2M);
     for (int l = hp.max_level - 1; l >= 0; --l) {
         int b = hp.level_ref_begin[size_t(l)], e = hp.level_ref_begin[size_t(l) + 1];
-        launch_m2m(a, p->d_ref_by_level + b, e - b);
+        launch_m2m(a, p->d_ref_by_level + b, e - b, reset);
+        if (e > b) reset = false;
         cnt(e - b);
     }
     // step 2: same-level interactions
     const int* cb = hp.class_begin;
-    const int n_top_red = int(hp.top_reduce.size());
     mark(FMMG_STAGE_TOP);
     if (!p->shape.persistent) {
         launch_class(a, IT_TOP, p->d_items_class + cb[IT_TOP], cb[IT_TOP + 1] - cb[IT_TOP]);
         cnt(cb[IT_TOP + 1] - cb[IT_TOP]);
-        launch_top_reduce(a, p->d_top_reduce, n_top_red);
-        cnt(n_top_red, 2);
     }
     mark(FMMG_STAGE_MONO);
     if (!p->shape.persistent) {
@@ -252,21 +258,18 @@ int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, h
     if (p->shape.persistent) {
         const int n = int(hp.items_lpt.size());
         const int grid = p->shape.blocks_per_cu * p->n_cu;
-        launch_persist(a, p->d_items_lpt, n, p->d_counter, grid < n ? grid : n);
-        cnt(n, 2);
-        launch_top_reduce(a, p->d_top_reduce, n_top_red);
-        cnt(n_top_red, 2);
+        launch_persist(a, p->d_items_lpt, n, grid < n ? grid : n);
+        cnt(n);
     }
-    // step 3: totals of stencil-mode top refined cells, leaves without
-    // parents, then top-down re-expansion
+    // step 3: leaves without parents, then top-down re-expansion (the level-0
+    // parents' totals come from their partial sums)
     mark(FMMG_STAGE_DOWN);
-    launch_sum_parts(a, p->d_top_ref_stencil, int(hp.top_ref_stencil.size()));
-    cnt(int(hp.top_ref_stencil.size()));
-    launch_leaf_out(a, p->d_top_leaf, int(hp.top_leaf.size()), phi, g);
-    cnt(int(hp.top_leaf.size()));
+    launch_leaf_out(a, p->d_top_leaf, n_tl, phi, g);
+    cnt(n_tl);
     for (int l = 0; l < hp.max_level; ++l) {
         int b = hp.level_ref_begin[size_t(l)], e = hp.level_ref_begin[size_t(l) + 1];
-        launch_l2l(a, p->d_ref_by_level + b, e - b, phi, g);
+        int mode = l > 0 ? PARENT_TOTAL : (hp.top_full ? PARENT_TOP_PARTS : PARENT_OWN_PARTS);
+        launch_l2l(a, p->d_ref_by_level + b, e - b, mode, phi, g);
         cnt(e - b);
     }
     if (ev) (void)hipEventRecord(ev[FMMG_N_STAGES], st);
@@ -491,7 +494,6 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         UP(p->d_leaf_sub, hp.leaf_sub, 0, "leaf list");
         UP(p->d_ref_by_level, hp.ref_by_level, 0, "level lists");
         UP(p->d_top_leaf, hp.top_leaf, 0, "top leaf list");
-        UP(p->d_top_ref_stencil, hp.top_ref_stencil, 0, "top refined list");
         UP(p->d_top_src, hp.top_src, 0, "top source list");
         UP(p->d_top_items, hp.top_items, 0, "top items");
         UP(p->d_top_reduce, hp.top_reduce, 0, "top reductions");

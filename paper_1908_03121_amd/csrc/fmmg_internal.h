@@ -32,6 +32,10 @@ constexpr int NCELL = 512;     // cells per sub-grid
 constexpr int REACH = 5;       // max |d_i| of the stencil
 constexpr int PW = NS + 2 * REACH;  // 18: edge of the source window around a sub-grid
 constexpr int PCELLS = PW * PW;     // 324 cells in one source z-plane window
+constexpr int PRS = 20;             // LDS row stride (cells) of windows and boxes: with
+                                    // 64 banks the 8 rows of a wave's 8x8 source block
+                                    // fall on disjoint bank sets
+constexpr int PSLOTS = PW * PRS;    // 360 LDS cells per plane window
 constexpr int NREC = 16;       // record components of a refined cell
 constexpr int NLOC = 19;       // Taylor components of a refined cell
 constexpr int NLEAF = 4;       // phi, gx, gy, gz of a leaf cell
@@ -58,6 +62,8 @@ struct SubDev {
     int32_t coord[3];
     int32_t flags;     // bit0: has a leaf neighbour; bit1: has a refined neighbour
     int32_t slot3;     // leaf with refined neighbours: its Lf3 slot, else -1
+    int32_t red;       // top level under the all-pairs rule: its TopReduce index, else -1
+    int32_t pad;
 };
 
 // Same-level work items.  A block of 256 threads (4 waves) runs one item.
@@ -102,7 +108,9 @@ struct TopItem {
     int32_t pad0, pad1;
 };
 
-// Reduction of the partial slots of one top-level target sub-grid.
+// Reduction of the partial slots (at most MAX_TOP_PARTS) of one top-level
+// target sub-grid.
+constexpr int MAX_TOP_PARTS = 8;
 struct TopReduce {
     int32_t target;
     int32_t part_begin;

@@ -37,13 +37,16 @@ __device__ __forceinline__ int io_index(int q) {
     return (x * 8 + y) * 8 + z;
 }
 
-// Accumulators of one target cell.  Refined targets carry all 19 components;
-// leaf targets only L0, L1 and the correction sum S.
+// Accumulators of one target cell.  Refined targets carry all 19 components
+// (L2 as its trace-free parts xx yy xy xz yz plus the running trace term
+// mb*d1 that both diagonal parts share); leaf targets only L0, L1 and the
+// correction sum S.
 template <typename P>
 struct Acc {
-    P l0, l1[3], l2[5], l3[7], s[3];
+    P l0, l1[3], l2[5], l2t, l3[7], s[3];
     __device__ __forceinline__ void zero() {
         l0 = 0;
+        l2t = 0;
         for (int i = 0; i < 3; ++i) l1[i] = 0, s[i] = 0;
         for (int i = 0; i < 5; ++i) l2[i] = 0;
         for (int i = 0; i < 7; ++i) l3[i] = 0;
@@ -54,18 +57,34 @@ struct Acc {
         for (int i = 0; i < 3; ++i) l1[i] += P(o.l1[i]), s[i] += P(o.s[i]);
         if (full) {
             for (int i = 0; i < 5; ++i) l2[i] += P(o.l2[i]);
+            l2t += P(o.l2t);
             for (int i = 0; i < 7; ++i) l3[i] += P(o.l3[i]);
         }
     }
+    // the 19 output components (L2 diagonal with its trace term)
+    __device__ __forceinline__ void out(double v[NLOC]) const {
+        v[T_L0] = double(l0);
+        for (int i = 0; i < 3; ++i) v[T_L1 + i] = double(l1[i]);
+        v[T_L2 + 0] = double(l2[0]) + double(l2t);
+        v[T_L2 + 1] = double(l2[1]) + double(l2t);
+        for (int i = 2; i < 5; ++i) v[T_L2 + i] = double(l2[i]);
+        for (int i = 0; i < 7; ++i) v[T_L3 + i] = double(l3[i]);
+        for (int i = 0; i < 3; ++i) v[T_S + i] = double(s[i]);
+    }
 };
 
-// M3:RR for a trace-free rank-3 tensor stored as xxx xxy xxz xyy xyz yyy yyz
+__device__ __forceinline__ double fmaP(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaP(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// o:RR for a trace-free rank-3 tensor o (xxx xxy xxz xyy xyz yyy yyz, with
+// o_xzz = -o_xxx - o_xyy and o_yzz = -o_xxy - o_yyy passed in oxzz, oyzz),
+// written with XmZ = XX - ZZ, YmZ = YY - ZZ and the doubled mixed products.
 template <typename P>
-__device__ __forceinline__ void oct_rr(const P o[7], P XX, P YY, P ZZ, P XY, P XZ, P YZ, P w[3]) {
-    P oxzz = -o[0] - o[3], oyzz = -o[1] - o[5], ozzz = -o[2] - o[6];
-    w[0] = o[0] * XX + o[3] * YY + oxzz * ZZ + P(2) * (o[1] * XY + o[2] * XZ + o[4] * YZ);
-    w[1] = o[1] * XX + o[5] * YY + oyzz * ZZ + P(2) * (o[3] * XY + o[4] * XZ + o[6] * YZ);
-    w[2] = o[2] * XX + o[6] * YY + ozzz * ZZ + P(2) * (o[4] * XY + oxzz * XZ + oyzz * YZ);
+__device__ __forceinline__ void oct_rr(const P o[7], P oxzz, P oyzz, P XmZ, P YmZ, P XY2, P XZ2,
+                                       P YZ2, P w[3]) {
+    w[0] = fmaP(o[0], XmZ, fmaP(o[3], YmZ, fmaP(o[1], XY2, fmaP(o[2], XZ2, o[4] * YZ2))));
+    w[1] = fmaP(o[1], XmZ, fmaP(o[5], YmZ, fmaP(o[3], XY2, fmaP(o[4], XZ2, o[6] * YZ2))));
+    w[2] = fmaP(o[2], XmZ, fmaP(o[6], YmZ, fmaP(o[4], XY2, fmaP(oxzz, XZ2, oyzz * YZ2))));
 }
 
 // One ordered pair: source B (mass mb, trace-free quadrupole q, octupole o)
@@ -79,162 +98,185 @@ __device__ __forceinline__ void oct_rr(const P o[7], P XX, P YY, P ZZ, P XY, P X
 //   q:D2 = d2 RqR,  (q:D3)_i = d3 R_i RqR + 2 d2 (qR)_i,  o:D3 = d3 o:RRR,
 //   (D4:Q)_i = d4 R_i Q:RRR + 3 d3 (Q:RR)_i,
 // where d0 = 1/r, d1 = -1/r^3, d2 = 3/r^5, d3 = -15/r^7, d4 = 105/r^9.
-// FULL: refined target (L2, L3 and its own octupole oa enter).
+// FULL: refined target (L2, L3 and its own octupole oa enter; oa[7], oa[8]
+// hold its dependent components xzz, yzz).
 template <bool FULL, typename P>
 __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], const P o[7],
-                                           P inv_ma, const P oa[7], bool corr, Acc<P>& a) {
-    P r2 = X * X + Y * Y + Z * Z;
-    P d0 = rsqrt_full(r2);
-    P ir2 = d0 * d0;
-    P d1 = -d0 * ir2;
-    P d2 = P(-3) * d1 * ir2;
-    P d3 = P(-5) * d2 * ir2;
-    P XX = X * X, YY = Y * Y, ZZ = Z * Z, XY = X * Y, XZ = X * Z, YZ = Y * Z;
-    P qzz = -q[0] - q[1];
-    P ux = q[0] * X + q[2] * Y + q[3] * Z;
-    P uy = q[2] * X + q[1] * Y + q[4] * Z;
-    P uz = q[3] * X + q[4] * Y + qzz * Z;
-    P RqR = X * ux + Y * uy + Z * uz;
+                                           P inv_ma, const P oa[9], bool corr, Acc<P>& a) {
+    const P XX = X * X, YY = Y * Y, ZZ = Z * Z;
+    const P r2 = XX + YY + ZZ;
+    const P d0 = rsqrt_full(r2);
+    const P ir2 = d0 * d0;
+    const P d1 = -d0 * ir2;
+    const P d2 = P(-3) * ir2 * d1;
+    const P d3 = P(-5) * ir2 * d2;
+    const P XY = X * Y, XZ = X * Z, YZ = Y * Z;
+    const P XmZ = XX - ZZ, YmZ = YY - ZZ, XY2 = XY + XY, XZ2 = XZ + XZ, YZ2 = YZ + YZ;
+    const P qzz = -q[0] - q[1];
+    const P ux = fmaP(q[0], X, fmaP(q[2], Y, q[3] * Z));
+    const P uy = fmaP(q[2], X, fmaP(q[1], Y, q[4] * Z));
+    const P uz = fmaP(q[3], X, fmaP(q[4], Y, qzz * Z));
+    const P RqR = fmaP(X, ux, fmaP(Y, uy, Z * uz));
     P wb[3];
-    oct_rr(o, XX, YY, ZZ, XY, XZ, YZ, wb);
-    P BRRR = X * wb[0] + Y * wb[1] + Z * wb[2];
-    a.l0 += mb * d0 + P(0.5) * d2 * RqR - P(1.0 / 6.0) * d3 * BRRR;
-    P c1 = mb * d1 + P(0.5) * d3 * RqR;
-    a.l1[0] += c1 * X + d2 * ux;
-    a.l1[1] += c1 * Y + d2 * uy;
-    a.l1[2] += c1 * Z + d2 * uz;
+    oct_rr(o, -o[0] - o[3], -o[1] - o[5], XmZ, YmZ, XY2, XZ2, YZ2, wb);
+    const P BRRR = fmaP(X, wb[0], fmaP(Y, wb[1], Z * wb[2]));
+    a.l0 = fmaP(mb, d0, fmaP(P(0.5) * d2, RqR, fmaP(P(-1.0 / 6.0) * d3, BRRR, a.l0)));
+    const P c1 = fmaP(mb, d1, P(0.5) * d3 * RqR);
+    a.l1[0] = fmaP(c1, X, fmaP(d2, ux, a.l1[0]));
+    a.l1[1] = fmaP(c1, Y, fmaP(d2, uy, a.l1[1]));
+    a.l1[2] = fmaP(c1, Z, fmaP(d2, uz, a.l1[2]));
     if (FULL) {
-        P md1 = mb * d1, md2 = mb * d2, md3 = mb * d3;
-        a.l2[0] += md2 * XX + md1;
-        a.l2[1] += md2 * YY + md1;
-        a.l2[2] += md2 * XY;
-        a.l2[3] += md2 * XZ;
-        a.l2[4] += md2 * YZ;
-        P tx = md3 * XX, ty = md3 * YY;
-        a.l3[0] += X * (tx + P(3) * md2);
-        a.l3[1] += Y * (tx + md2);
-        a.l3[2] += Z * (tx + md2);
-        a.l3[3] += X * (ty + md2);
-        a.l3[4] += md3 * XY * Z;
-        a.l3[5] += Y * (ty + P(3) * md2);
-        a.l3[6] += Z * (ty + md2);
+        const P md2 = mb * d2, md3 = mb * d3;
+        a.l2t = fmaP(mb, d1, a.l2t);
+        a.l2[0] = fmaP(md2, XX, a.l2[0]);
+        a.l2[1] = fmaP(md2, YY, a.l2[1]);
+        a.l2[2] = fmaP(md2, XY, a.l2[2]);
+        a.l2[3] = fmaP(md2, XZ, a.l2[3]);
+        a.l2[4] = fmaP(md2, YZ, a.l2[4]);
+        const P tx = md3 * XX, ty = md3 * YY, m3 = P(3) * md2;
+        const P bx = tx + md2, cy = ty + md2;
+        a.l3[0] = fmaP(X, tx + m3, a.l3[0]);
+        a.l3[1] = fmaP(Y, bx, a.l3[1]);
+        a.l3[2] = fmaP(Z, bx, a.l3[2]);
+        a.l3[3] = fmaP(X, cy, a.l3[3]);
+        a.l3[4] = fmaP(md3 * XY, Z, a.l3[4]);
+        a.l3[5] = fmaP(Y, ty + m3, a.l3[5]);
+        a.l3[6] = fmaP(Z, cy, a.l3[6]);
     }
     if (corr) {
-        P d4 = P(-7) * d3 * ir2;
+        const P d4 = P(-7) * ir2 * d3;
         P Qx = wb[0], Qy = wb[1], Qz = wb[2];
         if (FULL) {
             P wa[3];
-            oct_rr(oa, XX, YY, ZZ, XY, XZ, YZ, wa);
-            P rho = mb * inv_ma;
-            Qx -= rho * wa[0];
-            Qy -= rho * wa[1];
-            Qz -= rho * wa[2];
+            oct_rr(oa, oa[7], oa[8], XmZ, YmZ, XY2, XZ2, YZ2, wa);
+            const P nrho = -(mb * inv_ma);
+            Qx = fmaP(nrho, wa[0], Qx);
+            Qy = fmaP(nrho, wa[1], Qy);
+            Qz = fmaP(nrho, wa[2], Qz);
         }
-        P QRRR = X * Qx + Y * Qy + Z * Qz;
-        P t4 = d4 * QRRR, t3 = P(3) * d3;
-        a.s[0] += t4 * X + t3 * Qx;
-        a.s[1] += t4 * Y + t3 * Qy;
-        a.s[2] += t4 * Z + t3 * Qz;
+        const P QRRR = fmaP(X, Qx, fmaP(Y, Qy, Z * Qz));
+        const P t4 = d4 * QRRR, t3 = P(3) * d3;
+        a.s[0] = fmaP(t4, X, fmaP(t3, Qx, a.s[0]));
+        a.s[1] = fmaP(t4, Y, fmaP(t3, Qy, a.s[1]));
+        a.s[2] = fmaP(t4, Z, fmaP(t3, Qz, a.s[2]));
     }
 }
 
 // ---------------------------------------------------------------------------
-// step 1: leaf P2M and M2M
+// step 1: leaf masses and the upward pass
 // ---------------------------------------------------------------------------
-// m = rho h^3 in the internal cell order.  grid: one block of 512 per leaf.
-__global__ __launch_bounds__(512) void k_p2m(const double* __restrict__ rho,
-                                             const SubDev* __restrict__ subs,
-                                             const int32_t* __restrict__ leaf_sub,
-                                             double* __restrict__ mass) {
-    __shared__ double buf[NCELL];
-    int leaf = blockIdx.x, t = threadIdx.x;
-    double h = subs[leaf_sub[leaf]].h;
-    buf[t] = rho[size_t(leaf) * NCELL + t];
-    __syncthreads();
-    mass[size_t(leaf) * NCELL + t] = buf[io_index(t)] * (h * h * h);
+// Leaves without a parent: m = rho h^3 in the internal cell order.  Thread 0
+// of block 0 also clears the persistent launch's work counter.
+// grid: one block of 512 per listed leaf.
+__global__ __launch_bounds__(512) void k_p2m_top(Ctx cx, const int32_t* __restrict__ list, int reset) {
+    if (reset && blockIdx.x == 0 && threadIdx.x == 0) *cx.counter = 0;
+    const SubDev& S = cx.subs[list[blockIdx.x]];
+    const int q = threadIdx.x;
+    const double h = S.h;
+    cx.mass[size_t(S.idx) * NCELL + q] = cx.rho[size_t(S.idx) * NCELL + io_index(q)] * (h * h * h);
 }
 
-// Moments of the refined cells of one level from their 8 children, in one
-// pass about the parent cell centre c (r0 = child COM - c):
-//   m = sum m_c,  S1 = sum m_c r0,  S2 = sum (q_c + m_c r0 r0),
-//   S3 = sum (o_c + sym(q_c r0) + m_c r0 r0 r0),
-// then moved to the COM offset d = S1/m (binomial shift, M1 = m d):
+// One octant of a refined sub-grid's cells from the 512 cells of one child
+// sub-grid (leaf: point masses m = rho h^3 at the cell centres, also stored
+// for the same-level step; refined: their records).  Each thread takes one
+// child cell and forms its contribution about the parent cell centre c
+// (r0 = child COM - c):  m, m r0, q + m r0 r0, o + sym(q r0) + m r0 r0 r0.
+// The 8 siblings of a parent cell are summed (lane shuffles across x and y
+// parity, LDS across z parity); the sums are then moved to the parent COM
+// offset d = S1/m (binomial shift with M1 = m d):
 //   M2 = S2 - m d d,   M3 = S3 - sym(S2 d) + 2 m d d d,
 // and stored trace-free (children's trace parts only feed trace parts).
-// grid: one block of 512 (parent cells) per refined sub-grid of the level.
-__global__ __launch_bounds__(512) void k_m2m(const SubDev* __restrict__ subs,
-                                             const int32_t* __restrict__ list,
-                                             const double* __restrict__ mass,
-                                             double* __restrict__ rec) {
-    const SubDev& Ps = subs[list[blockIdx.x]];
+// grid: (refined sub-grids of the level) x 8 octants, 512 threads.
+__global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__ list, int reset) {
+    __shared__ double red[4][16][20];
+    __shared__ double rin[NCELL + NCELL / 8];  // leaf densities, I/O order, one pad per z-row
+    if (reset && blockIdx.x == 0 && threadIdx.x == 0) *cx.counter = 0;
+    const SubDev& Ps = cx.subs[list[blockIdx.x >> 3]];
+    const int e = blockIdx.x & 7;
+    const SubDev& Cs = cx.subs[Ps.child[e]];
     const int q = threadIdx.x;
-    const int x = q & 7, y = (q >> 3) & 7, z = q >> 6;
-    const int oct = ((x >> 2) << 2) | ((y >> 2) << 1) | (z >> 2);
-    const SubDev& Cs = subs[Ps.child[oct]];
-    const bool cref = Cs.kind == 1;
-    const double hc = Cs.h;
-    const double* crec = rec + size_t(Cs.idx) * NREC * NCELL;
-    const double* cmass = mass + size_t(Cs.idx) * NCELL;
-    double m = 0, s1x = 0, s1y = 0, s1z = 0;
-    // S2: xx yy zz xy xz yz;  S3: xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz
-    double p2[6] = {0, 0, 0, 0, 0, 0};
-    double p3[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll 2
-    for (int e = 0; e < 8; ++e) {
-        const int ex = e >> 2, ey = (e >> 1) & 1, ez = e & 1;
-        const int cq = (((2 * z + ez) & 7) * 8 + ((2 * y + ey) & 7)) * 8 + ((2 * x + ex) & 7);
-        double w, dx = 0, dy = 0, dz = 0;
-        double qxx = 0, qyy = 0, qxy = 0, qxz = 0, qyz = 0;
-        double o0 = 0, o1 = 0, o2 = 0, o3 = 0, o4 = 0, o5 = 0, o6 = 0;
-        if (cref) {
-            w = crec[R_M * NCELL + cq];
-            dx = crec[R_DX * NCELL + cq];
-            dy = crec[R_DY * NCELL + cq];
-            dz = crec[R_DZ * NCELL + cq];
-            qxx = crec[(R_Q + 0) * NCELL + cq];
-            qyy = crec[(R_Q + 1) * NCELL + cq];
-            qxy = crec[(R_Q + 2) * NCELL + cq];
-            qxz = crec[(R_Q + 3) * NCELL + cq];
-            qyz = crec[(R_Q + 4) * NCELL + cq];
-            o0 = crec[(R_O + 0) * NCELL + cq];
-            o1 = crec[(R_O + 1) * NCELL + cq];
-            o2 = crec[(R_O + 2) * NCELL + cq];
-            o3 = crec[(R_O + 3) * NCELL + cq];
-            o4 = crec[(R_O + 4) * NCELL + cq];
-            o5 = crec[(R_O + 5) * NCELL + cq];
-            o6 = crec[(R_O + 6) * NCELL + cq];
-        } else {
-            w = cmass[cq];
-        }
-        const double rx = (ex - 0.5) * hc + dx, ry = (ey - 0.5) * hc + dy, rz = (ez - 0.5) * hc + dz;
-        const double qzz = -qxx - qyy;
-        m += w;
-        s1x += w * rx;
-        s1y += w * ry;
-        s1z += w * rz;
-        p2[0] += qxx + w * rx * rx;
-        p2[1] += qyy + w * ry * ry;
-        p2[2] += qzz + w * rz * rz;
-        p2[3] += qxy + w * rx * ry;
-        p2[4] += qxz + w * rx * rz;
-        p2[5] += qyz + w * ry * rz;
-        p3[0] += o0 + 3 * qxx * rx + w * rx * rx * rx;
-        p3[1] += o1 + qxx * ry + 2 * qxy * rx + w * rx * rx * ry;
-        p3[2] += o2 + qxx * rz + 2 * qxz * rx + w * rx * rx * rz;
-        p3[3] += o3 + 2 * qxy * ry + qyy * rx + w * rx * ry * ry;
-        p3[4] += o4 + qxy * rz + qxz * ry + qyz * rx + w * rx * ry * rz;
-        p3[5] += (-o0 - o3) + 2 * qxz * rz + qzz * rx + w * rx * rz * rz;
-        p3[6] += o5 + 3 * qyy * ry + w * ry * ry * ry;
-        p3[7] += o6 + qyy * rz + 2 * qyz * ry + w * ry * ry * rz;
-        p3[8] += (-o1 - o5) + 2 * qyz * rz + qzz * ry + w * ry * rz * rz;
-        p3[9] += (-o2 - o6) + 3 * qzz * rz + w * rz * rz * rz;
+    if (Cs.kind == 0) {
+        rin[q + (q >> 3)] = cx.rho[size_t(Cs.idx) * NCELL + q];  // coalesced
+        __syncthreads();
     }
+    const int x = q & 7, y = (q >> 3) & 7, z = q >> 6;
+    const double hc = Cs.h;
+    double w, dx = 0, dy = 0, dz = 0;
+    double qxx = 0, qyy = 0, qxy = 0, qxz = 0, qyz = 0;
+    double o0 = 0, o1 = 0, o2 = 0, o3 = 0, o4 = 0, o5 = 0, o6 = 0;
+    if (Cs.kind == 1) {
+        const double* r = cx.rec + size_t(Cs.idx) * NREC * NCELL + q;
+        w = r[R_M * NCELL];
+        dx = r[R_DX * NCELL];
+        dy = r[R_DY * NCELL];
+        dz = r[R_DZ * NCELL];
+        qxx = r[(R_Q + 0) * NCELL];
+        qyy = r[(R_Q + 1) * NCELL];
+        qxy = r[(R_Q + 2) * NCELL];
+        qxz = r[(R_Q + 3) * NCELL];
+        qyz = r[(R_Q + 4) * NCELL];
+        o0 = r[(R_O + 0) * NCELL];
+        o1 = r[(R_O + 1) * NCELL];
+        o2 = r[(R_O + 2) * NCELL];
+        o3 = r[(R_O + 3) * NCELL];
+        o4 = r[(R_O + 4) * NCELL];
+        o5 = r[(R_O + 5) * NCELL];
+        o6 = r[(R_O + 6) * NCELL];
+    } else {
+        const int io = io_index(q);
+        w = rin[io + (io >> 3)] * (hc * hc * hc);
+        cx.mass[size_t(Cs.idx) * NCELL + q] = w;
+    }
+    const double rx = ((x & 1) - 0.5) * hc + dx, ry = ((y & 1) - 0.5) * hc + dy, rz = ((z & 1) - 0.5) * hc + dz;
+    const double qzz = -qxx - qyy;
+    double v[20];
+    v[0] = w;
+    v[1] = w * rx;
+    v[2] = w * ry;
+    v[3] = w * rz;
+    v[4] = qxx + w * rx * rx;
+    v[5] = qyy + w * ry * ry;
+    v[6] = qzz + w * rz * rz;
+    v[7] = qxy + w * rx * ry;
+    v[8] = qxz + w * rx * rz;
+    v[9] = qyz + w * ry * rz;
+    v[10] = o0 + 3 * qxx * rx + w * rx * rx * rx;
+    v[11] = o1 + qxx * ry + 2 * qxy * rx + w * rx * rx * ry;
+    v[12] = o2 + qxx * rz + 2 * qxz * rx + w * rx * rx * rz;
+    v[13] = o3 + 2 * qxy * ry + qyy * rx + w * rx * ry * ry;
+    v[14] = o4 + qxy * rz + qxz * ry + qyz * rx + w * rx * ry * rz;
+    v[15] = (-o0 - o3) + 2 * qxz * rz + qzz * rx + w * rx * rz * rz;
+    v[16] = o5 + 3 * qyy * ry + w * ry * ry * ry;
+    v[17] = o6 + qyy * rz + 2 * qyz * ry + w * ry * ry * rz;
+    v[18] = (-o1 - o5) + 2 * qyz * rz + qzz * ry + w * ry * rz * rz;
+    v[19] = (-o2 - o6) + 3 * qzz * rz + w * rz * rz * rz;
+    // siblings across x parity (lane ^ 1) and y parity (lane ^ 8)
+#pragma unroll
+    for (int k = 0; k < 20; ++k) {
+        v[k] += __shfl_xor(v[k], 1);
+        v[k] += __shfl_xor(v[k], 8);
+    }
+    const bool leader = ((x | y) & 1) == 0;
+    const int pc = (y >> 1) * 4 + (x >> 1);
+    if (leader && (z & 1)) {
+#pragma unroll
+        for (int k = 0; k < 20; ++k) red[z >> 1][pc][k] = v[k];
+    }
+    __syncthreads();
+    if (!leader || (z & 1)) return;
+#pragma unroll
+    for (int k = 0; k < 20; ++k) v[k] += red[z >> 1][pc][k];
+    const double m = v[0];
     double ox = 0, oy = 0, oz = 0;
     if (m > 0) {
         const double im = 1.0 / m;
-        ox = s1x * im; oy = s1y * im; oz = s1z * im;
+        ox = v[1] * im;
+        oy = v[2] * im;
+        oz = v[3] * im;
     }
-    // shift about the COM: M3 = S3 - sym(S2 d) + 2 m d d d (uses S2 before its shift)
+    double* p2 = v + 4;    // xx yy zz xy xz yz
+    double* p3 = v + 10;   // xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz
+    // shift to the COM: M3 = S3 - sym(S2 d) + 2 m d d d (S2 before its shift)
     const double m2 = 2 * m;
     p3[0] += -3 * p2[0] * ox + m2 * ox * ox * ox;
     p3[1] += -(p2[0] * oy + 2 * p2[3] * ox) + m2 * ox * ox * oy;
@@ -256,38 +298,42 @@ __global__ __launch_bounds__(512) void k_m2m(const SubDev* __restrict__ subs,
     const double tx = p3[0] + p3[3] + p3[5];
     const double ty = p3[1] + p3[6] + p3[8];
     const double tz = p3[2] + p3[7] + p3[9];
-    double* out = rec + size_t(Ps.idx) * NREC * NCELL;
-    out[R_M * NCELL + q] = m;
-    out[R_DX * NCELL + q] = ox;
-    out[R_DY * NCELL + q] = oy;
-    out[R_DZ * NCELL + q] = oz;
-    out[(R_Q + 0) * NCELL + q] = p2[0] - tr;
-    out[(R_Q + 1) * NCELL + q] = p2[1] - tr;
-    out[(R_Q + 2) * NCELL + q] = p2[3];
-    out[(R_Q + 3) * NCELL + q] = p2[4];
-    out[(R_Q + 4) * NCELL + q] = p2[5];
-    out[(R_O + 0) * NCELL + q] = p3[0] - 0.6 * tx;
-    out[(R_O + 1) * NCELL + q] = p3[1] - 0.2 * ty;
-    out[(R_O + 2) * NCELL + q] = p3[2] - 0.2 * tz;
-    out[(R_O + 3) * NCELL + q] = p3[3] - 0.2 * tx;
-    out[(R_O + 4) * NCELL + q] = p3[4];
-    out[(R_O + 5) * NCELL + q] = p3[6] - 0.6 * ty;
-    out[(R_O + 6) * NCELL + q] = p3[7] - 0.2 * tz;
+    const int ex = e >> 2, ey = (e >> 1) & 1, ez = e & 1;
+    const int pq = ((4 * ez + (z >> 1)) * NS + (4 * ey + (y >> 1))) * NS + (4 * ex + (x >> 1));
+    double* out = cx.rec + size_t(Ps.idx) * NREC * NCELL + pq;
+    out[R_M * NCELL] = m;
+    out[R_DX * NCELL] = ox;
+    out[R_DY * NCELL] = oy;
+    out[R_DZ * NCELL] = oz;
+    out[(R_Q + 0) * NCELL] = p2[0] - tr;
+    out[(R_Q + 1) * NCELL] = p2[1] - tr;
+    out[(R_Q + 2) * NCELL] = p2[3];
+    out[(R_Q + 3) * NCELL] = p2[4];
+    out[(R_Q + 4) * NCELL] = p2[5];
+    out[(R_O + 0) * NCELL] = p3[0] - 0.6 * tx;
+    out[(R_O + 1) * NCELL] = p3[1] - 0.2 * ty;
+    out[(R_O + 2) * NCELL] = p3[2] - 0.2 * tz;
+    out[(R_O + 3) * NCELL] = p3[3] - 0.2 * tx;
+    out[(R_O + 4) * NCELL] = p3[4];
+    out[(R_O + 5) * NCELL] = p3[6] - 0.6 * ty;
+    out[(R_O + 6) * NCELL] = p3[7] - 0.2 * tz;
 }
 
 // ---------------------------------------------------------------------------
 // step 2: same-level interactions as work items of 256 threads (4 waves)
 // ---------------------------------------------------------------------------
 // LDS of one item block: the largest of the multipole plane window (16
-// records x 324 cells + leaf flags), the monopole mass box (18^3) and the
-// 4-wave reduction buffer (doubles).
+// records x 18 rows of 20 cells + leaf flags), the monopole mass box (18
+// planes x 18 rows of 20 cells) and the 4-wave reduction buffer (doubles).
 template <typename P>
 struct Smem {
-    static constexpr int PLANE = NREC * PCELLS * int(sizeof(P)) + PCELLS;
-    static constexpr int BOX = PW * PW * PW * int(sizeof(P));
+    static constexpr int PLANE = NREC * PSLOTS * int(sizeof(P)) + PSLOTS;
+    static constexpr int BOX = PW * PSLOTS * int(sizeof(P));
     static constexpr int RED = 4 * NLOC * 64 * 8;
+    static constexpr int TOP = NREC * 256 * int(sizeof(P)) + 4 * 256 * 4;  // top-level source tile
     static constexpr int A = PLANE > BOX ? PLANE : BOX;
-    static constexpr int BYTES = ((A > RED ? A : RED) + 15) & ~15;
+    static constexpr int B = RED > TOP ? RED : TOP;
+    static constexpr int BYTES = ((A > B ? A : B) + 15) & ~15;
 };
 
 // Multipole item: 64 target cells (plane zt of sub-grid sid) against the
@@ -300,7 +346,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
                                         unsigned char* smem) {
     using P = typename std::conditional<MIXED, float, double>::type;
     P* sh = reinterpret_cast<P*>(smem);
-    unsigned char* leafflag = smem + NREC * PCELLS * sizeof(P);
+    unsigned char* leafflag = smem + NREC * PSLOTS * sizeof(P);
 
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index: uniform
@@ -313,7 +359,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
 
     // target data
     double mA, dAx = 0, dAy = 0, dAz = 0;
-    P oa[7] = {0, 0, 0, 0, 0, 0, 0};
+    P oa[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (!LEAF_T) {
         const double* r = cx.rec + size_t(tidx) * NREC * NCELL;
         mA = r[R_M * NCELL + q];
@@ -322,6 +368,8 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         dAz = r[R_DZ * NCELL + q];
 #pragma unroll
         for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q]);
+        oa[7] = -oa[0] - oa[3];
+        oa[8] = -oa[1] - oa[5];
     } else {
         mA = cx.mass[size_t(tidx) * NCELL + q];
     }
@@ -335,20 +383,32 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     acc.zero();
     const P hx = P(-h * sx), hy = P(-h * sy);
     // source cell of canonical offset (dx, dy) in the plane window:
-    // c = lbase + sx*dx + (sy*PW)*dy  (mirror signs per lane)
-    const int lbase = (y + REACH) * PW + (x + REACH);
-    const int syw = sy * PW;
+    // c = lbase + sx*dx + (sy*PRS)*dy  (mirror signs per lane)
+    const int lbase = (y + REACH) * PRS + (x + REACH);
+    const int syw = sy * PRS;
 
     for (int gi = i0; gi < i1; ++gi) {
         const int dz = sz * (DZ0 + gi);
         const int zs = zt + dz;
+        const int oz = zs < 0 ? -1 : (zs >= NS ? 1 : 0);
+        // a plane whose 9 neighbour sub-grids hold no usable source is skipped
+        // (uniform over the block)
+        {
+            bool any = false;
+#pragma unroll
+            for (int o = 0; o < 9; ++o) {
+                const int code = T.nbr[(o / 3) * 9 + (o % 3) * 3 + (oz + 1)];
+                any |= LEAF_T ? (code >= 0 && (code & 1)) : (code >= 0);
+            }
+            if (!any) continue;
+        }
         __syncthreads();
         // stage the 18x18 source window of plane zs
         {
-            const int oz = zs < 0 ? -1 : (zs >= NS ? 1 : 0);
             const int lz = zs - NS * oz;
-            for (int c = t; c < PCELLS; c += 256) {
-                const int wx = c % PW, wy = c / PW;
+            for (int cr = t; cr < PCELLS; cr += 256) {
+                const int wx = cr % PW, wy = cr / PW;
+                const int c = wy * PRS + wx;
                 const int lx = wx - REACH, ly = wy - REACH;
                 const int ox = lx < 0 ? -1 : (lx >= NS ? 1 : 0);
                 const int oy = ly < 0 ? -1 : (ly >= NS ? 1 : 0);
@@ -358,12 +418,12 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
                 if (kind == 1) {
                     const double* r = cx.rec + size_t(nidx) * NREC * NCELL + cq;
 #pragma unroll
-                    for (int k = 0; k < NREC; ++k) sh[k * PCELLS + c] = P(r[k * NCELL]);
+                    for (int k = 0; k < NREC; ++k) sh[k * PSLOTS + c] = P(r[k * NCELL]);
                 } else {
                     P mm = (kind == 0 && !LEAF_T) ? P(cx.mass[size_t(nidx) * NCELL + cq]) : P(0);
                     sh[c] = mm;
 #pragma unroll
-                    for (int k = 1; k < NREC; ++k) sh[k * PCELLS + c] = P(0);
+                    for (int k = 1; k < NREC; ++k) sh[k * PSLOTS + c] = P(0);
                 }
                 if (!LEAF_T) leafflag[c] = kind == 0;
             }
@@ -381,7 +441,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
             const int c = lbase + __mul24(sx, dxc) + __mul24(syw, dyc);
             P src[NREC];
 #pragma unroll
-            for (int k = 0; k < NREC; ++k) src[k] = sh[k * PCELLS + c];
+            for (int k = 0; k < NREC; ++k) src[k] = sh[k * PSLOTS + c];
             const P X = hx * P(dxc) + (P(dAx) - src[R_DX]);
             const P Y = hy * P(dyc) + (P(dAy) - src[R_DY]);
             const P Z = zoff + (P(dAz) - src[R_DZ]);
@@ -409,11 +469,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     double* red = reinterpret_cast<double*>(smem);
     {
         double v[NLOC];
-        v[0] = acc.l0;
-        for (int i = 0; i < 3; ++i) v[T_L1 + i] = acc.l1[i];
-        for (int i = 0; i < 5; ++i) v[T_L2 + i] = acc.l2[i];
-        for (int i = 0; i < 7; ++i) v[T_L3 + i] = acc.l3[i];
-        for (int i = 0; i < 3; ++i) v[T_S + i] = acc.s[i];
+        acc.out(v);
 #pragma unroll
         for (int k = 0; k < NLOC; ++k) red[(w * NLOC + k) * 64 + lane] = v[k];
     }
@@ -467,10 +523,10 @@ __device__ __forceinline__ void mono_class(const P* __restrict__ box, int cbeg, 
         const int pk = c_tab.mono_col[c];
         const int dx = (pk & 255) - 8, dy = ((pk >> 8) & 255) - 8;
         const P* col = box + lbase + __mul24(sx, dx) + __mul24(syw, dy)
-                       + (ZMIN + REACH) * (PW * PW);
+                       + (ZMIN + REACH) * PSLOTS;
         P m[NSRC];
 #pragma unroll
-        for (int j = 0; j < NSRC; ++j) m[j] = col[j * (PW * PW)];
+        for (int j = 0; j < NSRC; ++j) m[j] = col[j * PSLOTS];
         const int t0 = tab0 + (c - cbeg) * (3 * N);
         P s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -517,8 +573,9 @@ __device__ __forceinline__ void mono_item(const Ctx& cx, int sid, unsigned char*
     const int t = threadIdx.x;
     const SubDev& T = cx.subs[sid];
     __syncthreads();
-    for (int c = t; c < PW * PW * PW; c += 256) {
-        const int wx = c % PW, wy = (c / PW) % PW, wz = c / (PW * PW);
+    for (int cr = t; cr < PW * PW * PW; cr += 256) {
+        const int wx = cr % PW, wy = (cr / PW) % PW, wz = cr / (PW * PW);
+        const int c = wz * PSLOTS + wy * PRS + wx;
         const int lx = wx - REACH, ly = wy - REACH, lz = wz - REACH;
         const int ox = lx < 0 ? -1 : (lx >= NS ? 1 : 0);
         const int oy = ly < 0 ? -1 : (ly >= NS ? 1 : 0);
@@ -536,8 +593,8 @@ __device__ __forceinline__ void mono_item(const Ctx& cx, int sid, unsigned char*
     const int pz = w & 1, half = w >> 1;
     const int lane = t & 63, x = lane & 7, y = lane >> 3;
     const int sx = 1 - 2 * (x & 1), sy = 1 - 2 * (y & 1);
-    const int lbase = (y + REACH) * PW + (x + REACH);
-    const int syw = sy * PW;
+    const int lbase = (y + REACH) * PRS + (x + REACH);
+    const int syw = sy * PRS;
     double phi[4] = {0, 0, 0, 0}, gx[4] = {0, 0, 0, 0}, gy[4] = {0, 0, 0, 0}, gz[4] = {0, 0, 0, 0};
     if (pz == 0) mono_all<0, P>(box, half, 2, lbase, sx, syw, sy, phi, gx, gy, gz);
     else mono_all<1, P>(box, half, 2, lbase, sx, syw, sy, phi, gx, gy, gz);
@@ -583,7 +640,7 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
     const double h = T.h;
     const int cax = NS * T.coord[0] + x, cay = NS * T.coord[1] + y, caz = NS * T.coord[2] + it.zt;
     double mA, dAx = 0, dAy = 0, dAz = 0;
-    P oa[7] = {0, 0, 0, 0, 0, 0, 0};
+    P oa[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (tref) {
         const double* r = cx.rec + size_t(T.idx) * NREC * NCELL;
         mA = r[R_M * NCELL + q];
@@ -591,6 +648,8 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
         dAy = r[R_DY * NCELL + q];
         dAz = r[R_DZ * NCELL + q];
         for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q]);
+        oa[7] = -oa[0] - oa[3];
+        oa[8] = -oa[1] - oa[5];
     } else {
         mA = cx.mass[size_t(T.idx) * NCELL + q];
     }
@@ -598,40 +657,56 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
     const bool use_corr = cx.corr != 0;
     Acc<P> acc;
     acc.zero();
-    for (int j = it.src_begin + w; j < it.src_end; j += 4) {
-        const SubDev& S = cx.subs[cx.top_src[it.src_list + (j >> 9)]];
-        const int cq = j & 511;
-        const int dx = NS * S.coord[0] + (cq & 7) - cax;
-        const int dy = NS * S.coord[1] + ((cq >> 3) & 7) - cay;
-        const int dz = NS * S.coord[2] + (cq >> 6) - caz;
-        const int d2 = dx * dx + dy * dy + dz * dz;
-        const bool sref = S.kind == 1;
-        if (d2 == 0 || (d2 < 9 && tref && sref)) continue;
-        P src[NREC];
-        if (sref) {
-            const double* r = cx.rec + size_t(S.idx) * NREC * NCELL + cq;
-            for (int k = 0; k < NREC; ++k) src[k] = P(r[k * NCELL]);
-        } else {
-            src[0] = P(cx.mass[size_t(S.idx) * NCELL + cq]);
-            for (int k = 1; k < NREC; ++k) src[k] = P(0);
+    // sources staged through LDS, 256 per tile: 16 record values and the
+    // global integer cell coordinates (w = 1 for a refined sub-grid's cell)
+    P* sv = reinterpret_cast<P*>(smem);
+    int* sc = reinterpret_cast<int*>(smem + NREC * 256 * sizeof(P));
+    for (int tb = it.src_begin; tb < it.src_end; tb += 256) {
+        __syncthreads();
+        const int j = tb + t;
+        if (j < it.src_end) {
+            const SubDev& S = cx.subs[cx.top_src[it.src_list + (j >> 9)]];
+            const int cq = j & 511;
+            sc[0 * 256 + t] = NS * S.coord[0] + (cq & 7);
+            sc[1 * 256 + t] = NS * S.coord[1] + ((cq >> 3) & 7);
+            sc[2 * 256 + t] = NS * S.coord[2] + (cq >> 6);
+            sc[3 * 256 + t] = S.kind;
+            if (S.kind == 1) {
+                const double* r = cx.rec + size_t(S.idx) * NREC * NCELL + cq;
+#pragma unroll
+                for (int k = 0; k < NREC; ++k) sv[k * 256 + t] = P(r[k * NCELL]);
+            } else {
+                sv[t] = P(cx.mass[size_t(S.idx) * NCELL + cq]);
+#pragma unroll
+                for (int k = 1; k < NREC; ++k) sv[k * 256 + t] = P(0);
+            }
         }
-        const P X = P(-h * dx) + (P(dAx) - src[R_DX]);
-        const P Y = P(-h * dy) + (P(dAy) - src[R_DY]);
-        const P Z = P(-h * dz) + (P(dAz) - src[R_DZ]);
-        if (tref)
-            pair_terms<true, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], inv_ma, oa, use_corr, acc);
-        else
-            pair_terms<false, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], inv_ma, oa, use_corr, acc);
+        __syncthreads();
+        const int nt = min(256, it.src_end - tb);
+        for (int s = w; s < nt; s += 4) {
+            const int dx = sc[0 * 256 + s] - cax;
+            const int dy = sc[1 * 256 + s] - cay;
+            const int dz = sc[2 * 256 + s] - caz;
+            const int d2 = dx * dx + dy * dy + dz * dz;
+            const bool sref = sc[3 * 256 + s] == 1;
+            if (d2 == 0 || (d2 < 9 && tref && sref)) continue;
+            P src[NREC];
+#pragma unroll
+            for (int k = 0; k < NREC; ++k) src[k] = sv[k * 256 + s];
+            const P X = P(-h * dx) + (P(dAx) - src[R_DX]);
+            const P Y = P(-h * dy) + (P(dAy) - src[R_DY]);
+            const P Z = P(-h * dz) + (P(dAz) - src[R_DZ]);
+            if (tref)
+                pair_terms<true, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], inv_ma, oa, use_corr, acc);
+            else
+                pair_terms<false, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], inv_ma, oa, use_corr, acc);
+        }
     }
     __syncthreads();
     double* red = reinterpret_cast<double*>(smem);
     {
         double v[NLOC];
-        v[0] = double(acc.l0);
-        for (int i = 0; i < 3; ++i) v[T_L1 + i] = double(acc.l1[i]);
-        for (int i = 0; i < 5; ++i) v[T_L2 + i] = double(acc.l2[i]);
-        for (int i = 0; i < 7; ++i) v[T_L3 + i] = double(acc.l3[i]);
-        for (int i = 0; i < 3; ++i) v[T_S + i] = double(acc.s[i]);
+        acc.out(v);
 #pragma unroll
         for (int k = 0; k < NLOC; ++k) red[(w * NLOC + k) * 64 + lane] = v[k];
     }
@@ -670,8 +745,8 @@ __global__ __launch_bounds__(256) void k_class(Ctx cx, const Item* __restrict__ 
 // of the (largest-first) list from a device counter until the list is
 // exhausted, so every block exits once all items are taken.
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_persist(Ctx cx, const Item* __restrict__ items, int n,
-                                                 int* __restrict__ counter) {
+__global__ __launch_bounds__(256, 3) void k_persist(Ctx cx, const Item* __restrict__ items, int n) {
+    int* __restrict__ counter = cx.counter;
     using P = typename std::conditional<MIXED, float, double>::type;
     __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P>::BYTES];
     __shared__ int s_it;
@@ -685,85 +760,73 @@ __global__ __launch_bounds__(256) void k_persist(Ctx cx, const Item* __restrict_
     }
 }
 
-__global__ void k_reset_counter(int* counter) { *counter = 0; }
-
-// Sum a top-level target's partial slots in a fixed order and scale.
-// grid: (reductions x 19 components), 512 threads (cells).
-__global__ __launch_bounds__(512) void k_top_reduce(Ctx cx, const TopReduce* __restrict__ reds) {
-    const TopReduce R = reds[blockIdx.x / NLOC];
-    const int k = blockIdx.x % NLOC;
-    const SubDev& T = cx.subs[R.target];
-    const int q = threadIdx.x;
-    double v = 0;
-    for (int p = 0; p < R.n_part; ++p) v += cx.part[(size_t(R.part_begin + p) * NLOC + k) * NCELL + q];
-    const double G = cx.G, gs = cx.corr ? -G / 6.0 : 0.0;
-    if (T.kind == 1) {
-        cx.Lr[(size_t(T.idx) * NLOC + k) * NCELL + q] = (k >= T_S ? gs : -G) * v;
-    } else {
-        // leaf target: phi from L0, g = G L1 + gs S, accumulated into Lf
-        double* out = cx.Lf + size_t(T.idx) * NLEAF * NCELL + q;
-        if (k == 0) out[0] = -G * v;
-        else if (k >= T_L1 && k < T_L1 + 3) out[(1 + k - T_L1) * NCELL] = G * v;
-    }
-    (void)gs;
-}
-
-// The correction part of a top-level leaf target (kept apart from the L1
-// part so that each output is written by one block).
-__global__ __launch_bounds__(512) void k_top_reduce_leaf_dg(Ctx cx, const TopReduce* __restrict__ reds) {
-    const TopReduce R = reds[blockIdx.x];
-    const SubDev& T = cx.subs[R.target];
-    if (T.kind == 1 || !cx.corr) return;
-    const int q = threadIdx.x;
-    const double gs = -cx.G / 6.0;
-    double* out = cx.Lf + size_t(T.idx) * NLEAF * NCELL + q;
-    for (int a = 0; a < 3; ++a) {
-        double v = 0;
-        for (int p = 0; p < R.n_part; ++p) v += cx.part[(size_t(R.part_begin + p) * NLOC + T_S + a) * NCELL + q];
-        out[(1 + a) * NCELL] += gs * v;
-    }
-}
-
-// Level-0 refined sub-grids in the stencil-only mode: total = own.
-// grid: (sub-grids x 19 components), 512 threads.
-__global__ __launch_bounds__(512) void k_sum_parts(Ctx cx, const int32_t* __restrict__ list) {
-    const SubDev& T = cx.subs[list[blockIdx.x / NLOC]];
-    const int k = blockIdx.x % NLOC, q = threadIdx.x;
-    double v = 0;
-    for (int g = 0; g < cx.ngroups; ++g)
-        v += cx.Lp[size_t(g) * size_t(cx.part_stride) + (size_t(T.idx) * NLOC + k) * NCELL + q];
-    cx.Lr[(size_t(T.idx) * NLOC + k) * NCELL + q] = v;
-}
-
 // ---------------------------------------------------------------------------
 // step 3: downward pass
 // ---------------------------------------------------------------------------
+// Total expansion of a top-level target under the all-pairs rule: the sum of
+// its partial slots in a fixed order, scaled (-G for L0..L3, -G/6 for S).
+__device__ __forceinline__ double top_total(const Ctx& cx, const SubDev& T, int k, int q) {
+    const TopReduce R = cx.top_reds[T.red];
+    const double* base = cx.part + (size_t(R.part_begin) * NLOC + k) * NCELL + q;
+    double v = 0;
+#pragma unroll
+    for (int p = 0; p < MAX_TOP_PARTS; ++p) {  // all loads issued together
+        const double t = base[size_t(p < R.n_part ? p : R.n_part - 1) * (NLOC * NCELL)];
+        v += p < R.n_part ? t : 0.0;
+    }
+    return (k >= T_S ? (cx.corr ? -cx.G / 6.0 : 0.0) : -cx.G) * v;
+}
+
 // Parent expansion (L0, L1, trace-free L2, L3, correction dg) re-expanded at
 // the child COM, r = X_child - X_parent:
 //   o0 = L0 + L1.r + 1/2 r.L2.r + 1/6 L3:rrr,  o1 = L1 + L2.r + 1/2 L3:rr,
 //   o2 = L2 + L3.r,  o3 = L3,  dg passed unchanged.
+// The parent's total is read from Lr, or formed from the top-level partial
+// slots, or from its own plane-group sums (parent_mode).
 // Refined children: total = own (sum of plane groups) + shifted parent.
 // Leaf children: phi = own + o0,  g = own - o1 + dg.
 // grid: (refined parents at level l) x 8 child sub-grids, 512 threads.
-__global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__ list,
+__global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__ list, int parent_mode,
                                              double* __restrict__ phi, double* __restrict__ gout) {
     __shared__ double obuf[4][NCELL];
+    __shared__ double par[NLOC + 3][64];  // the octant's 64 parent cells: L (19), COM offset (3)
     const SubDev& Ps = cx.subs[list[blockIdx.x >> 3]];
     const int e = blockIdx.x & 7;
     const SubDev& Cs = cx.subs[Ps.child[e]];
     const int q = threadIdx.x;
     const int x = q & 7, y = (q >> 3) & 7, z = q >> 6;
-    const int px = (x >> 1) + 4 * (e >> 2), py = (y >> 1) + 4 * ((e >> 1) & 1), pz = (z >> 1) + 4 * (e & 1);
-    const int pq = (pz * NS + py) * NS + px;
-    const double* L = cx.Lr + size_t(Ps.idx) * NLOC * NCELL + pq;
-    const double* pr = cx.rec + size_t(Ps.idx) * NREC * NCELL + pq;
-    double l0 = L[0];
-    double l1x = L[1 * NCELL], l1y = L[2 * NCELL], l1z = L[3 * NCELL];
-    double qxx = L[4 * NCELL], qyy = L[5 * NCELL], qxy = L[6 * NCELL], qxz = L[7 * NCELL], qyz = L[8 * NCELL];
-    double qzz = -qxx - qyy;
+    const int ex = 4 * (e >> 2), ey = 4 * ((e >> 1) & 1), ez = 4 * (e & 1);
+    // cooperative fetch of the parent octant: value i = comp * 64 + cell
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int i = q + r * NCELL;
+        if (i >= (NLOC + 3) * 64) break;
+        const int k = i >> 6, c = i & 63;
+        const int pq = ((ez + (c >> 4)) * NS + ey + ((c >> 2) & 3)) * NS + ex + (c & 3);
+        double v;
+        if (k >= NLOC) {
+            v = cx.rec[(size_t(Ps.idx) * NREC + R_DX + (k - NLOC)) * NCELL + pq];
+        } else if (parent_mode == PARENT_TOP_PARTS) {
+            v = top_total(cx, Ps, k, pq);
+        } else if (parent_mode == PARENT_OWN_PARTS) {
+            const size_t base = (size_t(Ps.idx) * NLOC + k) * NCELL + pq;
+            v = 0;
+            for (int gg = 0; gg < cx.ngroups; ++gg) v += cx.Lp[size_t(gg) * size_t(cx.part_stride) + base];
+        } else {
+            v = cx.Lr[(size_t(Ps.idx) * NLOC + k) * NCELL + pq];
+        }
+        par[k][c] = v;
+    }
+    __syncthreads();
+    const int pc = ((z >> 1) * 4 + (y >> 1)) * 4 + (x >> 1);
+    double L[NLOC];
+    for (int k = 0; k < NLOC; ++k) L[k] = par[k][pc];
+    const double l0 = L[0], l1x = L[1], l1y = L[2], l1z = L[3];
+    const double qxx = L[4], qyy = L[5], qxy = L[6], qxz = L[7], qyz = L[8];
+    const double qzz = -qxx - qyy;
     double o[7];
-    for (int k = 0; k < 7; ++k) o[k] = L[(T_L3 + k) * NCELL];
-    double sgx = L[16 * NCELL], sgy = L[17 * NCELL], sgz = L[18 * NCELL];
+    for (int k = 0; k < 7; ++k) o[k] = L[T_L3 + k];
+    const double sgx = L[T_S], sgy = L[T_S + 1], sgz = L[T_S + 2];
     const double hc = Cs.h;
     double cdx = 0, cdy = 0, cdz = 0;
     const bool cref = Cs.kind == 1;
@@ -773,11 +836,12 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
         cdy = cr[R_DY * NCELL];
         cdz = cr[R_DZ * NCELL];
     }
-    const double rx = ((x & 1) - 0.5) * hc + cdx - pr[R_DX * NCELL];
-    const double ry = ((y & 1) - 0.5) * hc + cdy - pr[R_DY * NCELL];
-    const double rz = ((z & 1) - 0.5) * hc + cdz - pr[R_DZ * NCELL];
+    const double rx = ((x & 1) - 0.5) * hc + cdx - par[NLOC][pc];
+    const double ry = ((y & 1) - 0.5) * hc + cdy - par[NLOC + 1][pc];
+    const double rz = ((z & 1) - 0.5) * hc + cdz - par[NLOC + 2][pc];
     double w[3];
-    oct_rr<double>(o, rx * rx, ry * ry, rz * rz, rx * ry, rx * rz, ry * rz, w);
+    oct_rr<double>(o, -o[0] - o[3], -o[1] - o[5], rx * rx - rz * rz, ry * ry - rz * rz, 2 * rx * ry,
+                   2 * rx * rz, 2 * ry * rz, w);
     const double l3rrr = rx * w[0] + ry * w[1] + rz * w[2];
     const double vx = qxx * rx + qxy * ry + qxz * rz;
     const double vy = qxy * rx + qyy * ry + qyz * rz;
@@ -800,13 +864,13 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
         sh[7] = qxz + o[2] * rx + o[4] * ry + oxzz * rz;
         sh[8] = qyz + o[4] * rx + o[6] * ry + oyzz * rz;
         for (int k = 0; k < 7; ++k) sh[T_L3 + k] = o[k];
-        sh[16] = sgx;
-        sh[17] = sgy;
-        sh[18] = sgz;
+        sh[T_S] = sgx;
+        sh[T_S + 1] = sgy;
+        sh[T_S + 2] = sgz;
         const size_t base = size_t(Cs.idx) * NLOC * NCELL + q;
         for (int k = 0; k < NLOC; ++k) {
             double own = 0;
-            for (int g = 0; g < cx.ngroups; ++g) own += cx.Lp[size_t(g) * size_t(cx.part_stride) + base + k * NCELL];
+            for (int gg = 0; gg < cx.ngroups; ++gg) own += cx.Lp[size_t(gg) * size_t(cx.part_stride) + base + k * NCELL];
             cx.Lr[base + k * NCELL] = own + sh[k];
         }
     } else {
@@ -835,18 +899,26 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
     }
 }
 
-// Leaves without a parent: output their own terms.  grid: one block per leaf.
+// Leaves without a parent: output their own terms (from the top-level partial
+// slots under the all-pairs rule, else from the stencil kernels).
+// grid: one block per leaf.
 __global__ __launch_bounds__(512) void k_leaf_out(Ctx cx, const int32_t* __restrict__ list,
                                                   double* __restrict__ phi, double* __restrict__ gout) {
     __shared__ double obuf[4][NCELL];
     const SubDev& S = cx.subs[list[blockIdx.x]];
     const int q = threadIdx.x;
-    const double* F = cx.Lf + size_t(S.idx) * NLEAF * NCELL + q;
     const int io = io_index(q);
-    for (int k = 0; k < 4; ++k) {
-        double v = F[k * NCELL];
-        if (S.slot3 >= 0) v += cx.Lf3[size_t(S.slot3) * NLEAF * NCELL + k * NCELL + q];
-        obuf[k][io] = v;
+    if (S.red >= 0) {
+        obuf[0][io] = top_total(cx, S, T_L0, q);
+        for (int a = 0; a < 3; ++a)
+            obuf[1 + a][io] = -top_total(cx, S, T_L1 + a, q) + top_total(cx, S, T_S + a, q);
+    } else {
+        const double* F = cx.Lf + size_t(S.idx) * NLEAF * NCELL + q;
+        for (int k = 0; k < 4; ++k) {
+            double v = F[k * NCELL];
+            if (S.slot3 >= 0) v += cx.Lf3[size_t(S.slot3) * NLEAF * NCELL + k * NCELL + q];
+            obuf[k][io] = v;
+        }
     }
     __syncthreads();
     phi[size_t(S.idx) * NCELL + q] = obuf[0][q];
@@ -873,12 +945,12 @@ hipError_t upload_tables(const StencilTables* t, hipStream_t st) {
                                   hipMemcpyHostToDevice, st);
 }
 
-void launch_p2m(const Ctx& a, const double* rho, int n_leaf) {
-    if (n_leaf > 0) hipLaunchKernelGGL(k_p2m, dim3(n_leaf), dim3(512), 0, a.st, rho, a.subs, a.leaf_sub, a.mass);
+void launch_p2m_top(const Ctx& a, const int32_t* list, int n, bool reset_counter) {
+    if (n > 0) hipLaunchKernelGGL(k_p2m_top, dim3(n), dim3(512), 0, a.st, a, list, reset_counter ? 1 : 0);
 }
 
-void launch_m2m(const Ctx& a, const int32_t* list, int n) {
-    if (n > 0) hipLaunchKernelGGL(k_m2m, dim3(n), dim3(512), 0, a.st, a.subs, list, a.mass, a.rec);
+void launch_m2m(const Ctx& a, const int32_t* list, int n, bool reset_counter) {
+    if (n > 0) hipLaunchKernelGGL(k_m2m, dim3(n * 8), dim3(512), 0, a.st, a, list, reset_counter ? 1 : 0);
 }
 
 template <int K>
@@ -897,11 +969,10 @@ void launch_class(const Ctx& a, int kind, const Item* items, int n) {
     }
 }
 
-void launch_persist(const Ctx& a, const Item* items, int n, int* counter, int grid) {
+void launch_persist(const Ctx& a, const Item* items, int n, int grid) {
     if (n <= 0 || grid <= 0) return;
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, a.st, counter);
-    if (a.mixed) hipLaunchKernelGGL((k_persist<true>), dim3(grid), dim3(256), 0, a.st, a, items, n, counter);
-    else hipLaunchKernelGGL((k_persist<false>), dim3(grid), dim3(256), 0, a.st, a, items, n, counter);
+    if (a.mixed) hipLaunchKernelGGL((k_persist<true>), dim3(grid), dim3(256), 0, a.st, a, items, n);
+    else hipLaunchKernelGGL((k_persist<false>), dim3(grid), dim3(256), 0, a.st, a, items, n);
 }
 
 int persist_blocks_per_cu(int mixed) {
@@ -911,18 +982,8 @@ int persist_blocks_per_cu(int mixed) {
     return e == hipSuccess ? nb : 0;
 }
 
-void launch_top_reduce(const Ctx& a, const TopReduce* reds, int n) {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_top_reduce, dim3(n * NLOC), dim3(512), 0, a.st, a, reds);
-    hipLaunchKernelGGL(k_top_reduce_leaf_dg, dim3(n), dim3(512), 0, a.st, a, reds);
-}
-
-void launch_sum_parts(const Ctx& a, const int32_t* list, int n) {
-    if (n > 0) hipLaunchKernelGGL(k_sum_parts, dim3(n * NLOC), dim3(512), 0, a.st, a, list);
-}
-
-void launch_l2l(const Ctx& a, const int32_t* list, int n, double* phi, double* g) {
-    if (n > 0) hipLaunchKernelGGL(k_l2l, dim3(n * 8), dim3(512), 0, a.st, a, list, phi, g);
+void launch_l2l(const Ctx& a, const int32_t* list, int n, int parent_mode, double* phi, double* g) {
+    if (n > 0) hipLaunchKernelGGL(k_l2l, dim3(n * 8), dim3(512), 0, a.st, a, list, parent_mode, phi, g);
 }
 
 void launch_leaf_out(const Ctx& a, const int32_t* list, int n, double* phi, double* g) {

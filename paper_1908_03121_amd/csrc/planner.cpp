@@ -191,6 +191,7 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
             SubDev& S = P.subs[size_t(base + i)];
             memset(&S, 0, sizeof(S));
             S.slot3 = -1;
+            S.red = -1;
             S.level = l;
             S.tree = t;
             S.coord[0] = x; S.coord[1] = y; S.coord[2] = z;
@@ -279,9 +280,6 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
     }
     for (size_t k = 0; k < P.mp_leaf.size(); ++k) P.subs[size_t(P.mp_leaf[k])].slot3 = int32_t(k);
     P.n_slot3 = int32_t(P.mp_leaf.size());
-    if (!top_full)
-        for (int32_t sidx : P.ref_sub)
-            if (P.subs[size_t(sidx)].level == 0) P.top_ref_stencil.push_back(sidx);
     P.level_ref_begin.assign(size_t(P.max_level) + 2, 0);
     for (int l = 0; l <= P.max_level; ++l) {
         P.level_ref_begin[size_t(l)] = int32_t(P.ref_by_level.size());
@@ -321,6 +319,7 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
                     }
                 }
                 P.n_top_parts += nchunk;
+                P.subs[size_t(T)].red = int32_t(P.top_reduce.size());
                 P.top_reduce.push_back(R);
                 const SubDev& ST = P.subs[size_t(T)];
                 for (int32_t Sb : tops) {

@@ -44,8 +44,6 @@ struct HostPlan {
     std::vector<int32_t> level_ref_begin;  // refined sub ids sorted by level: [l, l+1)
     std::vector<int32_t> ref_by_level;
     std::vector<int32_t> top_leaf;     // top-level leaves (output straight from own terms)
-    std::vector<int32_t> top_ref_stencil;  // level-0 refined sub-grids when the top level
-                                           // uses the stencil (their total = own terms)
     int32_t n_slot3 = 0;               // leaves with refined neighbours (Lf3 slots)
 
     // same-level work items for a given number of plane groups

@@ -249,6 +249,28 @@ def test_mixed_c1_error_bounds(shape):
     assert f < 1e-6
 
 
+def test_mixed_c2_error_is_below_a_tenth_of_the_truncation_error():
+    """Mixed form on the binary-star field: its distance from the FP64 solve is
+    at most a tenth of the FP64 solve's own distance from Newton's sum (at
+    sampled cells), so the precision never dominates the accuracy."""
+    W = wl.c2()
+    t = W.trees[0]
+    p64, g64, _ = run([t], W.rho)
+    pmx, gmx, _ = run([t], W.rho, precision="mixed")
+    rng = np.random.default_rng(7)
+    li = rng.integers(0, t.n_leaves, 400).astype(np.int32)
+    ci = rng.integers(0, 512, 400).astype(np.int32)
+    pd, gd = oracle.direct_sum_sampled(t, W.rho, li, ci)
+    n = np.linalg.norm
+    trunc_phi = n(p64[li, ci] - pd) / n(pd)
+    trunc_g = n(g64[li, :, ci] - gd) / n(gd)
+    mix_phi = n(pmx[li, ci] - p64[li, ci]) / n(pd)
+    mix_g = n(gmx[li, :, ci] - g64[li, :, ci]) / n(gd)
+    print(f"  c2 truncation phi {trunc_phi:.3e} g {trunc_g:.3e}; mixed phi {mix_phi:.3e} g {mix_g:.3e}",
+          flush=True)
+    assert mix_phi <= 0.1 * trunc_phi and mix_g <= 0.1 * trunc_g
+
+
 @pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
 def test_mixed_amr_error_bounds(shape):
     W = wl.small_amr(3)
@@ -322,6 +344,6 @@ def test_stage_timing_counts_launches():
         assert tm["solves"] == 3
         assert all(v >= 0 for v in tm["ms"].values())
         if pers:
-            assert tm["launches"]["fused"] >= 2 and tm["launches"]["mp_refined"] == 0
+            assert tm["launches"]["fused"] >= 1 and tm["launches"]["mp_refined"] == 0
         else:
             assert tm["launches"]["mp_refined"] == 1 and tm["launches"]["fused"] == 0
