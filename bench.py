@@ -128,8 +128,9 @@ def field_err(np, phi, g, pr, gr):
 
 
 def traffic_entry(kernel_name):
-    """HBM bytes per launch from committed rocprofv3 counter runs, valid only
-    while the kernel source is unchanged (source hash recorded with them)."""
+    """HBM bytes per solve of the timed stage's launches, from committed
+    rocprofv3 counter runs; valid only while the kernel source is unchanged
+    (source hash recorded with them)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     src = os.path.join(ROOT, "paper_1908_03121_amd", "csrc", "kernels.hip")
     try:
@@ -139,7 +140,7 @@ def traffic_entry(kernel_name):
             h = hashlib.sha256(f.read()).hexdigest()
         e = tab.get(kernel_name)
         if e and e.get("kernels_hip_sha256") == h:
-            return float(e["bytes_per_launch"])
+            return float(e["bytes_per_solve"])
     except (OSError, ValueError, KeyError):
         pass
     return None
@@ -156,6 +157,8 @@ def main():
                     help="short run for hardware counters: 3 eager c1 FP64 solves in the launch "
                          "shape --shape, then a 256 MiB device-to-device copy whose byte "
                          "counters calibrate the ones of the solve kernels")
+    ap.add_argument("--bpc", type=int, default=0,
+                    help="--profile: blocks per CU of the persistent launch (0 = occupancy limit)")
     ap.add_argument("--shape", default="per_class_g2",
                     choices=["per_class_g1", "per_class_g2", "persistent_g1", "persistent_g2"])
     args = ap.parse_args()
@@ -180,7 +183,8 @@ def main():
         dev = torch.device("cuda:0")
         rho = torch.tensor(c1.rho, dtype=torch.float64, device=dev)
         pers, groups = args.shape.split("_g")
-        with fm.Plan(c1.trees, persistent=pers == "persistent", plane_groups=int(groups)) as plan:
+        with fm.Plan(c1.trees, persistent=pers == "persistent", plane_groups=int(groups),
+                     blocks_per_cu=args.bpc) as plan:
             phi, g = plan.solve(rho)
             for _ in range(2):
                 plan.solve(rho, phi, g)
@@ -192,7 +196,8 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"profile": "c1_fp64", "shape": args.shape, "solves": 3, "pairs": st["pairs"],
+        print(json.dumps({"profile": "c1_fp64", "shape": args.shape, "bpc": args.bpc, "solves": 3,
+                          "pairs": st["pairs"],
                           "pairs_top": st["pairs_top"], "copy_bytes_each_way": n * 8}), flush=True)
         return
 
@@ -206,23 +211,26 @@ def main():
     stages, launches, eager_ms, st_e = stage_times(fm, torch, c1.trees, c1.rho, "fp64", K, W, shape)
     log(f"  stages {stages}")
     p = st_e["pairs"]
+    # the same-level step runs as one launch per branch (fine levels, and the
+    # coarse levels when the tree splits); the timed stage spans both
     if shape["persistent"]:
-        # one persistent launch evaluates every same-level class
-        kname = "k_persist<fp64> (all same-level classes, one launch)"
+        kname = (f"k_persist<fp64> (every same-level class; {launches['fused']} launch(es) per solve: "
+                 "fine and coarse branch)")
         flops = algorithmic_flops(st_e)
-        kms = stages["fused"]  # one persistent launch per solve (+ counter reset, top reduction)
+        kms = stages["fused"]
         units = sum(p) + st_e["pairs_top"]
         tkey = "k_persist_fp64_c1"
     else:
-        kname = "k_class<refined-target multipole, fp64> (classes 1+2)"
+        kname = (f"k_class<refined-target multipole, fp64> (classes 1+2; {launches['mp_refined']} "
+                 "launch(es) per solve: fine and coarse branch)")
         flops = (p[0] + p[1]) * FLOP_PAIR_REFINED
-        kms = stages["mp_refined"] / max(1, launches["mp_refined"])
+        kms = stages["mp_refined"]
         units = p[0] + p[1]
         tkey = "k_class_mp_ref_fp64_c1"
     achieved = flops / (kms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic_entry(tkey),
-                "kernel": kname, "launch_ms": kms, "pairs_per_launch": units,
+                "kernel": kname, "stage_ms": kms, "pairs_per_stage": units,
                 "flop_per_pair": {"refined_target": FLOP_PAIR_REFINED, "leaf_multipole": FLOP_PAIR_LEAF_MP,
                                   "leaf_leaf": FLOP_PAIR_MONO}}
     mono_ms = stages["mono"]

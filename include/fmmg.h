@@ -108,11 +108,19 @@ typedef struct {
                                    0 = the occupancy limit                              */
     int32_t autotune;           /* 1 = the first solve times the candidate launch shapes
                                    (per-class or persistent, plane groups, blocks per
-                                   CU) on the caller's data, keeps the fastest, and
+                                   CU, overlap) on the caller's data, keeps the fastest, and
                                    records it in tuning_cache; that solve synchronises
                                    the stream.  A cached entry for the same plan
                                    signature is used without timing.                    */
     const char* tuning_cache;   /* JSON file of tuned launch shapes, or NULL            */
+    int32_t overlap;            /* 1 (default) = the coarse levels' passes and
+                                   same-level items (the levels below a split level
+                                   that carry at most a fifth of the estimated work)
+                                   run on a second, plan-owned stream, overlapping
+                                   the finer levels' same-level step; the solve still
+                                   completes in order on the caller's stream.
+                                   0 = everything on the caller's stream.  Timing
+                                   solves always run on one stream.                     */
 } fmmg_options;
 
 /* Stages of one solve, in launch order. */
@@ -141,6 +149,8 @@ typedef struct {
     int32_t blocks_per_cu;
     int32_t from_cache;         /* 1 if the shape came from the tuning cache           */
     double tuned_ms;            /* best solve time measured by the tuner, or 0         */
+    int32_t overlap;            /* 1 if the coarse levels run on the second stream     */
+    int32_t split_level;        /* levels below this one form the coarse branch        */
 } fmmg_launch_shape;
 
 typedef struct {

@@ -48,7 +48,8 @@ class fmmg_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("top_mode", C.c_int), ("G", C.c_double),
                 ("angular_correction", C.c_int32), ("use_graph", C.c_int32),
                 ("persistent", C.c_int32), ("timing", C.c_int32), ("plane_groups", C.c_int32),
-                ("blocks_per_cu", C.c_int32), ("autotune", C.c_int32), ("tuning_cache", C.c_char_p)]
+                ("blocks_per_cu", C.c_int32), ("autotune", C.c_int32), ("tuning_cache", C.c_char_p),
+                ("overlap", C.c_int32)]
 
 
 class fmmg_timings(C.Structure):
@@ -57,11 +58,13 @@ class fmmg_timings(C.Structure):
 
 class fmmg_launch_shape(C.Structure):
     _fields_ = [("persistent", C.c_int32), ("plane_groups", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("from_cache", C.c_int32), ("tuned_ms", C.c_double)]
+                ("from_cache", C.c_int32), ("tuned_ms", C.c_double), ("overlap", C.c_int32),
+                ("split_level", C.c_int32)]
 
     def as_dict(self):
         return {"persistent": int(self.persistent), "plane_groups": int(self.plane_groups),
-                "blocks_per_cu": int(self.blocks_per_cu), "from_cache": int(self.from_cache),
+                "blocks_per_cu": int(self.blocks_per_cu), "overlap": int(self.overlap),
+                "split_level": int(self.split_level), "from_cache": int(self.from_cache),
                 "tuned_ms": float(self.tuned_ms)}
 
 
@@ -244,7 +247,7 @@ class Plan:
                  G: float = 1.0, angular_correction: bool = True, use_graph: bool = False,
                  persistent: bool = False, timing: bool = False, plane_groups: int = 0,
                  blocks_per_cu: int = 0, autotune: bool = False, tuning_cache: str | None = None,
-                 stream=None):
+                 overlap: bool = True, stream=None):
         opt = fmmg_default_options()
         opt.precision = {"fp64": FMMG_FP64, "mixed": FMMG_MIXED}[precision]
         opt.top_mode = {"full": FMMG_TOP_FULL, "stencil": FMMG_TOP_STENCIL_ONLY}[top_mode]
@@ -258,6 +261,7 @@ class Plan:
         opt.autotune = int(bool(autotune))
         self._cache = tuning_cache.encode() if tuning_cache else None
         opt.tuning_cache = self._cache
+        opt.overlap = int(bool(overlap))
         self._h = fmmg_plan_create(trees, opt, stream)
         self.n_leaves = fmmg_plan_n_leaves(self._h)
 

@@ -90,17 +90,20 @@ struct fmmg_plan {
     fmmg_options opt;
     HostPlan hp;
     hipStream_t capture_stream = nullptr;
+    hipStream_t side_stream = nullptr;     // coarse branch of an overlapped solve
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     SubDev* d_subs = nullptr;
     int32_t* d_leaf_sub = nullptr;
     int32_t* d_ref_by_level = nullptr;
     int32_t* d_top_leaf = nullptr;
+    int32_t* d_l2l_tasks = nullptr;
     int32_t* d_top_src = nullptr;
     TopItem* d_top_items = nullptr;
     TopReduce* d_top_reduce = nullptr;
     Item* d_items_class = nullptr;
     Item* d_items_lpt = nullptr;
     size_t items_capacity = 0;
-    int* d_counter = nullptr;
+    int* d_counter = nullptr;              // two persistent-launch counter pairs
     double* d_mass = nullptr;
     double* d_rec = nullptr;
     double* d_Lp = nullptr;
@@ -139,7 +142,7 @@ void drop_graph(fmmg_plan* p) {
 void release(fmmg_plan* p) {
     if (!p) return;
     drop_graph(p);
-    void* bufs[] = {p->d_subs, p->d_leaf_sub, p->d_ref_by_level, p->d_top_leaf,
+    void* bufs[] = {p->d_subs, p->d_leaf_sub, p->d_ref_by_level, p->d_top_leaf, p->d_l2l_tasks,
                     p->d_top_src, p->d_top_items, p->d_top_reduce, p->d_items_class, p->d_items_lpt,
                     p->d_counter, p->d_mass, p->d_rec, p->d_Lp, p->d_Lr, p->d_Lf, p->d_Lf3, p->d_part,
                     p->d_bad};
@@ -150,6 +153,9 @@ void release(fmmg_plan* p) {
         for (hipEvent_t ev : set)
             if (ev) (void)hipEventDestroy(ev);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     delete p;
 }
 
@@ -168,7 +174,6 @@ Ctx make_ctx(const fmmg_plan* p, hipStream_t st) {
     a.top_src = p->d_top_src;
     a.top_reds = p->d_top_reduce;
     a.rho = nullptr;
-    a.counter = p->d_counter;
     a.part_stride = int64_t(p->hp.ref_sub.size()) * NLOC * NCELL;
     a.G = p->opt.G;
     a.corr = p->opt.angular_correction ? 1 : 0;
@@ -179,7 +184,7 @@ Ctx make_ctx(const fmmg_plan* p, hipStream_t st) {
 }
 
 // Rebuilds and uploads the work items for a launch shape.
-fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, hipStream_t st) {
+fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int overlap, hipStream_t st) {
     if (groups < 1 || groups > MAX_GROUPS) return fail(FMMG_EINVAL, "plane_groups must be 1 or 2");
     if (bpc < 0) return fail(FMMG_EINVAL, "blocks_per_cu must be >= 0");
     if (bpc == 0 || bpc > p->max_bpc) bpc = p->max_bpc;
@@ -194,89 +199,131 @@ fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, hipSt
         }
         HIP_TRY(hipStreamSynchronize(st), "item upload");
     }
-    if (p->shape.persistent != persistent || p->shape.plane_groups != groups || p->shape.blocks_per_cu != bpc)
+    overlap = overlap && p->hp.split > 0 ? 1 : 0;
+    if (p->shape.persistent != persistent || p->shape.plane_groups != groups || p->shape.blocks_per_cu != bpc ||
+        p->shape.overlap != overlap)
         drop_graph(p);
     p->shape.persistent = persistent;
     p->shape.plane_groups = groups;
     p->shape.blocks_per_cu = bpc;
+    p->shape.overlap = overlap;
+    p->shape.split_level = p->hp.split;
     return FMMG_OK;
 }
 
 // The solve's launch sequence; returns the number of launches.  ev (may be
-// null) receives an event at every stage boundary.
+// null) receives an event at every stage boundary; it forces one stream.
+//
+// Levels below the split level s form the coarse branch.  Dependencies: the
+// same-level items of level l need the upward pass down to level l - 1 (the
+// masses of level-l leaves); the downward task of a level-l parent needs its
+// own items (level l), its inherited part (the level l - 1 task) and, for
+// leaf children, their own items (level l + 1).  Overlapped order:
+//   caller's stream: upward levels max-1 .. s-1 | fork | fine items | join |
+//                    leaf children of level s-1, downward levels s .. max-1
+//   side stream:     (after fork) upward levels s-2 .. 0, parentless-leaf
+//                    masses, coarse items, parentless-leaf output, refined
+//                    children of levels 0 .. s-1, leaf children of levels
+//                    0 .. s-2 | join
 int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, hipStream_t st,
                       const hipEvent_t* ev) {
     const HostPlan& hp = p->hp;
+    const int s = hp.split;
+    const bool fork = !ev && p->shape.overlap && s > 0;
+    hipStream_t side = fork ? p->side_stream : st;
     Ctx a = make_ctx(p, st);
     a.rho = rho;
+    Ctx c = a;
+    c.st = side;
     int64_t per[FMMG_N_STAGES] = {0, 0, 0, 0, 0, 0, 0, 0};
     int stage = 0;
-    auto mark = [&](int s) {
-        stage = s;
-        if (ev) (void)hipEventRecord(ev[s], st);
+    auto mark = [&](int sg) {
+        stage = sg;
+        if (ev) (void)hipEventRecord(ev[sg], st);
     };
-    auto cnt = [&](int items, int launches = 1) { if (items > 0) per[stage] += launches; };
-    // the first kernel of the solve clears the persistent launch's counter
-    bool reset = p->shape.persistent != 0;
-    // step 1: masses of leaves without parents, then moments bottom-up (each
-    // level also stores the masses of its leaf children)
-    mark(FMMG_STAGE_P2M);
-    const int n_tl = int(hp.top_leaf.size());
-    launch_p2m_top(a, p->d_top_leaf, n_tl, reset);
-    if (n_tl > 0) reset = false;
-    cnt(n_tl);
-    mark(FMMG_STAGE_M2M);
-    for (int l = hp.max_level - 1; l >= 0; --l) {
+    auto cnt = [&](int n) { if (n > 0) per[stage] += 1; };
+    auto m2m = [&](const Ctx& x, int l) {
         int b = hp.level_ref_begin[size_t(l)], e = hp.level_ref_begin[size_t(l) + 1];
-        launch_m2m(a, p->d_ref_by_level + b, e - b, reset);
-        if (e > b) reset = false;
+        launch_m2m(x, p->d_ref_by_level + b, e - b);
         cnt(e - b);
-    }
-    // step 2: same-level interactions
-    const int* cb = hp.class_begin;
-    mark(FMMG_STAGE_TOP);
-    if (!p->shape.persistent) {
-        launch_class(a, IT_TOP, p->d_items_class + cb[IT_TOP], cb[IT_TOP + 1] - cb[IT_TOP]);
-        cnt(cb[IT_TOP + 1] - cb[IT_TOP]);
-    }
-    mark(FMMG_STAGE_MONO);
-    if (!p->shape.persistent) {
-        launch_class(a, IT_MONO, p->d_items_class + cb[IT_MONO], cb[IT_MONO + 1] - cb[IT_MONO]);
-        cnt(cb[IT_MONO + 1] - cb[IT_MONO]);
-    }
-    mark(FMMG_STAGE_MP_REFINED);
-    if (!p->shape.persistent) {
-        launch_class(a, IT_MP_REF, p->d_items_class + cb[IT_MP_REF], cb[IT_MP_REF + 1] - cb[IT_MP_REF]);
-        cnt(cb[IT_MP_REF + 1] - cb[IT_MP_REF]);
-    }
-    mark(FMMG_STAGE_MP_LEAF);
-    if (!p->shape.persistent) {
-        launch_class(a, IT_MP_LEAF, p->d_items_class + cb[IT_MP_LEAF], cb[IT_MP_LEAF + 1] - cb[IT_MP_LEAF]);
-        cnt(cb[IT_MP_LEAF + 1] - cb[IT_MP_LEAF]);
-    }
-    mark(FMMG_STAGE_FUSED);
-    if (p->shape.persistent) {
-        const int n = int(hp.items_lpt.size());
-        const int grid = p->shape.blocks_per_cu * p->n_cu;
-        launch_persist(a, p->d_items_lpt, n, grid < n ? grid : n);
+    };
+    const int kinds[IT_KINDS] = {IT_TOP, IT_MONO, IT_MP_REF, IT_MP_LEAF};
+    auto one_class = [&](const Ctx& x, int br, int k) {
+        const int n = hp.class_begin[br][k + 1] - hp.class_begin[br][k];
+        launch_class(x, k, p->d_items_class + hp.class_begin[br][k], n);
         cnt(n);
-    }
-    // step 3: leaves without parents, then top-down re-expansion (the level-0
-    // parents' totals come from their partial sums)
-    mark(FMMG_STAGE_DOWN);
-    launch_leaf_out(a, p->d_top_leaf, n_tl, phi, g);
-    cnt(n_tl);
-    for (int l = 0; l < hp.max_level; ++l) {
-        int b = hp.level_ref_begin[size_t(l)], e = hp.level_ref_begin[size_t(l) + 1];
-        int mode = l > 0 ? PARENT_TOTAL : (hp.top_full ? PARENT_TOP_PARTS : PARENT_OWN_PARTS);
-        launch_l2l(a, p->d_ref_by_level + b, e - b, mode, phi, g);
+    };
+    auto fused = [&](const Ctx& x, int br) {
+        const int n = hp.lpt_begin[br + 1] - hp.lpt_begin[br];
+        const int grid = br == 0 ? p->shape.blocks_per_cu * p->n_cu : p->n_cu;
+        launch_persist(x, p->d_items_lpt + hp.lpt_begin[br], n, grid, p->d_counter + 2 * br);
+        cnt(n);
+    };
+    auto items = [&](const Ctx& x, int br) {
+        if (p->shape.persistent) fused(x, br);
+        else
+            for (int k : kinds) one_class(x, br, k);
+    };
+    auto l2l = [&](const Ctx& x, int l, int kind) {  // kind 1: refined children, 0: leaf children
+        const int b = hp.l2l_begin[size_t(2 * l + (1 - kind))], e = hp.l2l_begin[size_t(2 * l + (2 - kind))];
+        const int mode = l > 0 ? PARENT_TOTAL : (hp.top_full ? PARENT_TOP_PARTS : PARENT_OWN_PARTS);
+        launch_l2l(x, p->d_l2l_tasks + b, e - b, mode, phi, g);
         cnt(e - b);
+    };
+    const int n_tl = int(hp.top_leaf.size());
+    if (!fork) {
+        // one stream, stage by stage
+        mark(FMMG_STAGE_P2M);
+        launch_p2m_top(a, p->d_top_leaf, n_tl);
+        cnt(n_tl);
+        mark(FMMG_STAGE_M2M);
+        for (int l = hp.max_level - 1; l >= 0; --l) m2m(a, l);
+        const int stage_of[IT_KINDS] = {FMMG_STAGE_MP_REFINED, FMMG_STAGE_MP_LEAF, FMMG_STAGE_MONO, FMMG_STAGE_TOP};
+        for (int k : kinds) {
+            mark(stage_of[k]);
+            if (!p->shape.persistent) {
+                one_class(a, 0, k);
+                one_class(a, 1, k);
+            }
+        }
+        mark(FMMG_STAGE_FUSED);
+        if (p->shape.persistent) {
+            fused(a, 0);
+            fused(a, 1);
+        }
+        mark(FMMG_STAGE_DOWN);
+        launch_leaf_out(a, p->d_top_leaf, n_tl, phi, g);
+        cnt(n_tl);
+        for (int l = 0; l < hp.max_level; ++l) {
+            l2l(a, l, 1);
+            l2l(a, l, 0);
+        }
+    } else {
+        for (int l = hp.max_level - 1; l >= s - 1; --l) m2m(a, l);
+        (void)hipEventRecord(p->ev_fork, st);
+        (void)hipStreamWaitEvent(side, p->ev_fork, 0);
+        items(a, 0);
+        for (int l = s - 2; l >= 0; --l) m2m(c, l);
+        launch_p2m_top(c, p->d_top_leaf, n_tl);
+        cnt(n_tl);
+        items(c, 1);
+        launch_leaf_out(c, p->d_top_leaf, n_tl, phi, g);
+        cnt(n_tl);
+        for (int l = 0; l < s; ++l) l2l(c, l, 1);
+        for (int l = 0; l < s - 1; ++l) l2l(c, l, 0);
+        (void)hipEventRecord(p->ev_join, side);
+        (void)hipStreamWaitEvent(st, p->ev_join, 0);
+        l2l(a, s - 1, 0);
+        for (int l = s; l < hp.max_level; ++l) {
+            l2l(a, l, 1);
+            l2l(a, l, 0);
+        }
     }
     if (ev) (void)hipEventRecord(ev[FMMG_N_STAGES], st);
     int64_t n = 0;
-    for (int s = 0; s < FMMG_N_STAGES; ++s) {
-        p->stage_launches[s] = per[s];
-        n += per[s];
+    for (int k = 0; k < FMMG_N_STAGES; ++k) {
+        p->stage_launches[k] = per[k];
+        n += per[k];
     }
     return n;
 }
@@ -290,13 +337,14 @@ std::string signature(const fmmg_plan* p) {
     o << "fmmg1 trees=" << hp.n_trees << " sub=" << hp.subs.size() << " ref=" << hp.ref_sub.size()
       << " leaf=" << hp.leaf_sub.size() << " lev=" << hp.max_level << " k3=" << hp.n_slot3
       << " top=" << (p->opt.top_mode == FMMG_TOP_FULL ? "full" : "stencil")
-      << " prec=" << (p->opt.precision == FMMG_MIXED ? "mixed" : "fp64") << " cu=" << p->n_cu;
+      << " prec=" << (p->opt.precision == FMMG_MIXED ? "mixed" : "fp64") << " cu=" << p->n_cu
+      << " split=" << hp.split << " ovl=" << (p->opt.overlap ? 1 : 0);
     return o.str();
 }
 
 // Cache file: a JSON object, one entry per line:
-//   "signature": {"persistent": P, "plane_groups": G, "blocks_per_cu": B, "ms": T},
-bool cache_lookup(const char* path, const std::string& sig, int* pers, int* groups, int* bpc) {
+//   "signature": {"persistent": P, "plane_groups": G, "blocks_per_cu": B, "overlap": O, "ms": T},
+bool cache_lookup(const char* path, const std::string& sig, int* pers, int* groups, int* bpc, int* ovl) {
     if (!path) return false;
     std::ifstream f(path);
     if (!f) return false;
@@ -304,20 +352,22 @@ bool cache_lookup(const char* path, const std::string& sig, int* pers, int* grou
     while (std::getline(f, line)) {
         size_t at = line.find(key);
         if (at == std::string::npos) continue;
-        int a = -1, b = -1, c = -1;
+        int a = -1, b = -1, c = -1, d = -1;
         const char* s = line.c_str() + at + key.size();
-        if (std::sscanf(s, " {\"persistent\": %d, \"plane_groups\": %d, \"blocks_per_cu\": %d", &a, &b, &c) == 3 &&
-            (a == 0 || a == 1) && b >= 1 && b <= MAX_GROUPS && c >= 0) {
+        if (std::sscanf(s, " {\"persistent\": %d, \"plane_groups\": %d, \"blocks_per_cu\": %d, \"overlap\": %d",
+                        &a, &b, &c, &d) == 4 &&
+            (a == 0 || a == 1) && b >= 1 && b <= MAX_GROUPS && c >= 0 && (d == 0 || d == 1)) {
             *pers = a;
             *groups = b;
             *bpc = c;
+            *ovl = d;
             return true;
         }
     }
     return false;
 }
 
-void cache_store(const char* path, const std::string& sig, int pers, int groups, int bpc, double ms) {
+void cache_store(const char* path, const std::string& sig, int pers, int groups, int bpc, int ovl, double ms) {
     if (!path) return;
     std::vector<std::string> keep;
     {
@@ -331,8 +381,10 @@ void cache_store(const char* path, const std::string& sig, int pers, int groups,
         }
     }
     char buf[512];
-    std::snprintf(buf, sizeof(buf), "  \"%s\": {\"persistent\": %d, \"plane_groups\": %d, \"blocks_per_cu\": %d, \"ms\": %.6f}",
-                  sig.c_str(), pers, groups, bpc, ms);
+    std::snprintf(buf, sizeof(buf),
+                  "  \"%s\": {\"persistent\": %d, \"plane_groups\": %d, \"blocks_per_cu\": %d, \"overlap\": %d, "
+                  "\"ms\": %.6f}",
+                  sig.c_str(), pers, groups, bpc, ovl, ms);
     keep.push_back(buf);
     std::string tmp = std::string(path) + ".tmp";
     {
@@ -346,21 +398,22 @@ void cache_store(const char* path, const std::string& sig, int pers, int groups,
 }
 
 fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStream_t st) {
-    int pers = 0, groups = 0, bpc = 0;
+    int pers = 0, groups = 0, bpc = 0, ovl = 0;
     const std::string sig = signature(p);
-    if (cache_lookup(p->opt.tuning_cache, sig, &pers, &groups, &bpc)) {
-        fmmg_status s = apply_shape(p, pers, groups, bpc, st);
+    if (cache_lookup(p->opt.tuning_cache, sig, &pers, &groups, &bpc, &ovl)) {
+        fmmg_status s = apply_shape(p, pers, groups, bpc, ovl, st);
         if (s != FMMG_OK) return s;
         p->shape.from_cache = 1;
         p->tuned = true;
         return FMMG_OK;
     }
-    struct Cand { int pers, groups, bpc; };
+    struct Cand { int pers, groups, bpc, ovl; };
     std::vector<Cand> cands;
-    for (int gr = 1; gr <= MAX_GROUPS; ++gr) {
-        cands.push_back({0, gr, 0});
-        for (int b = 1; b <= p->max_bpc; ++b) cands.push_back({1, gr, b});
-    }
+    for (int ov = 0; ov <= (p->opt.overlap && p->hp.split > 0 ? 1 : 0); ++ov)
+        for (int gr = 1; gr <= MAX_GROUPS; ++gr) {
+            cands.push_back({0, gr, 0, ov});
+            for (int b = 1; b <= p->max_bpc; ++b) cands.push_back({1, gr, b, ov});
+        }
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(FMMG_EHIP, "hipEventCreate"); }
@@ -368,7 +421,7 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
     Cand bc = cands[0];
     fmmg_status status = FMMG_OK;
     for (const Cand& c : cands) {
-        status = apply_shape(p, c.pers, c.groups, c.bpc, st);
+        status = apply_shape(p, c.pers, c.groups, c.bpc, c.ovl, st);
         if (status != FMMG_OK) break;
         enqueue_solve(p, rho, phi, g, st, nullptr);  // warm
         double t = 1e300;
@@ -388,12 +441,12 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (status != FMMG_OK) return status;
-    status = apply_shape(p, bc.pers, bc.groups, bc.bpc, st);
+    status = apply_shape(p, bc.pers, bc.groups, bc.bpc, bc.ovl, st);
     if (status != FMMG_OK) return status;
     p->shape.from_cache = 0;
     p->shape.tuned_ms = best;
     p->tuned = true;
-    cache_store(p->opt.tuning_cache, sig, bc.pers, bc.groups, p->shape.blocks_per_cu, best);
+    cache_store(p->opt.tuning_cache, sig, bc.pers, bc.groups, p->shape.blocks_per_cu, p->shape.overlap, best);
     return FMMG_OK;
 }
 
@@ -419,6 +472,7 @@ void fmmg_default_options(fmmg_options* opt) {
     opt->blocks_per_cu = 0;
     opt->autotune = 0;
     opt->tuning_cache = nullptr;
+    opt->overlap = 1;
 }
 
 fmmg_status fmmg_count_pairs(const fmmg_tree_desc* trees, int32_t n_trees, fmmg_top_mode top_mode,
@@ -494,6 +548,7 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         UP(p->d_leaf_sub, hp.leaf_sub, 0, "leaf list");
         UP(p->d_ref_by_level, hp.ref_by_level, 0, "level lists");
         UP(p->d_top_leaf, hp.top_leaf, 0, "top leaf list");
+        UP(p->d_l2l_tasks, hp.l2l_tasks, 0, "downward tasks");
         UP(p->d_top_src, hp.top_src, 0, "top source list");
         UP(p->d_top_items, hp.top_items, 0, "top items");
         UP(p->d_top_reduce, hp.top_reduce, 0, "top reductions");
@@ -510,8 +565,14 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         AL(p->d_Lf3, size_t(hp.n_slot3) * NLEAF * NCELL, "leaf terms from refined sources");
         AL(p->d_part, size_t(hp.n_top_parts) * NLOC * NCELL, "top partial sums");
 #undef AL
-        e = hipMalloc(reinterpret_cast<void**>(&p->d_counter), sizeof(int));
+        e = hipMalloc(reinterpret_cast<void**>(&p->d_counter), 4 * sizeof(int));
         if (e != hipSuccess) { release(p); return fail(FMMG_ENOMEM, "hipMalloc counter"); }
+        e = hipMemsetAsync(p->d_counter, 0, 4 * sizeof(int), st);
+        if (e != hipSuccess) { release(p); return hip_fail(e, "counter clear"); }
+        e = hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) { release(p); return hip_fail(e, "second stream"); }
         e = hipMalloc(reinterpret_cast<void**>(&p->d_bad), sizeof(unsigned long long));
         if (e != hipSuccess) { release(p); return fail(FMMG_ENOMEM, "hipMalloc flag"); }
         e = hipHostMalloc(reinterpret_cast<void**>(&p->h_bad), sizeof(unsigned long long), hipHostMallocDefault);
@@ -530,7 +591,8 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         }
         p->hp.ngroups = 0;  // force the first item upload
         memset(&p->shape, 0, sizeof(p->shape));
-        s = apply_shape(p, o.persistent ? 1 : 0, o.plane_groups ? o.plane_groups : MAX_GROUPS, o.blocks_per_cu, st);
+        s = apply_shape(p, o.persistent ? 1 : 0, o.plane_groups ? o.plane_groups : MAX_GROUPS, o.blocks_per_cu,
+                        o.overlap, st);
         if (s != FMMG_OK) { release(p); return s; }
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) { release(p); return hip_fail(e, "plan upload"); }

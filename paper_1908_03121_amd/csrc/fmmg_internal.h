@@ -33,8 +33,9 @@ constexpr int REACH = 5;       // max |d_i| of the stencil
 constexpr int PW = NS + 2 * REACH;  // 18: edge of the source window around a sub-grid
 constexpr int PCELLS = PW * PW;     // 324 cells in one source z-plane window
 constexpr int PRS = 20;             // LDS row stride (cells) of windows and boxes: with
-                                    // 64 banks the 8 rows of a wave's 8x8 source block
-                                    // fall on disjoint bank sets
+                                    // lanes y-fastest (lane = x*8 + y), each pass of 32
+                                    // lanes reading 8-byte words over 64 banks hits
+                                    // distinct banks for every mirrored stencil offset
 constexpr int PSLOTS = PW * PRS;    // 360 LDS cells per plane window
 constexpr int NREC = 16;       // record components of a refined cell
 constexpr int NLOC = 19;       // Taylor components of a refined cell
@@ -42,7 +43,7 @@ constexpr int NLEAF = 4;       // phi, gx, gy, gz of a leaf cell
 constexpr int NDZ = 10;        // canonical dz range [-4, 5] of the parity-000 stencil
 constexpr int DZ0 = -4;
 constexpr int MONO_COLS = 100; // canonical (dx, dy) columns
-constexpr int MONO_TAB = 3 * (52 * 10 + 32 * 6 + 16 * 2);  // 2232 kernel values
+constexpr int MONO_R2 = 76;     // squared canonical offsets |d|^2 of the monopole columns: 0..75
 
 // record component indices
 enum { R_M = 0, R_DX = 1, R_DY = 2, R_DZ = 3, R_Q = 4, R_O = 9 };
@@ -87,12 +88,13 @@ struct StencilTables {
     // monopole kernel: the 100 columns (dx, dy) of the canonical stencil fall
     // into three classes by their dz range: [-4,5] (52 columns), [-2,3] (32),
     // [0,1] (16).  Columns are sorted by class; entry = (dx+8) | (dy+8) << 8.
-    // mono_tab holds, per column and dz of its range, 1/|d|, |d|^-3 and
-    // dz |d|^-3 (zero for d = 0, the self term).
+    // The kernel values depend on |d|^2 only: mono_r[n] = {n^-1/2, n^-3/2}
+    // (zero for n = 0, the self term), 1.2 KB, so they stay in the scalar
+    // cache; dz |d|^-3 is formed in the kernel.
     int32_t mono_col[MONO_COLS];
     int32_t mono_class_begin[4];
-    double mono_tab[MONO_TAB];
-    float mono_tabf[MONO_TAB];
+    double mono_r[MONO_R2][2];
+    float mono_rf[MONO_R2][2];
 };
 
 // Top-level (all pairs) tile: 64 target cells (plane zt of sub-grid target)

@@ -3,9 +3,10 @@
 // with order-3 multipoles and the angular-momentum correction, downward pass).
 //
 // Thread mapping of the same-level kernels: a wavefront holds one z-plane of
-// 8x8 target cells (lane = y*8 + x).  Cells of different parity use mirror
-// images of one canonical stencil, so every lane of a wave walks the same
-// entry list (uniform control flow, scalar table loads) with its own signs.
+// 8x8 target cells (stencil kernels: lane = x*8 + y; top level: y*8 + x).
+// Cells of different parity use mirror images of one canonical stencil, so
+// every lane of a wave walks the same entry list (uniform control flow,
+// scalar table loads) with its own signs.
 // Sources are staged in LDS one z-plane window (18 x 18 cells) at a time.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -30,6 +31,15 @@ __device__ __forceinline__ double rsqrt_full(double x) {
     return __builtin_fma(y * e, t, y);
 }
 __device__ __forceinline__ float rsqrt_full(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// threadIdx.x made opaque to the optimiser: index arithmetic derived from it
+// then stays inside the work item instead of being hoisted out of the
+// persistent loop, where it would stay live across every item
+__device__ __forceinline__ int item_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
 
 // internal cell index (x fastest) -> I/O index (z fastest)
 __device__ __forceinline__ int io_index(int q) {
@@ -143,7 +153,9 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
         a.l3[5] = fmaP(Y, ty + m3, a.l3[5]);
         a.l3[6] = fmaP(Z, cy, a.l3[6]);
     }
-    if (corr) {
+    // correction terms: always accumulated (no branch in the pair body); the
+    // output scale of S is zero when the correction is off
+    {
         const P d4 = P(-7) * ir2 * d3;
         P Qx = wb[0], Qy = wb[1], Qz = wb[2];
         if (FULL) {
@@ -165,11 +177,9 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
 // ---------------------------------------------------------------------------
 // step 1: leaf masses and the upward pass
 // ---------------------------------------------------------------------------
-// Leaves without a parent: m = rho h^3 in the internal cell order.  Thread 0
-// of block 0 also clears the persistent launch's work counter.
+// Leaves without a parent: m = rho h^3 in the internal cell order.
 // grid: one block of 512 per listed leaf.
-__global__ __launch_bounds__(512) void k_p2m_top(Ctx cx, const int32_t* __restrict__ list, int reset) {
-    if (reset && blockIdx.x == 0 && threadIdx.x == 0) *cx.counter = 0;
+__global__ __launch_bounds__(512) void k_p2m_top(Ctx cx, const int32_t* __restrict__ list) {
     const SubDev& S = cx.subs[list[blockIdx.x]];
     const int q = threadIdx.x;
     const double h = S.h;
@@ -187,10 +197,9 @@ __global__ __launch_bounds__(512) void k_p2m_top(Ctx cx, const int32_t* __restri
 //   M2 = S2 - m d d,   M3 = S3 - sym(S2 d) + 2 m d d d,
 // and stored trace-free (children's trace parts only feed trace parts).
 // grid: (refined sub-grids of the level) x 8 octants, 512 threads.
-__global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__ list, int reset) {
+__global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__ list) {
     __shared__ double red[4][16][20];
     __shared__ double rin[NCELL + NCELL / 8];  // leaf densities, I/O order, one pad per z-row
-    if (reset && blockIdx.x == 0 && threadIdx.x == 0) *cx.counter = 0;
     const SubDev& Ps = cx.subs[list[blockIdx.x >> 3]];
     const int e = blockIdx.x & 7;
     const SubDev& Cs = cx.subs[Ps.child[e]];
@@ -333,7 +342,8 @@ struct Smem {
     static constexpr int TOP = NREC * 256 * int(sizeof(P)) + 4 * 256 * 4;  // top-level source tile
     static constexpr int A = PLANE > BOX ? PLANE : BOX;
     static constexpr int B = RED > TOP ? RED : TOP;
-    static constexpr int BYTES = ((A > B ? A : B) + 15) & ~15;
+    static constexpr int NBR_OFF = ((A > B ? A : B) + 15) & ~15;  // the target's 27 neighbour codes
+    static constexpr int BYTES = NBR_OFF + 128;
 };
 
 // Multipole item: 64 target cells (plane zt of sub-grid sid) against the
@@ -347,14 +357,20 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     using P = typename std::conditional<MIXED, float, double>::type;
     P* sh = reinterpret_cast<P*>(smem);
     unsigned char* leafflag = smem + NREC * PSLOTS * sizeof(P);
+    int* nb = reinterpret_cast<int*>(smem + Smem<P>::NBR_OFF);
 
-    const int t = threadIdx.x, lane = t & 63;
+    const int t = item_tid(), lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index: uniform
-    const int x = lane & 7, y = lane >> 3;
+    // y runs fastest over the lanes: with the window row stride of 20 cells,
+    // the 32 lanes of each LDS pass then hit distinct banks for every offset
+    const int x = lane >> 3, y = lane & 7, cl = y * 8 + x;
     const SubDev& T = cx.subs[sid];
+    // (visible to the staging loop after its barrier; no other use of this
+    // LDS region, so no barrier is needed before the write)
+    if (t < 27) nb[t] = T.nbr[t];
     const double h = T.h;
     const int tidx = T.idx;
-    const int q = zt * 64 + lane;
+    const int q = zt * 64 + cl;
     const int sx = 1 - 2 * (x & 1), sy = 1 - 2 * (y & 1), sz = 1 - 2 * (zt & 1);
 
     // target data
@@ -403,29 +419,35 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
             if (!any) continue;
         }
         __syncthreads();
-        // stage the 18x18 source window of plane zs
+        // stage the 18x18 source window of plane zs: each thread takes up to
+        // two cells and issues all loads of a cell at once (record and mass
+        // loads are unconditional, from a valid address, and then selected)
         {
             const int lz = zs - NS * oz;
-            for (int cr = t; cr < PCELLS; cr += 256) {
-                const int wx = cr % PW, wy = cr / PW;
-                const int c = wy * PRS + wx;
-                const int lx = wx - REACH, ly = wy - REACH;
-                const int ox = lx < 0 ? -1 : (lx >= NS ? 1 : 0);
-                const int oy = ly < 0 ? -1 : (ly >= NS ? 1 : 0);
-                const int code = T.nbr[(ox + 1) * 9 + (oy + 1) * 3 + (oz + 1)];
-                const int cq = (lz * NS + (ly - NS * oy)) * NS + (lx - NS * ox);
-                const int kind = code < 0 ? -1 : (code & 1), nidx = code >> 1;
-                if (kind == 1) {
-                    const double* r = cx.rec + size_t(nidx) * NREC * NCELL + cq;
+#pragma unroll 1
+            for (int u = 0; u < 2; ++u) {
+                const int cr = t + u * 256;
+                if (cr < PCELLS) {
+                    const int wx = cr % PW, wy = cr / PW;
+                    const int c = wy * PRS + wx;
+                    const int lx = wx - REACH, ly = wy - REACH;
+                    const int ox = lx < 0 ? -1 : (lx >= NS ? 1 : 0);
+                    const int oy = ly < 0 ? -1 : (ly >= NS ? 1 : 0);
+                    const int code = nb[(ox + 1) * 9 + (oy + 1) * 3 + (oz + 1)];
+                    const int cq = (lz * NS + (ly - NS * oy)) * NS + (lx - NS * ox);
+                    const int kind = code < 0 ? -1 : (code & 1), nidx = code >> 1;
+                    const double* r = cx.rec + (kind == 1 ? size_t(nidx) * NREC * NCELL + cq : size_t(0));
+                    const double* mp = cx.mass + (kind == 0 ? size_t(nidx) * NCELL + cq : size_t(0));
+                    double v[NREC];
 #pragma unroll
-                    for (int k = 0; k < NREC; ++k) sh[k * PSLOTS + c] = P(r[k * NCELL]);
-                } else {
-                    P mm = (kind == 0 && !LEAF_T) ? P(cx.mass[size_t(nidx) * NCELL + cq]) : P(0);
-                    sh[c] = mm;
+                    for (int k = 0; k < NREC; ++k) v[k] = r[k * NCELL];
+                    const double mm = *mp;
 #pragma unroll
-                    for (int k = 1; k < NREC; ++k) sh[k * PSLOTS + c] = P(0);
+                    for (int k = 0; k < NREC; ++k)
+                        sh[k * PSLOTS + c] = kind == 1 ? P(v[k])
+                                             : (k == 0 && kind == 0 && !LEAF_T ? P(mm) : P(0));
+                    if (!LEAF_T) leafflag[c] = kind == 0;
                 }
-                if (!LEAF_T) leafflag[c] = kind == 0;
             }
         }
         __syncthreads();
@@ -448,7 +470,13 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
             pair_terms<!LEAF_T, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], inv_ma, oa, use_corr, part);
         };
         const int fb = c_tab.mp_far_begin[gi], fe = fb + c_tab.mp_far_count[gi];
-        for (int e = fb + w; e < fe; e += 4) one(e);
+        // two independent pairs per iteration: two dependency chains per wave
+        int e = fb + w;
+        for (; e + 4 < fe; e += 8) {
+            one(e);
+            one(e + 4);
+        }
+        if (e < fe) one(e);
         if (do_near) {
             const int nbg = c_tab.mp_near_begin[gi], ne = nbg + c_tab.mp_near_count[gi];
             for (int e = nbg + w; e < ne; e += 4) {
@@ -471,7 +499,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         double v[NLOC];
         acc.out(v);
 #pragma unroll
-        for (int k = 0; k < NLOC; ++k) red[(w * NLOC + k) * 64 + lane] = v[k];
+        for (int k = 0; k < NLOC; ++k) red[(w * NLOC + k) * 64 + cl] = v[k];
     }
     __syncthreads();
     const double G = cx.G;
@@ -504,15 +532,22 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
 // its (x, y) column) and every second stencil column (w >> 1); the two
 // column halves are added in a fixed order.
 
+// kernel values {|d|^-1, |d|^-3} for |d|^2 = n (uniform: scalar loads)
 template <typename P>
-__device__ __forceinline__ P mono_tab(int i);
+__device__ __forceinline__ void mono_r(int n, P& a, P& b);
 template <>
-__device__ __forceinline__ double mono_tab<double>(int i) { return c_tab.mono_tab[i]; }
+__device__ __forceinline__ void mono_r<double>(int n, double& a, double& b) {
+    a = c_tab.mono_r[n][0];
+    b = c_tab.mono_r[n][1];
+}
 template <>
-__device__ __forceinline__ float mono_tab<float>(int i) { return c_tab.mono_tabf[i]; }
+__device__ __forceinline__ void mono_r<float>(int n, float& a, float& b) {
+    a = c_tab.mono_rf[n][0];
+    b = c_tab.mono_rf[n][1];
+}
 
 template <int PZ, int LO, int N, typename P>
-__device__ __forceinline__ void mono_class(const P* __restrict__ box, int cbeg, int cend, int tab0,
+__device__ __forceinline__ void mono_class(const P* __restrict__ box, int cbeg, int cend,
                                            int cstart, int cstep, int lbase, int sx, int syw, int sy,
                                            double (&phi)[4], double (&gx)[4], double (&gy)[4],
                                            double (&gz)[4]) {
@@ -527,19 +562,21 @@ __device__ __forceinline__ void mono_class(const P* __restrict__ box, int cbeg, 
         P m[NSRC];
 #pragma unroll
         for (int j = 0; j < NSRC; ++j) m[j] = col[j * PSLOTS];
-        const int t0 = tab0 + (c - cbeg) * (3 * N);
+        const int rxy = dx * dx + dy * dy;
         P s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int i = 0; i < N; ++i) {
-            const P a = mono_tab<P>(t0 + 3 * i), b = mono_tab<P>(t0 + 3 * i + 1),
-                    cz = mono_tab<P>(t0 + 3 * i + 2);
+            const int dzc = LO + i;  // canonical dz
+            P a, b;
+            mono_r<P>(rxy + dzc * dzc, a, b);
+            const P cz = P(dzc) * b;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 // target z = PZ + 2k, source z = PZ + 2k + SZ*(LO + i)
                 const P mm = m[PZ + 2 * k + SZ * (LO + i) - ZMIN];
                 s0[k] += mm * a;
                 s1[k] += mm * b;
-                s2[k] += mm * cz;
+                if (dzc != 0) s2[k] += mm * cz;
             }
         }
         const double fx = double(sx * dx), fy = double(sy * dy);
@@ -559,10 +596,9 @@ __device__ __forceinline__ void mono_all(const P* box, int cstart, int cstep, in
                                          double (&gy)[4], double (&gz)[4]) {
     const int b0 = c_tab.mono_class_begin[0], b1 = c_tab.mono_class_begin[1];
     const int b2 = c_tab.mono_class_begin[2], b3 = c_tab.mono_class_begin[3];
-    const int t1 = (b1 - b0) * 30, t2 = t1 + (b2 - b1) * 18;
-    mono_class<PZ, -4, 10, P>(box, b0, b1, 0, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
-    mono_class<PZ, -2, 6, P>(box, b1, b2, t1, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
-    mono_class<PZ, 0, 2, P>(box, b2, b3, t2, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
+    mono_class<PZ, -4, 10, P>(box, b0, b1, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
+    mono_class<PZ, -2, 6, P>(box, b1, b2, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
+    mono_class<PZ, 0, 2, P>(box, b2, b3, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
 }
 
 
@@ -570,28 +606,47 @@ template <bool MIXED>
 __device__ __forceinline__ void mono_item(const Ctx& cx, int sid, unsigned char* smem) {
     using P = typename std::conditional<MIXED, float, double>::type;
     P* box = reinterpret_cast<P*>(smem);
-    const int t = threadIdx.x;
+    int* nb = reinterpret_cast<int*>(smem + Smem<P>::NBR_OFF);
+    const int t = item_tid();
     const SubDev& T = cx.subs[sid];
+    if (t < 27) nb[t] = T.nbr[t];
     __syncthreads();
-    for (int cr = t; cr < PW * PW * PW; cr += 256) {
-        const int wx = cr % PW, wy = (cr / PW) % PW, wz = cr / (PW * PW);
-        const int c = wz * PSLOTS + wy * PRS + wx;
-        const int lx = wx - REACH, ly = wy - REACH, lz = wz - REACH;
-        const int ox = lx < 0 ? -1 : (lx >= NS ? 1 : 0);
-        const int oy = ly < 0 ? -1 : (ly >= NS ? 1 : 0);
-        const int oz = lz < 0 ? -1 : (lz >= NS ? 1 : 0);
-        const int code = T.nbr[(ox + 1) * 9 + (oy + 1) * 3 + (oz + 1)];
-        P mm = 0;
-        if (code >= 0 && (code & 1) == 0) {
+    // stage the 18^3 mass box, 8 cells per thread at a time with all their
+    // loads in flight together (unconditional, from a valid address)
+    constexpr int NBOX = PW * PW * PW, PER = (NBOX + 255) / 256;
+#pragma unroll
+    for (int u0 = 0; u0 < PER; u0 += 8) {
+        double v[8];
+        int dst[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            dst[u] = -1;
+            v[u] = 0;
+            if (u0 + u >= PER) continue;  // resolved at compile time
+            // no branch around the load: the tail's excess cells read cell 0
+            const int cr0 = t + (u0 + u) * 256;
+            const bool ok = cr0 < NBOX;
+            const int cr = ok ? cr0 : 0;
+            const int wx = cr % PW, wy = (cr / PW) % PW, wz = cr / (PW * PW);
+            const int lx = wx - REACH, ly = wy - REACH, lz = wz - REACH;
+            const int ox = lx < 0 ? -1 : (lx >= NS ? 1 : 0);
+            const int oy = ly < 0 ? -1 : (ly >= NS ? 1 : 0);
+            const int oz = lz < 0 ? -1 : (lz >= NS ? 1 : 0);
+            const int code = nb[(ox + 1) * 9 + (oy + 1) * 3 + (oz + 1)];
+            const bool leaf = code >= 0 && (code & 1) == 0;
             const int cq = ((lz - NS * oz) * NS + (ly - NS * oy)) * NS + (lx - NS * ox);
-            mm = P(cx.mass[size_t(code >> 1) * NCELL + cq]);
+            const double m = cx.mass[leaf ? size_t(code >> 1) * NCELL + cq : size_t(0)];
+            v[u] = leaf ? m : 0.0;
+            dst[u] = ok ? wz * PSLOTS + wy * PRS + wx : -1;
         }
-        box[c] = mm;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (dst[u] >= 0) box[dst[u]] = P(v[u]);
     }
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int pz = w & 1, half = w >> 1;
-    const int lane = t & 63, x = lane & 7, y = lane >> 3;
+    const int lane = t & 63, x = lane >> 3, y = lane & 7;  // y fastest (LDS banks)
     const int sx = 1 - 2 * (x & 1), sy = 1 - 2 * (y & 1);
     const int lbase = (y + REACH) * PRS + (x + REACH);
     const int syw = sy * PRS;
@@ -616,7 +671,7 @@ __device__ __forceinline__ void mono_item(const Ctx& cx, int sid, unsigned char*
         double* out = cx.Lf + size_t(T.idx) * NLEAF * NCELL;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int q = (pz + 2 * k) * 64 + lane;
+            const int q = (pz + 2 * k) * 64 + y * 8 + x;
             out[0 * NCELL + q] = gp * (phi[k] + red[((pz * 16) + 4 * k + 0) * 64 + lane]);
             out[1 * NCELL + q] = gh * (gx[k] + red[((pz * 16) + 4 * k + 1) * 64 + lane]);
             out[2 * NCELL + q] = gh * (gy[k] + red[((pz * 16) + 4 * k + 2) * 64 + lane]);
@@ -633,7 +688,7 @@ template <bool MIXED>
 __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsigned char* smem) {
     using P = typename std::conditional<MIXED, float, double>::type;
     const SubDev& T = cx.subs[it.target];
-    const int t = threadIdx.x, lane = t & 63, x = lane & 7, y = lane >> 3;
+    const int t = item_tid(), lane = t & 63, x = lane & 7, y = lane >> 3;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int q = it.zt * 64 + lane;
     const bool tref = T.kind == 1;
@@ -741,22 +796,27 @@ __global__ __launch_bounds__(256) void k_class(Ctx cx, const Item* __restrict__ 
     else top_item<MIXED>(cx, cx.top_items[it.sub], smem);
 }
 
-// Persistent launch of every class and tree: each block takes the next item
-// of the (largest-first) list from a device counter until the list is
-// exhausted, so every block exits once all items are taken.
+// Persistent launch over a list of items: each block takes the next item of
+// the (largest-first) list from ctr[0] until the list is exhausted, so every
+// block exits once all items are taken.  The last block to exit re-arms
+// ctr[0] and ctr[1] (both zero before the first launch) for the next launch.
 template <bool MIXED>
-__global__ __launch_bounds__(256, 3) void k_persist(Ctx cx, const Item* __restrict__ items, int n) {
-    int* __restrict__ counter = cx.counter;
+__global__ __launch_bounds__(256, 3) void k_persist(Ctx cx, const Item* __restrict__ items, int n,
+                                                    int* __restrict__ ctr) {
     using P = typename std::conditional<MIXED, float, double>::type;
     __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P>::BYTES];
     __shared__ int s_it;
     for (;;) {
-        if (threadIdx.x == 0) s_it = atomicAdd(counter, 1);
+        if (threadIdx.x == 0) s_it = atomicAdd(&ctr[0], 1);
         __syncthreads();
         const int it = s_it;
         __syncthreads();
         if (it >= n) break;
         run_item<MIXED>(cx, items[it], smem);
+    }
+    if (threadIdx.x == 0 && atomicAdd(&ctr[1], 1) == int(gridDim.x) - 1) {
+        atomicExch(&ctr[0], 0);
+        atomicExch(&ctr[1], 0);
     }
 }
 
@@ -781,17 +841,20 @@ __device__ __forceinline__ double top_total(const Ctx& cx, const SubDev& T, int 
 // the child COM, r = X_child - X_parent:
 //   o0 = L0 + L1.r + 1/2 r.L2.r + 1/6 L3:rrr,  o1 = L1 + L2.r + 1/2 L3:rr,
 //   o2 = L2 + L3.r,  o3 = L3,  dg passed unchanged.
-// The parent's total is read from Lr, or formed from the top-level partial
-// slots, or from its own plane-group sums (parent_mode).
-// Refined children: total = own (sum of plane groups) + shifted parent.
+// The parent's total is formed from its top-level partial slots (level 0
+// under the all-pairs rule), from its own plane-group sums (level 0 under the
+// stencil rule), or as its inherited part Lr plus its own plane-group sums.
+// Refined children: Lr = shifted parent (their own terms join when they act
+// as parents, so this step does not wait for them).
 // Leaf children: phi = own + o0,  g = own - o1 + dg.
-// grid: (refined parents at level l) x 8 child sub-grids, 512 threads.
-__global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__ list, int parent_mode,
+// grid: one block of 512 per task (parent sub-grid * 8 + child slot).
+__global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__ tasks, int parent_mode,
                                              double* __restrict__ phi, double* __restrict__ gout) {
     __shared__ double obuf[4][NCELL];
     __shared__ double par[NLOC + 3][64];  // the octant's 64 parent cells: L (19), COM offset (3)
-    const SubDev& Ps = cx.subs[list[blockIdx.x >> 3]];
-    const int e = blockIdx.x & 7;
+    const int task = tasks[blockIdx.x];
+    const SubDev& Ps = cx.subs[task >> 3];
+    const int e = task & 7;
     const SubDev& Cs = cx.subs[Ps.child[e]];
     const int q = threadIdx.x;
     const int x = q & 7, y = (q >> 3) & 7, z = q >> 6;
@@ -808,12 +871,10 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
             v = cx.rec[(size_t(Ps.idx) * NREC + R_DX + (k - NLOC)) * NCELL + pq];
         } else if (parent_mode == PARENT_TOP_PARTS) {
             v = top_total(cx, Ps, k, pq);
-        } else if (parent_mode == PARENT_OWN_PARTS) {
-            const size_t base = (size_t(Ps.idx) * NLOC + k) * NCELL + pq;
-            v = 0;
-            for (int gg = 0; gg < cx.ngroups; ++gg) v += cx.Lp[size_t(gg) * size_t(cx.part_stride) + base];
         } else {
-            v = cx.Lr[(size_t(Ps.idx) * NLOC + k) * NCELL + pq];
+            const size_t base = (size_t(Ps.idx) * NLOC + k) * NCELL + pq;
+            v = parent_mode == PARENT_TOTAL ? cx.Lr[base] : 0.0;
+            for (int gg = 0; gg < cx.ngroups; ++gg) v += cx.Lp[size_t(gg) * size_t(cx.part_stride) + base];
         }
         par[k][c] = v;
     }
@@ -868,11 +929,8 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
         sh[T_S + 1] = sgy;
         sh[T_S + 2] = sgz;
         const size_t base = size_t(Cs.idx) * NLOC * NCELL + q;
-        for (int k = 0; k < NLOC; ++k) {
-            double own = 0;
-            for (int gg = 0; gg < cx.ngroups; ++gg) own += cx.Lp[size_t(gg) * size_t(cx.part_stride) + base + k * NCELL];
-            cx.Lr[base + k * NCELL] = own + sh[k];
-        }
+#pragma unroll
+        for (int k = 0; k < NLOC; ++k) cx.Lr[base + k * NCELL] = sh[k];
     } else {
         const double* F = cx.Lf + size_t(Cs.idx) * NLEAF * NCELL + q;
         double f0 = F[0], f1 = F[1 * NCELL], f2 = F[2 * NCELL], f3 = F[3 * NCELL];
@@ -945,12 +1003,12 @@ hipError_t upload_tables(const StencilTables* t, hipStream_t st) {
                                   hipMemcpyHostToDevice, st);
 }
 
-void launch_p2m_top(const Ctx& a, const int32_t* list, int n, bool reset_counter) {
-    if (n > 0) hipLaunchKernelGGL(k_p2m_top, dim3(n), dim3(512), 0, a.st, a, list, reset_counter ? 1 : 0);
+void launch_p2m_top(const Ctx& a, const int32_t* list, int n) {
+    if (n > 0) hipLaunchKernelGGL(k_p2m_top, dim3(n), dim3(512), 0, a.st, a, list);
 }
 
-void launch_m2m(const Ctx& a, const int32_t* list, int n, bool reset_counter) {
-    if (n > 0) hipLaunchKernelGGL(k_m2m, dim3(n * 8), dim3(512), 0, a.st, a, list, reset_counter ? 1 : 0);
+void launch_m2m(const Ctx& a, const int32_t* list, int n) {
+    if (n > 0) hipLaunchKernelGGL(k_m2m, dim3(n * 8), dim3(512), 0, a.st, a, list);
 }
 
 template <int K>
@@ -969,10 +1027,11 @@ void launch_class(const Ctx& a, int kind, const Item* items, int n) {
     }
 }
 
-void launch_persist(const Ctx& a, const Item* items, int n, int grid) {
+void launch_persist(const Ctx& a, const Item* items, int n, int grid, int* ctr) {
     if (n <= 0 || grid <= 0) return;
-    if (a.mixed) hipLaunchKernelGGL((k_persist<true>), dim3(grid), dim3(256), 0, a.st, a, items, n);
-    else hipLaunchKernelGGL((k_persist<false>), dim3(grid), dim3(256), 0, a.st, a, items, n);
+    if (grid > n) grid = n;
+    if (a.mixed) hipLaunchKernelGGL((k_persist<true>), dim3(grid), dim3(256), 0, a.st, a, items, n, ctr);
+    else hipLaunchKernelGGL((k_persist<false>), dim3(grid), dim3(256), 0, a.st, a, items, n, ctr);
 }
 
 int persist_blocks_per_cu(int mixed) {
@@ -982,8 +1041,8 @@ int persist_blocks_per_cu(int mixed) {
     return e == hipSuccess ? nb : 0;
 }
 
-void launch_l2l(const Ctx& a, const int32_t* list, int n, int parent_mode, double* phi, double* g) {
-    if (n > 0) hipLaunchKernelGGL(k_l2l, dim3(n * 8), dim3(512), 0, a.st, a, list, parent_mode, phi, g);
+void launch_l2l(const Ctx& a, const int32_t* tasks, int n, int parent_mode, double* phi, double* g) {
+    if (n > 0) hipLaunchKernelGGL(k_l2l, dim3(n), dim3(512), 0, a.st, a, tasks, parent_mode, phi, g);
 }
 
 void launch_leaf_out(const Ctx& a, const int32_t* list, int n, double* phi, double* g) {

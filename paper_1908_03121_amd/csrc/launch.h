@@ -23,7 +23,6 @@ struct Ctx {
     const int32_t* top_src;
     const TopReduce* top_reds;  // partial slots of each top-level target
     const double* rho;          // caller's densities (I/O cell order)
-    int* counter;               // work counter of the persistent launch
     int64_t part_stride;    // elements between plane groups of Lp
     double G;
     int corr;
@@ -32,16 +31,18 @@ struct Ctx {
     hipStream_t st;
 };
 
-// parent expansions of one downward level
+// parent expansions of one downward level: inherited part + own plane-group
+// sums; top-level partial slots; own plane-group sums only
 enum { PARENT_TOTAL = 0, PARENT_TOP_PARTS = 1, PARENT_OWN_PARTS = 2 };
 
 hipError_t upload_tables(const StencilTables* t, hipStream_t st);
-void launch_p2m_top(const Ctx& a, const int32_t* list, int n, bool reset_counter);
-void launch_m2m(const Ctx& a, const int32_t* list, int n, bool reset_counter);
+void launch_p2m_top(const Ctx& a, const int32_t* list, int n);
+void launch_m2m(const Ctx& a, const int32_t* list, int n);
 void launch_class(const Ctx& a, int kind, const Item* items, int n);
-void launch_persist(const Ctx& a, const Item* items, int n, int grid);
+// ctr: two ints, zero before the first launch and re-armed by each launch
+void launch_persist(const Ctx& a, const Item* items, int n, int grid, int* ctr);
 int persist_blocks_per_cu(int mixed);
-void launch_l2l(const Ctx& a, const int32_t* list, int n, int parent_mode, double* phi, double* g);
+void launch_l2l(const Ctx& a, const int32_t* tasks, int n, int parent_mode, double* phi, double* g);
 void launch_leaf_out(const Ctx& a, const int32_t* list, int n, double* phi, double* g);
 void launch_check_density(const double* rho, int64_t n, unsigned long long* bad, hipStream_t st);
 

@@ -119,7 +119,7 @@ void build_stencil_tables(StencilTables* t) {
     }
     // monopole columns by dz-range class: [-4,5], [-2,3], [0,1]
     const int lo_of[3] = {-4, -2, 0}, n_of[3] = {10, 6, 2};
-    int nc = 0, pos_t = 0;
+    int nc = 0;
     for (int cls = 0; cls < 3; ++cls) {
         t->mono_class_begin[cls] = nc;
         for (int dx = -REACH; dx <= REACH; ++dx)
@@ -130,23 +130,16 @@ void build_stencil_tables(StencilTables* t) {
                 if (dx == 0 && dy == 0) { lo = -4; hi = 5; }  // the self offset sits inside this column
                 if (lo > hi || lo != lo_of[cls] || hi != lo_of[cls] + n_of[cls] - 1) continue;
                 t->mono_col[nc++] = (dx + 8) | ((dy + 8) << 8);
-                for (int i = 0; i < n_of[cls]; ++i) {
-                    int dz = lo + i, n2 = dx * dx + dy * dy + dz * dz;
-                    double a = 0, b = 0;
-                    if (n2 > 0) {
-                        a = 1.0 / sqrt(double(n2));
-                        b = 1.0 / (double(n2) * sqrt(double(n2)));
-                    }
-                    double v[3] = {a, b, dz * b};
-                    for (int k = 0; k < 3; ++k) {
-                        t->mono_tab[pos_t] = v[k];
-                        t->mono_tabf[pos_t] = float(v[k]);
-                        ++pos_t;
-                    }
-                }
             }
     }
     t->mono_class_begin[3] = nc;
+    for (int n2 = 1; n2 < MONO_R2; ++n2) {
+        const double a = 1.0 / sqrt(double(n2)), b = 1.0 / (double(n2) * sqrt(double(n2)));
+        t->mono_r[n2][0] = a;
+        t->mono_r[n2][1] = b;
+        t->mono_rf[n2][0] = float(a);
+        t->mono_rf[n2][1] = float(b);
+    }
 }
 
 int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chunks,
@@ -287,6 +280,18 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
             if (P.subs[size_t(s)].level == l) P.ref_by_level.push_back(s);
     }
     P.level_ref_begin[size_t(P.max_level) + 1] = int32_t(P.ref_by_level.size());
+    P.l2l_begin.assign(size_t(2 * P.max_level) + 1, 0);
+    for (int l = 0; l < P.max_level; ++l) {
+        for (int kind = 1; kind >= 0; --kind) {
+            P.l2l_begin[size_t(2 * l + (1 - kind))] = int32_t(P.l2l_tasks.size());
+            for (int i = P.level_ref_begin[size_t(l)]; i < P.level_ref_begin[size_t(l) + 1]; ++i) {
+                const int32_t ps = P.ref_by_level[size_t(i)];
+                for (int e = 0; e < 8; ++e)
+                    if (P.subs[size_t(P.subs[size_t(ps)].child[e])].kind == kind) P.l2l_tasks.push_back(ps * 8 + e);
+            }
+        }
+    }
+    P.l2l_begin[size_t(2 * P.max_level)] = int32_t(P.l2l_tasks.size());
     // top level under the all-pairs rule
     if (top_full) {
         for (int t = 0; t < n_trees; ++t) {
@@ -344,15 +349,9 @@ void build_items(HostPlan* Pp, int ngroups) {
     P.ngroups = ngroups;
     StencilTables tab;
     build_stencil_tables(&tab);
-    // estimated cost of an item, in refined-pair units
-    struct Costed { Item it; double cost; };
+    // estimated cost of an item, in refined-pair units, and its level
+    struct Costed { Item it; double cost; int level; };
     std::vector<Costed> all;
-    P.items_class.clear();
-    auto add = [&](const Item& it, double cost) {
-        P.items_class.push_back(it);
-        all.push_back({it, cost});
-    };
-    P.class_begin[IT_MP_REF] = 0;
     for (int32_t s : P.mp_ref) {
         const bool nearc = (P.subs[size_t(s)].flags & 1) != 0;
         for (int zt = 0; zt < NS; ++zt)
@@ -360,23 +359,50 @@ void build_items(HostPlan* Pp, int ngroups) {
                 int i0 = g * NDZ / ngroups, i1 = (g + 1) * NDZ / ngroups;
                 double n = 0;
                 for (int i = i0; i < i1; ++i) n += tab.mp_far_count[i] + (nearc ? tab.mp_near_count[i] : 0);
-                add(Item{IT_MP_REF, s, zt, g}, 64.0 * n + 2000.0);
+                all.push_back({Item{IT_MP_REF, s, zt, g}, 64.0 * n + 2000.0, P.subs[size_t(s)].level});
             }
     }
-    P.class_begin[IT_MP_LEAF] = int32_t(P.items_class.size());
     for (int32_t s : P.mp_leaf)
-        for (int zt = 0; zt < NS; ++zt) add(Item{IT_MP_LEAF, s, zt, 0}, 64.0 * 743.0 * 0.63 + 2000.0);
-    P.class_begin[IT_MONO] = int32_t(P.items_class.size());
-    for (int32_t s : P.mono_leaf) add(Item{IT_MONO, s, 0, 0}, 512.0 * 743.0 * 0.1 + 4000.0);
-    P.class_begin[IT_TOP] = int32_t(P.items_class.size());
+        for (int zt = 0; zt < NS; ++zt)
+            all.push_back({Item{IT_MP_LEAF, s, zt, 0}, 64.0 * 743.0 * 0.63 + 2000.0, P.subs[size_t(s)].level});
+    for (int32_t s : P.mono_leaf)
+        all.push_back({Item{IT_MONO, s, 0, 0}, 512.0 * 743.0 * 0.025 + 4000.0, P.subs[size_t(s)].level});
     for (size_t k = 0; k < P.top_items.size(); ++k) {
         const TopItem& ti = P.top_items[k];
-        add(Item{IT_TOP, int32_t(k), 0, 0}, 64.0 * double(ti.src_end - ti.src_begin) + 1000.0);
+        all.push_back({Item{IT_TOP, int32_t(k), 0, 0}, 64.0 * double(ti.src_end - ti.src_begin) + 1000.0, 0});
     }
-    P.class_begin[IT_KINDS] = int32_t(P.items_class.size());
+    // split level: the coarse levels below it carry at most a fifth of the work
+    std::vector<double> lc(size_t(P.max_level) + 1, 0.0);
+    double total = 0;
+    for (const Costed& c : all) {
+        lc[size_t(c.level)] += c.cost;
+        total += c.cost;
+    }
+    P.split = 0;
+    double below = 0;
+    for (int s = 1; s <= P.max_level; ++s) {
+        below += lc[size_t(s) - 1];
+        if (below <= 0.2 * total) P.split = s;
+    }
+    auto branch = [&](const Costed& c) { return c.level < P.split ? 1 : 0; };
+    P.items_class.clear();
+    for (int b = 0; b < 2; ++b) {
+        const int order[IT_KINDS] = {IT_MP_REF, IT_MP_LEAF, IT_MONO, IT_TOP};
+        for (int k : order) {
+            P.class_begin[b][k] = int32_t(P.items_class.size());
+            for (const Costed& c : all)
+                if (c.it.kind == k && branch(c) == b) P.items_class.push_back(c.it);
+        }
+        P.class_begin[b][IT_KINDS] = int32_t(P.items_class.size());
+    }
     std::stable_sort(all.begin(), all.end(), [](const Costed& a, const Costed& b) { return a.cost > b.cost; });
     P.items_lpt.clear();
-    for (const Costed& c : all) P.items_lpt.push_back(c.it);
+    for (int b = 0; b < 2; ++b) {
+        P.lpt_begin[b] = int32_t(P.items_lpt.size());
+        for (const Costed& c : all)
+            if (branch(c) == b) P.items_lpt.push_back(c.it);
+    }
+    P.lpt_begin[2] = int32_t(P.items_lpt.size());
 }
 
 }  // namespace fmmg

@@ -44,13 +44,21 @@ struct HostPlan {
     std::vector<int32_t> level_ref_begin;  // refined sub ids sorted by level: [l, l+1)
     std::vector<int32_t> ref_by_level;
     std::vector<int32_t> top_leaf;     // top-level leaves (output straight from own terms)
+    // downward tasks, parent sub id * 8 + child slot, grouped by parent level
+    // and child kind: level l's refined children are [l2l_begin[2l],
+    // l2l_begin[2l+1]), its leaf children [l2l_begin[2l+1], l2l_begin[2l+2])
+    std::vector<int32_t> l2l_tasks;
+    std::vector<int32_t> l2l_begin;
     int32_t n_slot3 = 0;               // leaves with refined neighbours (Lf3 slots)
 
-    // same-level work items for a given number of plane groups
+    // same-level work items for a given number of plane groups, in two
+    // branches: 0 = levels >= split (fine), 1 = levels < split (coarse)
     int ngroups = 1;
-    std::vector<Item> items_class;     // grouped by kind, in list order
-    int32_t class_begin[IT_KINDS + 1] = {0, 0, 0, 0, 0};
-    std::vector<Item> items_lpt;       // all items, largest estimated cost first
+    int split = 0;
+    std::vector<Item> items_class;     // grouped by branch, then kind, in list order
+    int32_t class_begin[2][IT_KINDS + 1] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
+    std::vector<Item> items_lpt;       // branch 0 then branch 1, each largest estimated cost first
+    int32_t lpt_begin[3] = {0, 0, 0};
 
     // top level under the all-pairs rule
     std::vector<int32_t> top_src;      // per tree, its level-0 sub ids (concatenated)
@@ -67,7 +75,9 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
                     HostPlan* out, std::string* err);
 
 // (Re)builds the work-item lists with ngroups (1..MAX_GROUPS) plane groups
-// per refined-target plane item.
+// per refined-target plane item.  The split level is the largest s <=
+// max_level whose levels below s carry at most a fifth of the estimated
+// same-level work (0: no coarse branch).
 void build_items(HostPlan* P, int ngroups);
 
 // Fills the canonical stencil tables.

@@ -70,6 +70,7 @@ def test_c0_forest_all_pairs_fp64():
 
 SHAPES = {"per_class_g1": dict(plane_groups=1), "per_class_g2": dict(plane_groups=2),
           "persistent_g2": dict(persistent=True, plane_groups=2),
+          "persistent_g1": dict(persistent=True, plane_groups=1),
           "persistent_g1_bpc1": dict(persistent=True, plane_groups=1, blocks_per_cu=1)}
 
 
@@ -306,6 +307,32 @@ def test_density_check_and_argument_errors():
             p.solve(r.float())
 
 
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g1"])
+def test_overlapped_coarse_branch_equals_one_stream(shape):
+    """The coarse levels on the second stream (eager and graph) give bitwise
+    the same result as one stream: every output has one writer and a fixed
+    summation order, whatever runs concurrently."""
+    cases = [wl.c1(), wl.small_amr(1), wl.small_amr(3), wl.c1(max_level=2)]
+    forked = 0
+    for W in cases:
+        t = W.trees[0]
+        r = torch.tensor(W.rho, dtype=torch.float64, device=DEV)
+        with fm.Plan([t], overlap=False, **SHAPES[shape]) as p1:
+            ref = [x.clone() for x in p1.solve(r)]
+            torch.cuda.synchronize()
+            assert p1.launch_shape()["overlap"] == 0
+        for graph in (False, True):
+            with fm.Plan([t], overlap=True, use_graph=graph, **SHAPES[shape]) as p2:
+                for rep in range(3):
+                    out = p2.solve(r)
+                    torch.cuda.synchronize()
+                    assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1]), (W.name, graph, rep)
+                sh = p2.launch_shape()
+                print(f"  {W.name}: split level {sh['split_level']}, overlap {sh['overlap']}", flush=True)
+                forked += sh["overlap"]
+    assert forked >= 2  # the uniform trees split (levels 0-1 coarse)
+
+
 def test_autotune_picks_a_shape_and_caches_it(tmp_path):
     W = wl.small_amr(1)
     t = W.trees[0]
@@ -327,7 +354,7 @@ def test_autotune_picks_a_shape_and_caches_it(tmp_path):
         torch.cuda.synchronize()
         sh2 = p2.launch_shape()
     assert sh2["from_cache"] == 1
-    for k in ("persistent", "plane_groups", "blocks_per_cu"):
+    for k in ("persistent", "plane_groups", "blocks_per_cu", "overlap", "split_level"):
         assert sh2[k] == sh[k]
     assert max(field_errors(phi2.cpu().numpy(), g2.cpu().numpy(), pr, gr)) < TOL64
 
@@ -346,4 +373,4 @@ def test_stage_timing_counts_launches():
         if pers:
             assert tm["launches"]["fused"] >= 1 and tm["launches"]["mp_refined"] == 0
         else:
-            assert tm["launches"]["mp_refined"] == 1 and tm["launches"]["fused"] == 0
+            assert tm["launches"]["mp_refined"] >= 1 and tm["launches"]["fused"] == 0
