@@ -102,8 +102,11 @@ typedef struct {
     int32_t timing;             /* 1 = eager solves record a hipEvent at every stage
                                    boundary on the solve's stream (fmmg_get_timings);
                                    not allowed together with use_graph                  */
-    int32_t plane_groups;       /* source-plane groups per refined-target item: 1 or 2
-                                   (each group writes its own partial sums); 0 = 2      */
+    int32_t plane_groups;       /* source-plane groups per refined-target item, 1..5
+                                   (the 10 source planes split into that many groups,
+                                   each writing its own partial sums); 0 = 2.  Partial
+                                   buffers are allocated for this many groups, or for
+                                   5 when autotune is on                                */
     int32_t blocks_per_cu;      /* persistent launch: resident blocks per compute unit;
                                    0 = the occupancy limit                              */
     int32_t autotune;           /* 1 = the first solve times the candidate launch shapes

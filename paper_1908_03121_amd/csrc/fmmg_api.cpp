@@ -87,6 +87,7 @@ struct fmmg_plan {
     int device = -1;
     int n_cu = 0;
     int max_bpc = 0;
+    int max_groups = MAX_GROUPS;   // plane groups the partial buffers are sized for
     fmmg_options opt;
     HostPlan hp;
     hipStream_t capture_stream = nullptr;
@@ -185,7 +186,8 @@ Ctx make_ctx(const fmmg_plan* p, hipStream_t st) {
 
 // Rebuilds and uploads the work items for a launch shape.
 fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int overlap, hipStream_t st) {
-    if (groups < 1 || groups > MAX_GROUPS) return fail(FMMG_EINVAL, "plane_groups must be 1 or 2");
+    if (groups < 1 || groups > p->max_groups)
+        return fail(FMMG_EINVAL, "plane_groups must be 1.." + std::to_string(p->max_groups) + " for this plan");
     if (bpc < 0) return fail(FMMG_EINVAL, "blocks_per_cu must be >= 0");
     if (bpc == 0 || bpc > p->max_bpc) bpc = p->max_bpc;
     if (groups != p->hp.ngroups) {
@@ -219,9 +221,10 @@ fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int o
 // masses of level-l leaves); the downward task of a level-l parent needs its
 // own items (level l), its inherited part (the level l - 1 task) and, for
 // leaf children, their own items (level l + 1).  Overlapped order:
-//   caller's stream: upward levels max-1 .. s-1 | fork | fine items | join |
+//   caller's stream: upward levels max-1 .. s-1 (.. s when level s has no
+//                    leaves) | fork | fine items | join |
 //                    leaf children of level s-1, downward levels s .. max-1
-//   side stream:     (after fork) upward levels s-2 .. 0, parentless-leaf
+//   side stream:     (after fork) the remaining upward levels, parentless-leaf
 //                    masses, coarse items, parentless-leaf output, refined
 //                    children of levels 0 .. s-1, leaf children of levels
 //                    0 .. s-2 | join
@@ -299,11 +302,14 @@ int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, h
             l2l(a, l, 0);
         }
     } else {
-        for (int l = hp.max_level - 1; l >= s - 1; --l) m2m(a, l);
+        // the fine items need the records of levels >= s and the masses of
+        // leaves at levels >= s (level s's come from the level s-1 step)
+        const int lo = hp.level_leaves[size_t(s)] > 0 ? s - 1 : s;
+        for (int l = hp.max_level - 1; l >= lo; --l) m2m(a, l);
         (void)hipEventRecord(p->ev_fork, st);
         (void)hipStreamWaitEvent(side, p->ev_fork, 0);
         items(a, 0);
-        for (int l = s - 2; l >= 0; --l) m2m(c, l);
+        for (int l = lo - 1; l >= 0; --l) m2m(c, l);
         launch_p2m_top(c, p->d_top_leaf, n_tl);
         cnt(n_tl);
         items(c, 1);
@@ -357,6 +363,7 @@ bool cache_lookup(const char* path, const std::string& sig, int* pers, int* grou
         if (std::sscanf(s, " {\"persistent\": %d, \"plane_groups\": %d, \"blocks_per_cu\": %d, \"overlap\": %d",
                         &a, &b, &c, &d) == 4 &&
             (a == 0 || a == 1) && b >= 1 && b <= MAX_GROUPS && c >= 0 && (d == 0 || d == 1)) {
+            // (a group count above the plan's buffers is rejected by apply_shape)
             *pers = a;
             *groups = b;
             *bpc = c;
@@ -410,7 +417,8 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
     struct Cand { int pers, groups, bpc, ovl; };
     std::vector<Cand> cands;
     for (int ov = 0; ov <= (p->opt.overlap && p->hp.split > 0 ? 1 : 0); ++ov)
-        for (int gr = 1; gr <= MAX_GROUPS; ++gr) {
+        for (int gr : {1, 2, 3, 5}) {
+            if (gr > p->max_groups) continue;
             cands.push_back({0, gr, 0, ov});
             for (int b = 1; b <= p->max_bpc; ++b) cands.push_back({1, gr, b, ov});
         }
@@ -518,7 +526,7 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         else if (o.top_mode != FMMG_TOP_FULL && o.top_mode != FMMG_TOP_STENCIL_ONLY) bad = "bad top_mode";
         else if (o.timing && o.use_graph) bad = "timing needs eager launches (use_graph = 0)";
         else if (o.timing && o.autotune) bad = "timing and autotune cannot be combined";
-        else if (o.plane_groups < 0 || o.plane_groups > MAX_GROUPS) bad = "plane_groups must be 0, 1 or 2";
+        else if (o.plane_groups < 0 || o.plane_groups > MAX_GROUPS) bad = "plane_groups must be 0..5";
         else if (o.blocks_per_cu < 0) bad = "blocks_per_cu must be >= 0";
         if (!bad.empty()) { release(p); return fail(FMMG_EINVAL, bad); }
         hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
@@ -539,8 +547,10 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         int rc = build_host_plan(tv.data(), n_trees, o.top_mode == FMMG_TOP_FULL, TOP_CHUNKS, &p->hp, &err);
         if (rc) { release(p); return fail(rc == -2 ? FMMG_ETREE : FMMG_EINVAL, err); }
         HostPlan& hp = p->hp;
-        // item capacity: the largest list over the plane-group choices
-        build_items(&hp, MAX_GROUPS);
+        // partial buffers and item capacity for the plane-group counts this plan may use
+        p->max_groups = (o.plane_groups > 0 && !o.autotune) ? o.plane_groups : MAX_GROUPS;
+        if (!o.autotune && o.plane_groups == 0) p->max_groups = 2;
+        build_items(&hp, p->max_groups);
         p->items_capacity = hp.items_class.size();
         fmmg_status s;
 #define UP(dst, src, cap, what) if ((s = dev_upload(&(dst), (src), (cap), st, what)) != FMMG_OK) { release(p); return s; }
@@ -559,7 +569,7 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
 #define AL(dst, n, what) if ((s = dev_alloc(&(dst), (n), what)) != FMMG_OK) { release(p); return s; }
         AL(p->d_mass, nl * NCELL, "leaf masses");
         AL(p->d_rec, nr * NREC * NCELL, "multipole records");
-        AL(p->d_Lp, size_t(MAX_GROUPS) * nr * NLOC * NCELL, "refined own terms");
+        AL(p->d_Lp, size_t(p->max_groups) * nr * NLOC * NCELL, "refined own terms");
         AL(p->d_Lr, nr * NLOC * NCELL, "refined expansions");
         AL(p->d_Lf, nl * NLEAF * NCELL, "leaf terms");
         AL(p->d_Lf3, size_t(hp.n_slot3) * NLEAF * NCELL, "leaf terms from refined sources");
@@ -591,7 +601,7 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         }
         p->hp.ngroups = 0;  // force the first item upload
         memset(&p->shape, 0, sizeof(p->shape));
-        s = apply_shape(p, o.persistent ? 1 : 0, o.plane_groups ? o.plane_groups : MAX_GROUPS, o.blocks_per_cu,
+        s = apply_shape(p, o.persistent ? 1 : 0, o.plane_groups ? o.plane_groups : 2, o.blocks_per_cu,
                         o.overlap, st);
         if (s != FMMG_OK) { release(p); return s; }
         e = hipStreamSynchronize(st);

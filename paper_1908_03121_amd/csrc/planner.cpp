@@ -280,6 +280,9 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
             if (P.subs[size_t(s)].level == l) P.ref_by_level.push_back(s);
     }
     P.level_ref_begin[size_t(P.max_level) + 1] = int32_t(P.ref_by_level.size());
+    P.level_leaves.assign(size_t(P.max_level) + 1, 0);
+    for (const SubDev& S : P.subs)
+        if (S.kind == 0) P.level_leaves[size_t(S.level)]++;
     P.l2l_begin.assign(size_t(2 * P.max_level) + 1, 0);
     for (int l = 0; l < P.max_level; ++l) {
         for (int kind = 1; kind >= 0; --kind) {

@@ -44,6 +44,7 @@ struct HostPlan {
     std::vector<int32_t> level_ref_begin;  // refined sub ids sorted by level: [l, l+1)
     std::vector<int32_t> ref_by_level;
     std::vector<int32_t> top_leaf;     // top-level leaves (output straight from own terms)
+    std::vector<int32_t> level_leaves; // number of leaf sub-grids per level
     // downward tasks, parent sub id * 8 + child slot, grouped by parent level
     // and child kind: level l's refined children are [l2l_begin[2l],
     // l2l_begin[2l+1]), its leaf children [l2l_begin[2l+1], l2l_begin[2l+2])

@@ -71,6 +71,8 @@ def test_c0_forest_all_pairs_fp64():
 SHAPES = {"per_class_g1": dict(plane_groups=1), "per_class_g2": dict(plane_groups=2),
           "persistent_g2": dict(persistent=True, plane_groups=2),
           "persistent_g1": dict(persistent=True, plane_groups=1),
+          "per_class_g3": dict(plane_groups=3),
+          "persistent_g5": dict(persistent=True, plane_groups=5),
           "persistent_g1_bpc1": dict(persistent=True, plane_groups=1, blocks_per_cu=1)}
 
 
@@ -145,7 +147,7 @@ def test_single_leaf_and_single_refined_root():
     assert max(field_errors(phi, g, pr, gr)) < TOL64
 
 
-@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2", "per_class_g3", "persistent_g5"])
 def test_c1_full_size_fp64_graph(shape):
     """Uniform level-3 polytrope (64^3 leaf cells), in the launch
     configurations the benchmark may time (captured graph)."""
