@@ -160,7 +160,7 @@ def main():
     ap.add_argument("--bpc", type=int, default=0,
                     help="--profile: blocks per CU of the persistent launch (0 = occupancy limit)")
     ap.add_argument("--shape", default="per_class_g2",
-                    choices=["per_class_g1", "per_class_g2", "persistent_g1", "persistent_g2"])
+                    choices=[f"{k}_g{g}" for k in ("per_class", "persistent") for g in (1, 2, 3, 5)])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
@@ -219,14 +219,14 @@ def main():
         flops = algorithmic_flops(st_e)
         kms = stages["fused"]
         units = sum(p) + st_e["pairs_top"]
-        tkey = "k_persist_fp64_c1"
+        tkey = f"k_persist_fp64_c1_g{shape['plane_groups']}_bpc{shape['blocks_per_cu']}"
     else:
         kname = (f"k_class<refined-target multipole, fp64> (classes 1+2; {launches['mp_refined']} "
                  "launch(es) per solve: fine and coarse branch)")
         flops = (p[0] + p[1]) * FLOP_PAIR_REFINED
         kms = stages["mp_refined"]
         units = p[0] + p[1]
-        tkey = "k_class_mp_ref_fp64_c1"
+        tkey = f"k_class_mp_ref_fp64_c1_g{shape['plane_groups']}"
     achieved = flops / (kms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
                 "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic_entry(tkey),
