@@ -497,6 +497,9 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     double* red = reinterpret_cast<double*>(smem);
     {
         double v[NLOC];
+        // a target without mass gets no correction term (its descendants
+        // carry no mass either, so no momentum is involved)
+        if (!(mA > 0)) acc.s[0] = acc.s[1] = acc.s[2] = 0.0;
         acc.out(v);
 #pragma unroll
         for (int k = 0; k < NLOC; ++k) red[(w * NLOC + k) * 64 + cl] = v[k];
@@ -611,37 +614,50 @@ __device__ __forceinline__ void mono_item(const Ctx& cx, int sid, unsigned char*
     const SubDev& T = cx.subs[sid];
     if (t < 27) nb[t] = T.nbr[t];
     __syncthreads();
-    // stage the 18^3 mass box, 8 cells per thread at a time with all their
-    // loads in flight together (unconditional, from a valid address)
-    constexpr int NBOX = PW * PW * PW, PER = (NBOX + 255) / 256;
+    // stage the 18^3 mass box by row segments: a window row (wy, wz) of 18
+    // cells is three runs, 5 cells of the -x neighbour, 8 of the centre column,
+    // 5 of the +x neighbour; a thread takes one run (up to 8 contiguous
+    // masses) per unit, two units at a time with all their loads in flight
+    // (unconditional, from a valid address, then selected)
+    constexpr int NUNIT = PW * PW * 3, PER = (NUNIT + 255) / 256;
 #pragma unroll
-    for (int u0 = 0; u0 < PER; u0 += 8) {
-        double v[8];
-        int dst[8];
+    for (int u0 = 0; u0 < PER; u0 += 2) {
+        double v[2][NS];
+        int dst[2], len[2];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            dst[u] = -1;
-            v[u] = 0;
+        for (int u = 0; u < 2; ++u) {
+            len[u] = 0;
+            dst[u] = 0;
             if (u0 + u >= PER) continue;  // resolved at compile time
-            // no branch around the load: the tail's excess cells read cell 0
-            const int cr0 = t + (u0 + u) * 256;
-            const bool ok = cr0 < NBOX;
-            const int cr = ok ? cr0 : 0;
-            const int wx = cr % PW, wy = (cr / PW) % PW, wz = cr / (PW * PW);
-            const int lx = wx - REACH, ly = wy - REACH, lz = wz - REACH;
-            const int ox = lx < 0 ? -1 : (lx >= NS ? 1 : 0);
+            const int un0 = t + (u0 + u) * 256;
+            const bool ok = un0 < NUNIT;
+            const int un = ok ? un0 : 0;
+            const int part = un % 3, row = un / 3;
+            const int wy = row % PW, wz = row / PW;
+            const int ly = wy - REACH, lz = wz - REACH;
+            const int ox = part - 1;
             const int oy = ly < 0 ? -1 : (ly >= NS ? 1 : 0);
             const int oz = lz < 0 ? -1 : (lz >= NS ? 1 : 0);
             const int code = nb[(ox + 1) * 9 + (oy + 1) * 3 + (oz + 1)];
             const bool leaf = code >= 0 && (code & 1) == 0;
-            const int cq = ((lz - NS * oz) * NS + (ly - NS * oy)) * NS + (lx - NS * ox);
-            const double m = cx.mass[leaf ? size_t(code >> 1) * NCELL + cq : size_t(0)];
-            v[u] = leaf ? m : 0.0;
-            dst[u] = ok ? wz * PSLOTS + wy * PRS + wx : -1;
+            const int x0 = part == 0 ? NS - REACH : 0;  // first neighbour-local x of the run
+            const double* src = cx.mass + (leaf ? size_t(code >> 1) * NCELL +
+                                                      ((lz - NS * oz) * NS + (ly - NS * oy)) * NS + x0
+                                                : size_t(0));
+            const int n = part == 1 ? NS : REACH;
+#pragma unroll
+            for (int i = 0; i < NS; ++i) {
+                const double m = src[i < n ? i : 0];
+                v[u][i] = leaf ? m : 0.0;
+            }
+            len[u] = ok ? n : 0;
+            dst[u] = wz * PSLOTS + wy * PRS + (part == 0 ? 0 : part == 1 ? REACH : REACH + NS);
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (dst[u] >= 0) box[dst[u]] = P(v[u]);
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int i = 0; i < NS; ++i)
+                if (i < len[u]) box[dst[u] + i] = P(v[u][i]);
     }
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -761,6 +777,9 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
     double* red = reinterpret_cast<double*>(smem);
     {
         double v[NLOC];
+        // a target without mass gets no correction term (its descendants
+        // carry no mass either, so no momentum is involved)
+        if (!(mA > 0)) acc.s[0] = acc.s[1] = acc.s[2] = 0.0;
         acc.out(v);
 #pragma unroll
         for (int k = 0; k < NLOC; ++k) red[(w * NLOC + k) * 64 + lane] = v[k];

@@ -200,6 +200,56 @@ def test_batched_trees_equal_each_tree_alone(shape):
     assert st["n_trees"] == 4
 
 
+def test_c4_full_batch_autotuned_sampled(tmp_path):
+    """The 16-tree binary-star batch in the configuration the benchmark times
+    (autotuned launch shape, graph replay), each tree sampled against the
+    oracle, with its force and torque residuals."""
+    W = wl.c4()
+    r = torch.tensor(W.rho, dtype=torch.float64, device=DEV)
+    with fm.Plan(W.trees, autotune=True, tuning_cache=str(tmp_path / "tune.json"), use_graph=True) as p:
+        phi_t, g_t = p.solve(r)
+        p.solve(r, phi_t, g_t)  # a replay of the captured graph
+        torch.cuda.synchronize()
+        sh = p.launch_shape()
+        st = p.stats()
+    print(f"  c4 shape {sh}", flush=True)
+    assert st["n_trees"] == 16
+    phi, g = phi_t.cpu().numpy(), g_t.cpu().numpy()
+    rng = np.random.default_rng(4)
+    off = 0
+    worst = 0.0
+    for k, t in enumerate(W.trees):
+        n = t.n_leaves
+        rho_k = W.rho[off:off + n]
+        li = rng.integers(0, n, 150).astype(np.int32)
+        ci = rng.integers(0, 512, 150).astype(np.int32)
+        ps, gs = oracle.solve_sampled(t, rho_k, li, ci)
+        e_phi = np.abs(phi[off + li, ci] - ps).max() / np.abs(ps).max()
+        e_g = np.abs(g[off + li, :, ci] - gs).max() / np.abs(gs).max()
+        worst = max(worst, e_phi, e_g)
+        assert e_phi < TOL64 and e_g < TOL64, (k, e_phi, e_g)
+        f, tq = residuals(t, rho_k, g[off:off + n])
+        assert f < 1e-12 and tq < 1e-12, (k, f, tq)
+        off += n
+    print(f"  c4 worst sampled error {worst:.3e}", flush=True)
+
+
+def test_zero_density_regions():
+    """Cells without mass: their centre is their centre of mass and they act
+    on nothing; an all-zero field gives exactly zero."""
+    W = wl.small_amr(2)
+    t = W.trees[0]
+    rho = W.rho.copy()
+    rho[::2] = 0.0                        # every other leaf empty
+    rho[1, :, :, :4] = 0.0                # half of another leaf
+    phi, g, _ = run([t], rho)
+    pr, gr = oracle.solve(t, rho)
+    assert np.isfinite(phi).all() and np.isfinite(g).all()
+    assert max(field_errors(phi, g, pr, gr)) < TOL64
+    phi0, g0, _ = run([t], np.zeros_like(rho))
+    assert not phi0.any() and not g0.any()
+
+
 @pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
 def test_graph_replays_match_eager(shape):
     W = wl.small_amr(5)
