@@ -333,7 +333,8 @@ __global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__
 // ---------------------------------------------------------------------------
 // LDS of one item block: the largest of the multipole plane window (16
 // records x 18 rows of 20 cells + leaf flags), the monopole mass box (18
-// planes x 18 rows of 20 cells) and the 4-wave reduction buffer (doubles).
+// planes x 18 rows of 20 cells), the 4-wave reduction buffer (doubles) and
+// the top-level source tile, followed by the target's 27 neighbour codes.
 template <typename P>
 struct Smem {
     static constexpr int PLANE = NREC * PSLOTS * int(sizeof(P)) + PSLOTS;
@@ -697,9 +698,10 @@ __device__ __forceinline__ void mono_item(const Ctx& cx, int sid, unsigned char*
 }
 
 // Top-level tile (all-pairs rule): 64 targets (one plane of a top-level
-// sub-grid) against a chunk of the tree's top-level cells; the 4 waves take
-// every fourth source and their sums are added in a fixed order.  The source
-// index is uniform across a wave, so source data come through scalar loads.
+// sub-grid) against a chunk of the tree's top-level cells; the sources are
+// staged through LDS 256 at a time, the 4 waves take every fourth source
+// (one LDS address per wave: broadcast reads) and their sums are added in a
+// fixed order.
 template <bool MIXED>
 __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsigned char* smem) {
     using P = typename std::conditional<MIXED, float, double>::type;
