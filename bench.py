@@ -54,7 +54,7 @@ def time_form(fm, torch, trees, rho_np, precision, steps, warmup, use_graph=True
     dev = torch.device("cuda:0")
     rho = torch.tensor(rho_np, dtype=torch.float64, device=dev)
     with fm.Plan(trees, precision=precision, use_graph=use_graph, autotune=True,
-                 tuning_cache=TUNE_CACHE) as plan:
+                 tuning_cache=TUNE_CACHE, overlap=2) as plan:
         phi, g = plan.solve(rho)
         shape = plan.launch_shape()
         for _ in range(warmup):

@@ -122,8 +122,12 @@ typedef struct {
                                    run on a second, plan-owned stream, overlapping
                                    the finer levels' same-level step; the solve still
                                    completes in order on the caller's stream.
+                                   2 = as 1, and with one launch per class the fine
+                                   levels' monopole class runs on a third plan-owned
+                                   stream beside their multipole classes.
                                    0 = everything on the caller's stream.  Timing
-                                   solves always run on one stream.                     */
+                                   solves always run on one stream.  With autotune,
+                                   this is the largest value tried.                     */
 } fmmg_options;
 
 /* Stages of one solve, in launch order. */
@@ -152,7 +156,8 @@ typedef struct {
     int32_t blocks_per_cu;
     int32_t from_cache;         /* 1 if the shape came from the tuning cache           */
     double tuned_ms;            /* best solve time measured by the tuner, or 0         */
-    int32_t overlap;            /* 1 if the coarse levels run on the second stream     */
+    int32_t overlap;            /* 1 if the coarse levels run on the second stream, 2 if
+                                   also the fine monopole class runs on a third one      */
     int32_t split_level;        /* levels below this one form the coarse branch        */
 } fmmg_launch_shape;
 

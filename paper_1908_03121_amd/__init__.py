@@ -247,7 +247,7 @@ class Plan:
                  G: float = 1.0, angular_correction: bool = True, use_graph: bool = False,
                  persistent: bool = False, timing: bool = False, plane_groups: int = 0,
                  blocks_per_cu: int = 0, autotune: bool = False, tuning_cache: str | None = None,
-                 overlap: bool = True, stream=None):
+                 overlap: int = 1, stream=None):
         opt = fmmg_default_options()
         opt.precision = {"fp64": FMMG_FP64, "mixed": FMMG_MIXED}[precision]
         opt.top_mode = {"full": FMMG_TOP_FULL, "stencil": FMMG_TOP_STENCIL_ONLY}[top_mode]
@@ -261,7 +261,7 @@ class Plan:
         opt.autotune = int(bool(autotune))
         self._cache = tuning_cache.encode() if tuning_cache else None
         opt.tuning_cache = self._cache
-        opt.overlap = int(bool(overlap))
+        opt.overlap = int(overlap)  # 0, 1 (True) or 2
         self._h = fmmg_plan_create(trees, opt, stream)
         self.n_leaves = fmmg_plan_n_leaves(self._h)
 

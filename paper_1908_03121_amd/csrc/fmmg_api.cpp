@@ -92,7 +92,8 @@ struct fmmg_plan {
     HostPlan hp;
     hipStream_t capture_stream = nullptr;
     hipStream_t side_stream = nullptr;     // coarse branch of an overlapped solve
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t mono_stream = nullptr;     // fine monopole class (overlap 2)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join_mono = nullptr;
     SubDev* d_subs = nullptr;
     int32_t* d_leaf_sub = nullptr;
     int32_t* d_ref_by_level = nullptr;
@@ -157,6 +158,8 @@ void release(fmmg_plan* p) {
     if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+    if (p->mono_stream) (void)hipStreamDestroy(p->mono_stream);
+    if (p->ev_join_mono) (void)hipEventDestroy(p->ev_join_mono);
     delete p;
 }
 
@@ -201,7 +204,8 @@ fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int o
         }
         HIP_TRY(hipStreamSynchronize(st), "item upload");
     }
-    overlap = overlap && p->hp.split > 0 ? 1 : 0;
+    if (overlap < 0 || overlap > 2) return fail(FMMG_EINVAL, "overlap must be 0, 1 or 2");
+    if (p->hp.split == 0) overlap = 0;
     if (p->shape.persistent != persistent || p->shape.plane_groups != groups || p->shape.blocks_per_cu != bpc ||
         p->shape.overlap != overlap)
         drop_graph(p);
@@ -308,7 +312,20 @@ int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, h
         for (int l = hp.max_level - 1; l >= lo; --l) m2m(a, l);
         (void)hipEventRecord(p->ev_fork, st);
         (void)hipStreamWaitEvent(side, p->ev_fork, 0);
-        items(a, 0);
+        const bool mono_apart = p->shape.overlap == 2 && !p->shape.persistent;
+        if (mono_apart) {
+            // the fine monopole class on a third stream, beside the fine
+            // multipole classes (their blocks fill each other's idle slots)
+            Ctx m = a;
+            m.st = p->mono_stream;
+            (void)hipStreamWaitEvent(p->mono_stream, p->ev_fork, 0);
+            one_class(m, 0, IT_MONO);
+            (void)hipEventRecord(p->ev_join_mono, p->mono_stream);
+            for (int k : kinds)
+                if (k != IT_MONO) one_class(a, 0, k);
+        } else {
+            items(a, 0);
+        }
         for (int l = lo - 1; l >= 0; --l) m2m(c, l);
         launch_p2m_top(c, p->d_top_leaf, n_tl);
         cnt(n_tl);
@@ -319,6 +336,7 @@ int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, h
         for (int l = 0; l < s - 1; ++l) l2l(c, l, 0);
         (void)hipEventRecord(p->ev_join, side);
         (void)hipStreamWaitEvent(st, p->ev_join, 0);
+        if (mono_apart) (void)hipStreamWaitEvent(st, p->ev_join_mono, 0);
         l2l(a, s - 1, 0);
         for (int l = s; l < hp.max_level; ++l) {
             l2l(a, l, 1);
@@ -362,7 +380,7 @@ bool cache_lookup(const char* path, const std::string& sig, int* pers, int* grou
         const char* s = line.c_str() + at + key.size();
         if (std::sscanf(s, " {\"persistent\": %d, \"plane_groups\": %d, \"blocks_per_cu\": %d, \"overlap\": %d",
                         &a, &b, &c, &d) == 4 &&
-            (a == 0 || a == 1) && b >= 1 && b <= MAX_GROUPS && c >= 0 && (d == 0 || d == 1)) {
+            (a == 0 || a == 1) && b >= 1 && b <= MAX_GROUPS && c >= 0 && d >= 0 && d <= 2) {
             // (a group count above the plan's buffers is rejected by apply_shape)
             *pers = a;
             *groups = b;
@@ -416,10 +434,12 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
     }
     struct Cand { int pers, groups, bpc, ovl; };
     std::vector<Cand> cands;
-    for (int ov = 0; ov <= (p->opt.overlap && p->hp.split > 0 ? 1 : 0); ++ov)
+    const int max_ov = p->hp.split > 0 ? p->opt.overlap : 0;
+    for (int ov = 0; ov <= max_ov; ++ov)
         for (int gr : {1, 2, 3, 5}) {
             if (gr > p->max_groups) continue;
             cands.push_back({0, gr, 0, ov});
+            if (ov == 2) continue;  // the third stream applies to per-class launches only
             for (int b = 1; b <= p->max_bpc; ++b) cands.push_back({1, gr, b, ov});
         }
     hipEvent_t e0, e1;
@@ -528,6 +548,7 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         else if (o.timing && o.autotune) bad = "timing and autotune cannot be combined";
         else if (o.plane_groups < 0 || o.plane_groups > MAX_GROUPS) bad = "plane_groups must be 0..5";
         else if (o.blocks_per_cu < 0) bad = "blocks_per_cu must be >= 0";
+        else if (o.overlap < 0 || o.overlap > 2) bad = "overlap must be 0, 1 or 2";
         if (!bad.empty()) { release(p); return fail(FMMG_EINVAL, bad); }
         hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
         hipError_t e = hipGetDevice(&p->device);
@@ -582,6 +603,8 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         e = hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->mono_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join_mono, hipEventDisableTiming);
         if (e != hipSuccess) { release(p); return hip_fail(e, "second stream"); }
         e = hipMalloc(reinterpret_cast<void**>(&p->d_bad), sizeof(unsigned long long));
         if (e != hipSuccess) { release(p); return fail(FMMG_ENOMEM, "hipMalloc flag"); }
