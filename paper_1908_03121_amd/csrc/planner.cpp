@@ -355,19 +355,39 @@ void build_items(HostPlan* Pp, int ngroups) {
     // estimated cost of an item, in refined-pair units, and its level
     struct Costed { Item it; double cost; int level; };
     std::vector<Costed> all;
+    // a source plane with no usable neighbour among the 9 at its z offset is
+    // skipped by the kernels; the estimates count the planes they visit
+    auto plane_used = [&](const SubDev& S, int zs, bool refined_only) {
+        const int oz = zs < 0 ? -1 : (zs >= NS ? 1 : 0);
+        for (int o = 0; o < 9; ++o) {
+            const int code = S.nbr[(o / 3) * 9 + (o % 3) * 3 + (oz + 1)];
+            if (code >= 0 && (!refined_only || (code & 1))) return true;
+        }
+        return false;
+    };
     for (int32_t s : P.mp_ref) {
-        const bool nearc = (P.subs[size_t(s)].flags & 1) != 0;
+        const SubDev& S = P.subs[size_t(s)];
+        const bool nearc = (S.flags & 1) != 0;
         for (int zt = 0; zt < NS; ++zt)
             for (int g = 0; g < ngroups; ++g) {
                 int i0 = g * NDZ / ngroups, i1 = (g + 1) * NDZ / ngroups;
                 double n = 0;
-                for (int i = i0; i < i1; ++i) n += tab.mp_far_count[i] + (nearc ? tab.mp_near_count[i] : 0);
-                all.push_back({Item{IT_MP_REF, s, zt, g}, 64.0 * n + 2000.0, P.subs[size_t(s)].level});
+                for (int i = i0; i < i1; ++i)
+                    if (plane_used(S, zt + (1 - 2 * (zt & 1)) * (DZ0 + i), false))
+                        n += tab.mp_far_count[i] + (nearc ? tab.mp_near_count[i] : 0);
+                all.push_back({Item{IT_MP_REF, s, zt, g}, 64.0 * n + 2000.0, S.level});
             }
     }
-    for (int32_t s : P.mp_leaf)
-        for (int zt = 0; zt < NS; ++zt)
-            all.push_back({Item{IT_MP_LEAF, s, zt, 0}, 64.0 * 743.0 * 0.63 + 2000.0, P.subs[size_t(s)].level});
+    for (int32_t s : P.mp_leaf) {
+        const SubDev& S = P.subs[size_t(s)];
+        for (int zt = 0; zt < NS; ++zt) {
+            double n = 0;
+            for (int i = 0; i < NDZ; ++i)
+                if (plane_used(S, zt + (1 - 2 * (zt & 1)) * (DZ0 + i), true))
+                    n += tab.mp_far_count[i] + tab.mp_near_count[i];
+            all.push_back({Item{IT_MP_LEAF, s, zt, 0}, 64.0 * n * 0.68 + 2000.0, S.level});
+        }
+    }
     for (int32_t s : P.mono_leaf)
         all.push_back({Item{IT_MONO, s, 0, 0}, 512.0 * 743.0 * 0.025 + 4000.0, P.subs[size_t(s)].level});
     for (size_t k = 0; k < P.top_items.size(); ++k) {
@@ -388,6 +408,9 @@ void build_items(HostPlan* Pp, int ngroups) {
         if (below <= 0.2 * total) P.split = s;
     }
     auto branch = [&](const Costed& c) { return c.level < P.split ? 1 : 0; };
+    // class lists in sub-grid order (measured no slower than largest first,
+    // since neighbouring items share sources in the caches); the persistent
+    // list largest estimated cost first
     P.items_class.clear();
     for (int b = 0; b < 2; ++b) {
         const int order[IT_KINDS] = {IT_MP_REF, IT_MP_LEAF, IT_MONO, IT_TOP};

@@ -273,6 +273,30 @@ def test_graph_replays_match_eager(shape):
         assert pg.stats()["solves"] == 4
 
 
+def test_graph_recaptures_for_new_buffers_on_a_side_stream():
+    """A graph plan used on a non-default stream with two alternating output
+    buffers: every solve lands in its own buffers, in stream order."""
+    W = wl.small_amr(3)
+    t = W.trees[0]
+    pr, gr = oracle.solve(t, W.rho)
+    r = torch.tensor(W.rho, dtype=torch.float64, device=DEV)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    outs = [(torch.empty((W.n_leaves, 512), dtype=torch.float64, device=DEV),
+             torch.empty((W.n_leaves, 3, 512), dtype=torch.float64, device=DEV)) for _ in range(2)]
+    with fm.Plan([t], use_graph=True, persistent=True) as p:
+        with torch.cuda.stream(s):
+            for rep in range(4):
+                phi, g = outs[rep % 2]
+                phi.fill_(float("nan"))
+                g.fill_(float("nan"))
+                p.solve(r, phi, g, stream=s)
+        s.synchronize()
+        assert p.stats()["solves"] == 4
+    for phi, g in outs:
+        assert max(field_errors(phi.cpu().numpy(), g.cpu().numpy(), pr, gr)) < TOL64
+
+
 @pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
 def test_repeat_solves_are_bitwise_deterministic(shape):
     """Every output is written by one work item in a fixed order, so even the
