@@ -94,8 +94,9 @@ typedef struct {
     double G;                   /* gravitational constant, default 1.0                  */
     int32_t angular_correction; /* 1 (default) | 0 = uncorrected result (tests only)    */
     int32_t use_graph;          /* 1 = capture the launch sequence in a hipGraph on the
-                                   first solve and replay it (re-captured when the
-                                   rho/phi/g pointers or the stream change); 0 = eager  */
+                                   first solve and replay it on the solve's stream
+                                   (re-captured when the rho/phi/g pointers change);
+                                   0 = eager                                            */
     int32_t persistent;         /* 1 = same-level step as one persistent launch over a
                                    work list of all classes and trees; 0 = one launch
                                    per class                                            */
