@@ -78,6 +78,31 @@ def time_form(fm, torch, trees, rho_np, precision, steps, warmup, use_graph=True
     return out, phi.cpu().numpy(), g.cpu().numpy(), st
 
 
+def time_paper_model(fm, torch, trees, rho_np, precision, steps, warmup, groups, ref, streams=128):
+    """The paper's execution model (Sec. 5.1) on the same work items: eager
+    solves with one launch per target sub-grid and class, round-robin over a
+    pool of `streams` streams.  `ref` = (phi, g) of the default shape with the
+    same plane groups, which it must reproduce bitwise."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    rho = torch.tensor(rho_np, dtype=torch.float64, device=dev)
+    with fm.Plan(trees, precision=precision, plane_groups=groups, launch_streams=streams) as plan:
+        phi, g = plan.solve(rho)
+        for _ in range(warmup):
+            plan.solve(rho, phi, g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.solve(rho, phi, g)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        st = plan.stats()
+    same = bool(np.array_equal(phi.cpu().numpy(), ref[0]) and np.array_equal(g.cpu().numpy(), ref[1]))
+    return {"ms_per_step": dt * 1e3, "cell_interactions_per_s": st["total_pairs"] / dt,
+            "launches_per_step": st["launches"], "streams": streams, "plane_groups": groups,
+            "launch": "eager", "bitwise_equal_to_default_shape": same}
+
+
 def stage_times(fm, torch, trees, rho_np, precision, steps, warmup, shape):
     """Eager solves in the given launch shape with HIP events at every stage
     boundary on the solve's stream."""
@@ -241,6 +266,12 @@ def main():
         forms["c1_fp64"]["mono_kernel_tflops"] = p[2] * FLOP_PAIR_MONO / (mono_ms * 1e-3) / 1e12
     forms["c1_fp64"]["residual_force_torque"] = residuals(np, c1.trees, c1.rho, g64)
 
+    log("c1 fp64, the paper's per-sub-grid launch model (128 streams, eager)")
+    pm = time_paper_model(fm, torch, c1.trees, c1.rho, "fp64", K, W, shape["plane_groups"], (phi64, g64))
+    pm["default_shape_speedup"] = pm["ms_per_step"] / head["ms_per_step"]
+    log(f"  {pm['ms_per_step']:.3f} ms/step, {pm['launches_per_step']} launches")
+    forms["c1_fp64_paper_launch_model"] = pm
+
     log("c1 mixed (graph)")
     mixed, phim, gm, _ = time_form(fm, torch, c1.trees, c1.rho, "mixed", K, W)
     mixed["err_vs_fp64"] = field_err(np, phim, gm, phi64, g64)
@@ -259,6 +290,13 @@ def main():
             else:
                 r["err_vs_fp64"] = field_err(np, p_, g_, *ref)
             forms["c2_" + prec] = r
+            if prec == "fp64":
+                log("c2 fp64, the paper's per-sub-grid launch model (128 streams, eager)")
+                pm = time_paper_model(fm, torch, c2.trees, c2.rho, "fp64", K, W,
+                                      r["launch_shape"]["plane_groups"], ref)
+                pm["default_shape_speedup"] = pm["ms_per_step"] / r["ms_per_step"]
+                log(f"  {pm['ms_per_step']:.3f} ms/step, {pm['launches_per_step']} launches")
+                forms["c2_fp64_paper_launch_model"] = pm
         log("generating c4 (16 binary-star octrees)")
         c4 = wl.c4()
         for prec in ("fp64", "mixed"):

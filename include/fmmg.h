@@ -129,6 +129,17 @@ typedef struct {
                                    0 = everything on the caller's stream.  Timing
                                    solves always run on one stream.  With autotune,
                                    this is the largest value tried.                     */
+    int32_t launch_streams;     /* 0 (default) = the launch shapes above.  1..128 = the
+                                   execution model of Sec. 5.1 of the paper, kept as a
+                                   baseline for comparison: one kernel launch per target
+                                   sub-grid and interaction class, issued coarse level
+                                   first and round-robin over this many plan-owned
+                                   streams (forked from and joined back to the solve's
+                                   stream); the passes stay on the solve's stream.
+                                   persistent and overlap are then ignored; timing and
+                                   autotune are not allowed.  Results are bitwise equal
+                                   to those of the default shapes with the same
+                                   plane_groups.                                        */
 } fmmg_options;
 
 /* Stages of one solve, in launch order. */
@@ -160,6 +171,7 @@ typedef struct {
     int32_t overlap;            /* 1 if the coarse levels run on the second stream, 2 if
                                    also the fine monopole class runs on a third one      */
     int32_t split_level;        /* levels below this one form the coarse branch        */
+    int32_t launch_streams;     /* streams of the per-sub-grid launch model, or 0      */
 } fmmg_launch_shape;
 
 typedef struct {

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
 #include <array>
 #include <cstdio>
 #include <fstream>
@@ -80,6 +81,7 @@ std::vector<TreeIn> to_trees(const fmmg_tree_desc* trees, int32_t n_trees) {
 }
 
 constexpr int TOP_CHUNKS = MAX_TOP_PARTS;
+constexpr int MAX_LAUNCH_STREAMS = 128;  // stream pool of the per-sub-grid launch model
 
 }  // namespace
 
@@ -130,6 +132,14 @@ struct fmmg_plan {
     std::vector<std::array<hipEvent_t, FMMG_N_STAGES + 1>> events;
     size_t n_timed = 0;
     int64_t stage_launches[FMMG_N_STAGES] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // per-sub-grid launch model (options.launch_streams > 0): the work items of
+    // one target sub-grid and class form a run, launched on its own
+    struct Run {
+        int32_t kind, begin, n;
+    };
+    std::vector<Run> runs;                 // coarse level first, then sub-grid, then class
+    std::vector<hipStream_t> pool;
+    std::vector<hipEvent_t> pool_join;
 };
 
 namespace {
@@ -160,6 +170,10 @@ void release(fmmg_plan* p) {
     if (p->ev_join) (void)hipEventDestroy(p->ev_join);
     if (p->mono_stream) (void)hipStreamDestroy(p->mono_stream);
     if (p->ev_join_mono) (void)hipEventDestroy(p->ev_join_mono);
+    for (hipStream_t q : p->pool)
+        if (q) (void)hipStreamDestroy(q);
+    for (hipEvent_t ev : p->pool_join)
+        if (ev) (void)hipEventDestroy(ev);
     delete p;
 }
 
@@ -188,6 +202,37 @@ Ctx make_ctx(const fmmg_plan* p, hipStream_t st) {
 }
 
 // Rebuilds and uploads the work items for a launch shape.
+// Runs of the per-sub-grid launch model: the class list split at every change
+// of (class, target sub-grid), ordered like a top-down walk of the trees
+// (coarse level first), then by sub-grid and class.
+void build_runs(fmmg_plan* p) {
+    const HostPlan& hp = p->hp;
+    struct Keyed {
+        int32_t level, target, kind;
+        fmmg_plan::Run r;
+    };
+    std::vector<Keyed> v;
+    const int32_t n = int32_t(hp.items_class.size());
+    for (int32_t i = 0; i < n;) {
+        const Item& it = hp.items_class[size_t(i)];
+        auto target = [&](const Item& x) {
+            return x.kind == IT_TOP ? hp.top_items[size_t(x.sub)].target : x.sub;
+        };
+        const int32_t t = target(it);
+        int32_t j = i + 1;
+        while (j < n && hp.items_class[size_t(j)].kind == it.kind && target(hp.items_class[size_t(j)]) == t) ++j;
+        v.push_back({hp.subs[size_t(t)].level, t, it.kind, {it.kind, i, j - i}});
+        i = j;
+    }
+    std::stable_sort(v.begin(), v.end(), [](const Keyed& a, const Keyed& b) {
+        if (a.level != b.level) return a.level < b.level;
+        if (a.target != b.target) return a.target < b.target;
+        return a.kind < b.kind;
+    });
+    p->runs.clear();
+    for (const Keyed& k : v) p->runs.push_back(k.r);
+}
+
 fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int overlap, hipStream_t st) {
     if (groups < 1 || groups > p->max_groups)
         return fail(FMMG_EINVAL, "plane_groups must be 1.." + std::to_string(p->max_groups) + " for this plan");
@@ -203,6 +248,7 @@ fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int o
                                    p->hp.items_lpt.size() * sizeof(Item), hipMemcpyHostToDevice, st), "item upload");
         }
         HIP_TRY(hipStreamSynchronize(st), "item upload");
+        build_runs(p);
     }
     if (overlap < 0 || overlap > 2) return fail(FMMG_EINVAL, "overlap must be 0, 1 or 2");
     if (p->hp.split == 0) overlap = 0;
@@ -214,6 +260,7 @@ fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int o
     p->shape.blocks_per_cu = bpc;
     p->shape.overlap = overlap;
     p->shape.split_level = p->hp.split;
+    p->shape.launch_streams = int32_t(p->pool.size());
     return FMMG_OK;
 }
 
@@ -278,7 +325,35 @@ int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, h
         cnt(e - b);
     };
     const int n_tl = int(hp.top_leaf.size());
-    if (!fork) {
+    if (!p->pool.empty()) {
+        // the execution model of Sec. 5.1: many small launches, one per target
+        // sub-grid and class, spread over a pool of streams; the passes stay
+        // on the solve's stream
+        launch_p2m_top(a, p->d_top_leaf, n_tl);
+        cnt(n_tl);
+        for (int l = hp.max_level - 1; l >= 0; --l) m2m(a, l);
+        const size_t used = std::min(p->pool.size(), p->runs.size());
+        (void)hipEventRecord(p->ev_fork, st);
+        for (size_t k = 0; k < used; ++k) (void)hipStreamWaitEvent(p->pool[k], p->ev_fork, 0);
+        size_t k = 0;
+        for (const fmmg_plan::Run& r : p->runs) {
+            Ctx x = a;
+            x.st = p->pool[k];
+            launch_class(x, r.kind, p->d_items_class + r.begin, r.n);
+            cnt(r.n);
+            k = k + 1 == used ? 0 : k + 1;
+        }
+        for (size_t q = 0; q < used; ++q) {
+            (void)hipEventRecord(p->pool_join[q], p->pool[q]);
+            (void)hipStreamWaitEvent(st, p->pool_join[q], 0);
+        }
+        launch_leaf_out(a, p->d_top_leaf, n_tl, phi, g);
+        cnt(n_tl);
+        for (int l = 0; l < hp.max_level; ++l) {
+            l2l(a, l, 1);
+            l2l(a, l, 0);
+        }
+    } else if (!fork) {
         // one stream, stage by stage
         mark(FMMG_STAGE_P2M);
         launch_p2m_top(a, p->d_top_leaf, n_tl);
@@ -549,6 +624,9 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         else if (o.plane_groups < 0 || o.plane_groups > MAX_GROUPS) bad = "plane_groups must be 0..5";
         else if (o.blocks_per_cu < 0) bad = "blocks_per_cu must be >= 0";
         else if (o.overlap < 0 || o.overlap > 2) bad = "overlap must be 0, 1 or 2";
+        else if (o.launch_streams < 0 || o.launch_streams > MAX_LAUNCH_STREAMS) bad = "launch_streams must be 0..128";
+        else if (o.launch_streams && o.timing) bad = "timing needs launch_streams = 0";
+        else if (o.launch_streams && o.autotune) bad = "autotune needs launch_streams = 0";
         if (!bad.empty()) { release(p); return fail(FMMG_EINVAL, bad); }
         hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
         hipError_t e = hipGetDevice(&p->device);
@@ -606,6 +684,15 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->mono_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join_mono, hipEventDisableTiming);
         if (e != hipSuccess) { release(p); return hip_fail(e, "second stream"); }
+        for (int k = 0; k < o.launch_streams && e == hipSuccess; ++k) {
+            hipStream_t q = nullptr;
+            hipEvent_t ev = nullptr;
+            e = hipStreamCreateWithFlags(&q, hipStreamNonBlocking);
+            if (e == hipSuccess) p->pool.push_back(q);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) p->pool_join.push_back(ev);
+        }
+        if (e != hipSuccess) { release(p); return hip_fail(e, "launch stream pool"); }
         e = hipMalloc(reinterpret_cast<void**>(&p->d_bad), sizeof(unsigned long long));
         if (e != hipSuccess) { release(p); return fail(FMMG_ENOMEM, "hipMalloc flag"); }
         e = hipHostMalloc(reinterpret_cast<void**>(&p->h_bad), sizeof(unsigned long long), hipHostMallocDefault);

@@ -409,6 +409,33 @@ def test_overlapped_coarse_branch_equals_one_stream(shape):
     assert forked >= 4  # the uniform trees split (levels 0-1 coarse)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_per_subgrid_launch_model_equals_class_launches(precision):
+    """The paper's execution model (one launch per target sub-grid and class,
+    round-robin over a stream pool; Sec. 5.1) runs the same work items as the
+    class launches, so its result is bitwise the same, eager and in a graph,
+    for one tree and for a batch."""
+    a, b, u = wl.small_amr(2), wl.small_amr(3), wl.c1(max_level=2)
+    cases = [([wl.small_amr(1).trees[0]], wl.small_amr(1).rho), ([u.trees[0]], u.rho),
+             ([a.trees[0], b.trees[0]], np.concatenate([a.rho, b.rho]))]
+    for trees, rho in cases:
+        r = torch.tensor(rho, dtype=torch.float64, device=DEV)
+        with fm.Plan(trees, precision=precision, overlap=0, plane_groups=2) as p1:
+            ref = [x.clone() for x in p1.solve(r)]
+            torch.cuda.synchronize()
+            base_launches = p1.stats()["launches"]
+        for ns, graph in ((1, False), (8, False), (128, False), (128, True)):
+            with fm.Plan(trees, precision=precision, plane_groups=2, launch_streams=ns, use_graph=graph) as p2:
+                for rep in range(2):
+                    out = p2.solve(r)
+                    torch.cuda.synchronize()
+                    assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1]), (len(trees), ns, graph, rep)
+                assert p2.launch_shape()["launch_streams"] == ns
+                n = p2.stats()["launches"]
+        print(f"  {len(trees)} tree(s): {base_launches} class launches, {n} per-sub-grid launches", flush=True)
+        assert n > base_launches
+
+
 def test_autotune_picks_a_shape_and_caches_it(tmp_path):
     W = wl.small_amr(1)
     t = W.trees[0]

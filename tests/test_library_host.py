@@ -33,6 +33,22 @@ def test_default_options():
     o = fm.fmmg_default_options()
     assert o.precision == fm.FMMG_FP64 and o.top_mode == fm.FMMG_TOP_FULL
     assert o.G == 1.0 and o.angular_correction == 1
+    assert o.overlap == 1 and o.launch_streams == 0 and o.use_graph == 0 and o.persistent == 0
+
+
+@pytest.mark.parametrize("bad", [
+    {"launch_streams": 129}, {"launch_streams": -1}, {"launch_streams": 4, "timing": 1},
+    {"launch_streams": 4, "autotune": 1}, {"overlap": 3}, {"plane_groups": 6},
+    {"timing": 1, "use_graph": 1}, {"timing": 1, "autotune": 1}, {"blocks_per_cu": -1},
+])
+def test_bad_options_are_rejected_before_any_device_call(bad):
+    # option checks come first, so they answer the same with or without a GPU
+    o = fm.fmmg_default_options()
+    for k, v in bad.items():
+        setattr(o, k, v)
+    with pytest.raises(fm.FmmgError) as e:
+        fm.fmmg_plan_create([wl.uniform_tree(1)], o, stream=0)
+    assert e.value.status == fm.FMMG_EINVAL
 
 
 def test_library_does_not_link_the_oracle():
@@ -100,3 +116,4 @@ def test_malformed_trees_are_rejected():
     with pytest.raises(fm.FmmgError) as e:
         fm.fmmg_count_pairs([t], top_mode=7)
     assert e.value.status == fm.FMMG_EINVAL
+
