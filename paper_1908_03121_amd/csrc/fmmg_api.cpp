@@ -597,6 +597,7 @@ fmmg_status fmmg_count_pairs(const fmmg_tree_desc* trees, int32_t n_trees, fmmg_
         stats->n_refined = int64_t(hp.ref_sub.size());
         stats->max_level = hp.max_level;
         stats->n_trees = n_trees;
+        stats->sweep_y_targets = hp.sweep_y_targets;
         return FMMG_OK;
     } catch (const std::bad_alloc&) {
         return fail(FMMG_ENOMEM, "host allocation failed");
@@ -847,6 +848,7 @@ fmmg_status fmmg_get_stats(const fmmg_plan* p, fmmg_stats* s) {
     s->n_refined = int64_t(p->hp.ref_sub.size());
     s->max_level = p->hp.max_level;
     s->n_trees = p->hp.n_trees;
+    s->sweep_y_targets = p->hp.sweep_y_targets;
     return FMMG_OK;
 }
 

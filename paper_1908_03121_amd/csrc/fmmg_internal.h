@@ -73,8 +73,9 @@ constexpr int MAX_GROUPS = 5;   // source-plane groups of a refined-target item 
 struct Item {
     int32_t kind;
     int32_t sub;   // target sub-grid (IT_TOP: index into the top items)
-    int32_t a;     // IT_MP_*: target plane zt
-    int32_t b;     // IT_MP_REF: plane group
+    int32_t a;     // IT_MP_*: target plane along the sweep axis
+    int32_t b;     // IT_MP_REF: plane group in bits 0..2; IT_MP_*: sweep in bit 3
+                   // (0: planes along z, lanes on (x, y); 1: along y, lanes on (x, z))
 };
 
 // Canonical stencil tables (parity (0,0,0); other parities are mirror images:

@@ -347,14 +347,48 @@ struct Smem {
     static constexpr int BYTES = NBR_OFF + 128;
 };
 
-// Multipole item: 64 target cells (plane zt of sub-grid sid) against the
-// source planes of one group of canonical dz.  All 4 waves hold the same 64
-// targets and split each plane's entry list.  Refined targets: every existing
-// source over the far entries, leaf sources also over the near entries
-// (classes 1 + 2).  Leaf targets: refined sources over all entries (class 4).
-template <bool LEAF_T, bool MIXED>
-__device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int group,
-                                        unsigned char* smem) {
+// Swap of the y and z axes in a record (mass, centre-of-mass offset,
+// trace-free quadrupole xx yy xy xz yz, trace-free octupole xxx xxy xxz xyy
+// xyz yyy yyz) or, with the same index pattern, in the 19 Taylor components
+// (L0, L1, trace-free L2, trace-free L3, correction): dependent components
+// (zz = -xx - yy, xzz = -xxx - xyy, zzz = -xxz - yyz, yzz = -xxy - yyy) take
+// the place of the swapped ones.  The map is its own inverse.
+template <typename T>
+__device__ __forceinline__ void swap_yz(T& y, T& z) {
+    const T t = y;
+    y = z;
+    z = t;
+}
+template <typename T>
+__device__ __forceinline__ void swap_yz_q(T* q) {
+    q[1] = -q[0] - q[1];
+    swap_yz(q[2], q[3]);
+}
+template <typename T>
+__device__ __forceinline__ void swap_yz_o(T* o) {
+    const T o0 = o[0], o1 = o[1], o2 = o[2], o3 = o[3], o5 = o[5], o6 = o[6];
+    o[1] = o2;
+    o[2] = o1;
+    o[3] = -o0 - o3;
+    o[5] = -o2 - o6;
+    o[6] = -o1 - o5;
+}
+
+// Multipole item: 64 target cells (one plane of sub-grid sid) against the
+// source planes of one group of canonical plane offsets.  All 4 waves hold
+// the same 64 targets and split each plane's entry list.  Refined targets:
+// every existing source over the far entries, leaf sources also over the
+// near entries (classes 1 + 2).  Leaf targets: refined sources over all
+// entries (class 4).
+// The sweep frame (u, v, w) puts the target plane at w = zt and the lanes on
+// (u, v): sweep 0 is (x, y, z); sweep 1 is (x, z, y), chosen by the planner
+// for targets whose sources lie mostly beside them in y, so that whole source
+// planes without sources are skipped.  x, the fastest index in memory, stays
+// in the plane either way (coalesced staging), and the stencil is symmetric
+// under the swap, so one set of tables serves both: records are swapped into
+// the frame when staged and the results swapped back before they are stored.
+template <bool LEAF_T, bool MIXED, int SWEEP>
+__device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int group, unsigned char* smem) {
     using P = typename std::conditional<MIXED, float, double>::type;
     P* sh = reinterpret_cast<P*>(smem);
     unsigned char* leafflag = smem + NREC * PSLOTS * sizeof(P);
@@ -371,7 +405,11 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     if (t < 27) nb[t] = T.nbr[t];
     const double h = T.h;
     const int tidx = T.idx;
-    const int q = zt * 64 + cl;
+    // cell index strides of the frame's v and w, and neighbour-code strides
+    // of their sub-grid offsets (x: stride 1, code stride 9, in both frames)
+    constexpr int VS = SWEEP ? 64 : 8, WS = SWEEP ? 8 : 64;
+    constexpr int VN = SWEEP ? 1 : 3, WN = SWEEP ? 3 : 1;
+    const int q = zt * WS + y * VS + x;
     const int sx = 1 - 2 * (x & 1), sy = 1 - 2 * (y & 1), sz = 1 - 2 * (zt & 1);
 
     // target data
@@ -385,6 +423,10 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         dAz = r[R_DZ * NCELL + q];
 #pragma unroll
         for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q]);
+        if (SWEEP) {
+            swap_yz(dAy, dAz);
+            swap_yz_o(oa);
+        }
         oa[7] = -oa[0] - oa[3];
         oa[8] = -oa[1] - oa[5];
     } else {
@@ -414,7 +456,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
             bool any = false;
 #pragma unroll
             for (int o = 0; o < 9; ++o) {
-                const int code = T.nbr[(o / 3) * 9 + (o % 3) * 3 + (oz + 1)];
+                const int code = T.nbr[(o / 3) * 9 + (o % 3) * VN + (oz + 1) * WN];
                 any |= LEAF_T ? (code >= 0 && (code & 1)) : (code >= 0);
             }
             if (!any) continue;
@@ -434,8 +476,8 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
                     const int lx = wx - REACH, ly = wy - REACH;
                     const int ox = lx < 0 ? -1 : (lx >= NS ? 1 : 0);
                     const int oy = ly < 0 ? -1 : (ly >= NS ? 1 : 0);
-                    const int code = nb[(ox + 1) * 9 + (oy + 1) * 3 + (oz + 1)];
-                    const int cq = (lz * NS + (ly - NS * oy)) * NS + (lx - NS * ox);
+                    const int code = nb[(ox + 1) * 9 + (oy + 1) * VN + (oz + 1) * WN];
+                    const int cq = lz * WS + (ly - NS * oy) * VS + (lx - NS * ox);
                     const int kind = code < 0 ? -1 : (code & 1), nidx = code >> 1;
                     const double* r = cx.rec + (kind == 1 ? size_t(nidx) * NREC * NCELL + cq : size_t(0));
                     const double* mp = cx.mass + (kind == 0 ? size_t(nidx) * NCELL + cq : size_t(0));
@@ -443,6 +485,11 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
 #pragma unroll
                     for (int k = 0; k < NREC; ++k) v[k] = r[k * NCELL];
                     const double mm = *mp;
+                    if (SWEEP) {
+                        swap_yz(v[R_DY], v[R_DZ]);
+                        swap_yz_q(v + R_Q);
+                        swap_yz_o(v + R_O);
+                    }
 #pragma unroll
                     for (int k = 0; k < NREC; ++k)
                         sh[k * PSLOTS + c] = kind == 1 ? P(v[k])
@@ -502,6 +549,12 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         // carry no mass either, so no momentum is involved)
         if (!(mA > 0)) acc.s[0] = acc.s[1] = acc.s[2] = 0.0;
         acc.out(v);
+        if (SWEEP) {  // back from the frame
+            swap_yz(v[T_L1 + 1], v[T_L1 + 2]);
+            swap_yz_q(v + T_L2);
+            swap_yz_o(v + T_L3);
+            swap_yz(v[T_S + 1], v[T_S + 2]);
+        }
 #pragma unroll
         for (int k = 0; k < NLOC; ++k) red[(w * NLOC + k) * 64 + cl] = v[k];
     }
@@ -512,18 +565,20 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         return red[(0 * NLOC + k) * 64 + l] + red[(1 * NLOC + k) * 64 + l] +
                red[(2 * NLOC + k) * 64 + l] + red[(3 * NLOC + k) * 64 + l];
     };
+    // reduction slot l = v*8 + u holds target cell zt*WS + v*VS + u
     if (!LEAF_T) {
-        double* out = cx.Lp + size_t(group) * size_t(cx.part_stride) + size_t(tidx) * NLOC * NCELL + zt * 64;
+        double* out = cx.Lp + size_t(group) * size_t(cx.part_stride) + size_t(tidx) * NLOC * NCELL + zt * WS;
         for (int i = t; i < NLOC * 64; i += 256) {
             const int k = i >> 6, l = i & 63;
-            out[k * NCELL + l] = (k >= T_S ? gs : -G) * sum4(k, l);
+            out[k * NCELL + (l >> 3) * VS + (l & 7)] = (k >= T_S ? gs : -G) * sum4(k, l);
         }
     } else {
         // own terms from refined sources: phi = -G L0;  g = G L1 + (-G/6) S
-        double* out = cx.Lf3 + size_t(T.slot3) * NLEAF * NCELL + zt * 64;
+        double* out = cx.Lf3 + size_t(T.slot3) * NLEAF * NCELL + zt * WS;
         if (t < 64) {
-            out[0 * NCELL + t] = -G * sum4(0, t);
-            for (int a = 0; a < 3; ++a) out[(1 + a) * NCELL + t] = G * sum4(T_L1 + a, t) + gs * sum4(T_S + a, t);
+            const int o = (t >> 3) * VS + (t & 7);
+            out[0 * NCELL + o] = -G * sum4(0, t);
+            for (int a = 0; a < 3; ++a) out[(1 + a) * NCELL + o] = G * sum4(T_L1 + a, t) + gs * sum4(T_S + a, t);
         }
     }
 }
@@ -798,8 +853,14 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
 template <bool MIXED>
 __device__ __forceinline__ void run_item(const Ctx& cx, const Item& it, unsigned char* smem) {
     switch (it.kind) {
-        case IT_MP_REF: mp_item<false, MIXED>(cx, it.sub, it.a, it.b, smem); break;
-        case IT_MP_LEAF: mp_item<true, MIXED>(cx, it.sub, it.a, 0, smem); break;
+        case IT_MP_REF:
+            if (it.b >> 3) mp_item<false, MIXED, 1>(cx, it.sub, it.a, it.b & 7, smem);
+            else mp_item<false, MIXED, 0>(cx, it.sub, it.a, it.b & 7, smem);
+            break;
+        case IT_MP_LEAF:
+            if (it.b >> 3) mp_item<true, MIXED, 1>(cx, it.sub, it.a, 0, smem);
+            else mp_item<true, MIXED, 0>(cx, it.sub, it.a, 0, smem);
+            break;
         case IT_MONO: mono_item<MIXED>(cx, it.sub, smem); break;
         default: top_item<MIXED>(cx, cx.top_items[it.sub], smem); break;
     }
@@ -811,8 +872,10 @@ __global__ __launch_bounds__(256) void k_class(Ctx cx, const Item* __restrict__ 
     using P = typename std::conditional<MIXED, float, double>::type;
     __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P>::BYTES];
     const Item it = items[blockIdx.x];
-    if (KIND == IT_MP_REF) mp_item<false, MIXED>(cx, it.sub, it.a, it.b, smem);
-    else if (KIND == IT_MP_LEAF) mp_item<true, MIXED>(cx, it.sub, it.a, 0, smem);
+    if (KIND == IT_MP_REF || KIND == IT_MP_LEAF) {
+        if (it.b >> 3) mp_item<KIND == IT_MP_LEAF, MIXED, 1>(cx, it.sub, it.a, it.b & 7, smem);
+        else mp_item<KIND == IT_MP_LEAF, MIXED, 0>(cx, it.sub, it.a, it.b & 7, smem);
+    }
     else if (KIND == IT_MONO) mono_item<MIXED>(cx, it.sub, smem);
     else top_item<MIXED>(cx, cx.top_items[it.sub], smem);
 }

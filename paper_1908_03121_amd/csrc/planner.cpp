@@ -355,37 +355,53 @@ void build_items(HostPlan* Pp, int ngroups) {
     // estimated cost of an item, in refined-pair units, and its level
     struct Costed { Item it; double cost; int level; };
     std::vector<Costed> all;
-    // a source plane with no usable neighbour among the 9 at its z offset is
-    // skipped by the kernels; the estimates count the planes they visit
-    auto plane_used = [&](const SubDev& S, int zs, bool refined_only) {
-        const int oz = zs < 0 ? -1 : (zs >= NS ? 1 : 0);
+    // a source plane with no usable neighbour among the 9 at its offset along
+    // the sweep axis (z for sweep 0, y for sweep 1) is skipped by the kernels;
+    // the estimates count the planes they visit
+    auto plane_used = [&](const SubDev& S, int sweep, int ws, bool refined_only) {
+        const int ow = ws < 0 ? -1 : (ws >= NS ? 1 : 0);
+        const int VN = sweep ? 1 : 3, WN = sweep ? 3 : 1;
         for (int o = 0; o < 9; ++o) {
-            const int code = S.nbr[(o / 3) * 9 + (o % 3) * 3 + (oz + 1)];
+            const int code = S.nbr[(o / 3) * 9 + (o % 3) * VN + (ow + 1) * WN];
             if (code >= 0 && (!refined_only || (code & 1))) return true;
         }
         return false;
     };
+    // stencil entries that target plane zt visits over the canonical plane
+    // offsets [i0, i1)
+    auto visited = [&](const SubDev& S, int sweep, int zt, int i0, int i1, bool leaf_t, bool nearc) {
+        double n = 0;
+        for (int i = i0; i < i1; ++i)
+            if (plane_used(S, sweep, zt + (1 - 2 * (zt & 1)) * (DZ0 + i), leaf_t))
+                n += tab.mp_far_count[i] + (nearc ? tab.mp_near_count[i] : 0);
+        return n;
+    };
+    // the sweep of a target: the frame that visits fewer entries (z on a tie)
+    auto best_sweep = [&](const SubDev& S, bool leaf_t, bool nearc) {
+        double n[2] = {0, 0};
+        for (int sw = 0; sw < 2; ++sw)
+            for (int zt = 0; zt < NS; ++zt) n[sw] += visited(S, sw, zt, 0, NDZ, leaf_t, nearc);
+        return n[1] < n[0] ? 1 : 0;
+    };
+    P.sweep_y_targets = 0;
     for (int32_t s : P.mp_ref) {
         const SubDev& S = P.subs[size_t(s)];
         const bool nearc = (S.flags & 1) != 0;
+        const int sw = best_sweep(S, false, nearc);
+        P.sweep_y_targets += sw;
         for (int zt = 0; zt < NS; ++zt)
             for (int g = 0; g < ngroups; ++g) {
-                int i0 = g * NDZ / ngroups, i1 = (g + 1) * NDZ / ngroups;
-                double n = 0;
-                for (int i = i0; i < i1; ++i)
-                    if (plane_used(S, zt + (1 - 2 * (zt & 1)) * (DZ0 + i), false))
-                        n += tab.mp_far_count[i] + (nearc ? tab.mp_near_count[i] : 0);
-                all.push_back({Item{IT_MP_REF, s, zt, g}, 64.0 * n + 2000.0, S.level});
+                const double n = visited(S, sw, zt, g * NDZ / ngroups, (g + 1) * NDZ / ngroups, false, nearc);
+                all.push_back({Item{IT_MP_REF, s, zt, g | (sw << 3)}, 64.0 * n + 2000.0, S.level});
             }
     }
     for (int32_t s : P.mp_leaf) {
         const SubDev& S = P.subs[size_t(s)];
+        const int sw = best_sweep(S, true, true);
+        P.sweep_y_targets += sw;
         for (int zt = 0; zt < NS; ++zt) {
-            double n = 0;
-            for (int i = 0; i < NDZ; ++i)
-                if (plane_used(S, zt + (1 - 2 * (zt & 1)) * (DZ0 + i), true))
-                    n += tab.mp_far_count[i] + tab.mp_near_count[i];
-            all.push_back({Item{IT_MP_LEAF, s, zt, 0}, 64.0 * n * 0.68 + 2000.0, S.level});
+            const double n = visited(S, sw, zt, 0, NDZ, true, true);
+            all.push_back({Item{IT_MP_LEAF, s, zt, sw << 3}, 64.0 * n * 0.68 + 2000.0, S.level});
         }
     }
     for (int32_t s : P.mono_leaf)

@@ -361,6 +361,46 @@ def test_mixed_amr_error_bounds(shape):
     assert f < 1e-6 and tq < 1e-6
 
 
+def flat_forest(seed):
+    """A 3 x 1 x 3 forest of refined level-0 sub-grids (level 1 is 6 x 2 x 6
+    sub-grids, one side in y always absent), a few level-1 sub-grids refined
+    once more: multipole targets whose sources lie beside them in y, the case
+    where plane items run along y."""
+    rng = np.random.default_rng(seed)
+    subs = [(0, x, 0, z) for x in range(3) for z in range(3)]
+    l1 = [(1, x, y, z) for x in range(6) for y in range(2) for z in range(6)]
+    subs += l1
+    for k in rng.choice(len(l1), 5, replace=False):
+        _, x, y, z = l1[k]
+        subs += [(2, 2 * x + a, 2 * y + b, 2 * z + c) for a in (0, 1) for b in (0, 1) for c in (0, 1)]
+    t = wl._desc_from_list(subs, (0.0, 0.0, 0.0), 1.0)
+    return t, rng.lognormal(0.0, 1.0, (t.n_leaves, 8, 8, 8))
+
+
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g1", "per_class_g3"])
+def test_y_sweep_targets_fp64(shape):
+    t, rho = flat_forest(7)
+    n_y = fm.fmmg_count_pairs([t])["sweep_y_targets"]
+    phi, g, st = run([t], rho, **SHAPES[shape])
+    pr, gr, ost = oracle.solve(t, rho, with_stats=True)
+    errs = field_errors(phi, g, pr, gr)
+    f, tq = residuals(t, rho, g, centre=(0.75, 0.0625, 0.75))
+    print(f"  {n_y} y-sweep targets, errors {errs}, force {f:.3e} torque {tq:.3e}", flush=True)
+    assert n_y >= 8 and st["pairs"][3] > 0
+    assert max(errs) < TOL64
+    assert st["pairs"] == ost["cls"]
+    assert f < 1e-13 and tq < 1e-13
+
+
+def test_y_sweep_targets_mixed():
+    t, rho = flat_forest(8)
+    phi, g, _ = run([t], rho, precision="mixed", persistent=True)
+    pr, gr = oracle.solve(t, rho)
+    errs = field_errors(phi, g, pr, gr)
+    print(f"  mixed errors {errs}", flush=True)
+    assert errs[0] < 2e-6 and max(errs[1:]) < 2e-5
+
+
 # ---------------------------------------------------------------------------
 # interface behaviour
 # ---------------------------------------------------------------------------

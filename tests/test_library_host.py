@@ -117,3 +117,59 @@ def test_malformed_trees_are_rejected():
         fm.fmmg_count_pairs([t], top_mode=7)
     assert e.value.status == fm.FMMG_EINVAL
 
+
+def _plane_visits(usable, sweep, near, far_by_w, near_by_w):
+    """Stencil entries the plane items of one target visit in a sweep frame:
+    a source plane is visited iff one of the 9 neighbour sub-grids at its
+    offset along the sweep axis (z: sweep 0, y: sweep 1) is usable."""
+    axis = 2 if sweep == 0 else 1
+    n = 0
+    for t in range(8):
+        s = 1 - 2 * (t & 1)
+        for i in range(10):
+            w = t + s * (i - 4)
+            side = -1 if w < 0 else (1 if w >= 8 else 0)
+            if np.take(usable, side + 1, axis=axis).any():
+                n += far_by_w[i] + (near_by_w[i] if near else 0)
+    return n
+
+
+@pytest.mark.parametrize("name", ["c2", "amr11"])
+def test_planner_sweep_choice(name):
+    """The planner runs a multipole target's plane items along y exactly when
+    that frame visits fewer stencil entries than the z frame; recounted here
+    from the interaction rule and the tree alone."""
+    import itertools
+    W = wl.c2() if name == "c2" else wl.small_amr(11, max_level=3, p_refine=0.3)
+    t = W.trees[0]
+    far = np.zeros(10, int)
+    near = np.zeros(10, int)
+    for d in itertools.product(range(-5, 6), repeat=3):
+        if oracle.pair_rule(0, [0, 0, 0], list(d), 0, 1):
+            (far if oracle.pair_rule(0, [0, 0, 0], list(d), 0, 0) else near)[d[2] + 4] += 1
+    assert far.sum() == 651 and near.sum() == 92
+    ref = t.refined_mask()
+    key = {(int(l), *map(int, c)): i for i, (l, c) in enumerate(zip(t.level, t.coord))}
+    n_y = 0
+    for s in range(t.n_subgrids):
+        lv, c = int(t.level[s]), t.coord[s]
+        if lv == 0:
+            continue                      # the top level has its own all-pairs kernel
+        nb = np.full((3, 3, 3), -1)
+        for o in itertools.product((-1, 0, 1), repeat=3):
+            j = key.get((lv, c[0] + o[0], c[1] + o[1], c[2] + o[2]))
+            if j is not None:
+                nb[o[0] + 1, o[1] + 1, o[2] + 1] = 1 if ref[j] else 0
+        others = nb.copy()
+        others[1, 1, 1] = -1
+        if ref[s]:
+            usable, near_on = nb >= 0, bool((others == 0).any())
+        elif (others == 1).any():
+            usable, near_on = nb == 1, True
+        else:
+            continue
+        v = [_plane_visits(usable, sw, near_on, far, near) for sw in (0, 1)]
+        n_y += v[1] < v[0]
+    st = fm.fmmg_count_pairs([t])
+    print(f"  {name}: {n_y} targets along y", flush=True)
+    assert st["sweep_y_targets"] == n_y and n_y > 0
