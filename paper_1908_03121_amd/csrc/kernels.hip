@@ -613,6 +613,8 @@ __device__ __forceinline__ void mono_class(const P* __restrict__ box, int cbeg, 
     constexpr int SZ = 1 - 2 * PZ;
     constexpr int ZMIN = SZ > 0 ? PZ + LO : PZ - (LO + N - 1);  // lowest source z
     constexpr int NSRC = N + 6;
+    // two columns per trip: their LDS and table loads are waited for together
+#pragma unroll 2
     for (int c = cbeg + cstart; c < cend; c += cstep) {
         const int pk = c_tab.mono_col[c];
         const int dx = (pk & 255) - 8, dy = ((pk >> 8) & 255) - 8;
@@ -943,24 +945,42 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
     const int q = threadIdx.x;
     const int x = q & 7, y = (q >> 3) & 7, z = q >> 6;
     const int ex = 4 * (e >> 2), ey = 4 * ((e >> 1) & 1), ez = 4 * (e & 1);
-    // cooperative fetch of the parent octant: value i = comp * 64 + cell
+    // cooperative fetch of the parent octant: value i = comp * 64 + cell (the
+    // component is uniform over a wave); every load of the three rounds is
+    // issued before the first is used (group partials beyond the plan's
+    // count re-read the last one and are not added)
+    const int ng = cx.ngroups;
+    double v[3], t[3][MAX_GROUPS];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         const int i = q + r * NCELL;
-        if (i >= (NLOC + 3) * 64) break;
         const int k = i >> 6, c = i & 63;
         const int pq = ((ez + (c >> 4)) * NS + ey + ((c >> 2) & 3)) * NS + ex + (c & 3);
-        double v;
+        v[r] = 0.0;
+        if (i >= (NLOC + 3) * 64) continue;
         if (k >= NLOC) {
-            v = cx.rec[(size_t(Ps.idx) * NREC + R_DX + (k - NLOC)) * NCELL + pq];
+            v[r] = cx.rec[(size_t(Ps.idx) * NREC + R_DX + (k - NLOC)) * NCELL + pq];
         } else if (parent_mode == PARENT_TOP_PARTS) {
-            v = top_total(cx, Ps, k, pq);
+            v[r] = top_total(cx, Ps, k, pq);
         } else {
             const size_t base = (size_t(Ps.idx) * NLOC + k) * NCELL + pq;
-            v = parent_mode == PARENT_TOTAL ? cx.Lr[base] : 0.0;
-            for (int gg = 0; gg < cx.ngroups; ++gg) v += cx.Lp[size_t(gg) * size_t(cx.part_stride) + base];
+            if (parent_mode == PARENT_TOTAL) v[r] = cx.Lr[base];
+#pragma unroll
+            for (int gg = 0; gg < MAX_GROUPS; ++gg)
+                t[r][gg] = cx.Lp[size_t(gg < ng ? gg : ng - 1) * size_t(cx.part_stride) + base];
         }
-        par[k][c] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int i = q + r * NCELL;
+        if (i >= (NLOC + 3) * 64) continue;
+        const int k = i >> 6;
+        if (k < NLOC && parent_mode != PARENT_TOP_PARTS) {
+#pragma unroll
+            for (int gg = 0; gg < MAX_GROUPS; ++gg)
+                if (gg < ng) v[r] += t[r][gg];
+        }
+        par[k][i & 63] = v[r];
     }
     __syncthreads();
     const int pc = ((z >> 1) * 4 + (y >> 1)) * 4 + (x >> 1);
