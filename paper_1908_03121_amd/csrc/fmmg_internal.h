@@ -81,9 +81,14 @@ struct Item {
 // Canonical stencil tables (parity (0,0,0); other parities are mirror images:
 // a cell of parity p uses offset (sx*dx, sy*dy, sz*dz) with s = 1 - 2p).
 struct StencilTables {
-    // multipole kernels: entries grouped by canonical dz (DZ0..DZ0+NDZ-1),
-    // far entries first, then near ones.  entry = (dx+8) | (dy+8) << 8
+    // multipole kernels: entries (dx + 8) | (dy + 8) << 8 | footprint << 16,
+    // the footprint being the 9-bit set of in-plane neighbour columns the 64
+    // lanes of a plane reach; grouped by canonical dz (DZ0..DZ0+NDZ-1),
+    // far entries first, then near ones.  mp_entry_fp holds the same groups
+    // with each sorted by footprint (the leaf-target kernel skips entries
+    // whose footprint misses the refined neighbours, in runs)
     int32_t mp_entry[743];
+    int32_t mp_entry_fp[743];
     int32_t mp_far_begin[NDZ], mp_far_count[NDZ];
     int32_t mp_near_begin[NDZ], mp_near_count[NDZ];
     // monopole kernel: the 100 columns (dx, dy) of the canonical stencil fall

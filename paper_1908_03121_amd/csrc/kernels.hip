@@ -450,17 +450,19 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         const int dz = sz * (DZ0 + gi);
         const int zs = zt + dz;
         const int oz = zs < 0 ? -1 : (zs >= NS ? 1 : 0);
-        // a plane whose 9 neighbour sub-grids hold no usable source is skipped
-        // (uniform over the block)
-        {
-            bool any = false;
+        // in-plane neighbour columns (bit (o_u + 1) * 3 + o_v + 1) holding
+        // usable sources: refined ones for leaf targets, any for refined
+        // targets.  A plane without any is skipped (uniform over the block);
+        // leaf targets also skip the entries whose footprint (the columns
+        // their 64 lanes reach) misses them.  (For refined targets the entry
+        // test costs more than it saves.)
+        int cols = 0;
 #pragma unroll
-            for (int o = 0; o < 9; ++o) {
-                const int code = T.nbr[(o / 3) * 9 + (o % 3) * VN + (oz + 1) * WN];
-                any |= LEAF_T ? (code >= 0 && (code & 1)) : (code >= 0);
-            }
-            if (!any) continue;
+        for (int o = 0; o < 9; ++o) {
+            const int code = T.nbr[(o / 3) * 9 + (o % 3) * VN + (oz + 1) * WN];
+            cols |= (LEAF_T ? (code >= 0 && (code & 1)) : (code >= 0)) << o;
         }
+        if (!cols) continue;
         __syncthreads();
         // stage the 18x18 source window of plane zs: each thread takes up to
         // two cells and issues all loads of a cell at once (record and mass
@@ -505,8 +507,10 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         Acc<P> part_store;
         Acc<P>& part = MIXED ? part_store : *reinterpret_cast<Acc<P>*>(&acc);
         if (MIXED) part.zero();
+        const int32_t* tab = LEAF_T ? c_tab.mp_entry_fp : c_tab.mp_entry;
+        auto reaches = [&](int e) { return !LEAF_T || ((tab[e] >> 16) & cols) != 0; };
         auto one = [&](int e) {
-            const int ent = c_tab.mp_entry[e];
+            const int ent = tab[e];
             const int dxc = (ent & 255) - 8, dyc = ((ent >> 8) & 255) - 8;
             const int c = lbase + __mul24(sx, dxc) + __mul24(syw, dyc);
             P src[NREC];
@@ -519,22 +523,25 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         };
         const int fb = c_tab.mp_far_begin[gi], fe = fb + c_tab.mp_far_count[gi];
         // two independent pairs per iteration: two dependency chains per wave
+        // (entries are sorted by footprint, so the two mostly share it)
         int e = fb + w;
         for (; e + 4 < fe; e += 8) {
-            one(e);
-            one(e + 4);
+            if (reaches(e) || reaches(e + 4)) {
+                one(e);
+                one(e + 4);
+            }
         }
-        if (e < fe) one(e);
+        if (e < fe && reaches(e)) one(e);
         if (do_near) {
             const int nbg = c_tab.mp_near_begin[gi], ne = nbg + c_tab.mp_near_count[gi];
             for (int e = nbg + w; e < ne; e += 4) {
                 if (!LEAF_T) {
-                    const int ent = c_tab.mp_entry[e];
+                    const int ent = tab[e];
                     const int dxc = (ent & 255) - 8, dyc = ((ent >> 8) & 255) - 8;
                     const int c = lbase + __mul24(sx, dxc) + __mul24(syw, dyc);
                     if (!leafflag[c]) continue;
                 }
-                one(e);
+                if (reaches(e)) one(e);
             }
         }
         if (MIXED) acc.add(part, !LEAF_T);

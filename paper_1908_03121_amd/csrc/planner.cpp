@@ -101,6 +101,17 @@ int64_t top_far_pairs(int ox, int oy, int oz) {
 
 }  // namespace
 
+// 3-bit set (bit o + 1) of the sub-grid sides o in {-1, 0, 1} that the 8 lanes
+// of a row reach with canonical offset d (odd lanes mirror d)
+static int side_set(int d) {
+    int m = 0;
+    for (int u = 0; u < NS; ++u) {
+        const int us = u + ((u & 1) ? -d : d);
+        m |= 1 << ((us < 0 ? -1 : (us >= NS ? 1 : 0)) + 1);
+    }
+    return m;
+}
+
 void build_stencil_tables(StencilTables* t) {
     memset(t, 0, sizeof(*t));
     const Canon& c = canon();
@@ -111,8 +122,20 @@ void build_stencil_tables(StencilTables* t) {
             int begin = pos;
             for (size_t e = 0; e < c.dx.size(); ++e) {
                 if (c.dz[e] != dz || c.far[e] != (pass == 0)) continue;
-                t->mp_entry[pos++] = (c.dx[e] + 8) | ((c.dy[e] + 8) << 8);
+                // footprint: the in-plane neighbour columns (o_u, o_v) that the
+                // 64 lanes of a plane reach, bit (o_u + 1) * 3 + (o_v + 1)
+                const int su = side_set(c.dx[e]), sv = side_set(c.dy[e]);
+                int fp = 0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        if (((su >> a) & 1) && ((sv >> b) & 1)) fp |= 1 << (a * 3 + b);
+                t->mp_entry[pos++] = (c.dx[e] + 8) | ((c.dy[e] + 8) << 8) | (fp << 16);
             }
+            // the same group with equal footprints next to each other, so that
+            // the leaf-target kernel's entry skipping drops them in runs
+            std::copy(t->mp_entry + begin, t->mp_entry + pos, t->mp_entry_fp + begin);
+            std::stable_sort(t->mp_entry_fp + begin, t->mp_entry_fp + pos,
+                             [](int32_t a, int32_t b) { return (a >> 16) < (b >> 16); });
             if (pass == 0) { t->mp_far_begin[g] = begin; t->mp_far_count[g] = pos - begin; }
             else { t->mp_near_begin[g] = begin; t->mp_near_count[g] = pos - begin; }
         }

@@ -423,6 +423,25 @@ def test_density_check_and_argument_errors():
             p.solve(r.float())
 
 
+@pytest.mark.parametrize("groups", [1, 3])
+def test_persistent_and_class_launches_are_bitwise_equal(groups):
+    """The persistent launch (items taken largest first from a counter, all
+    classes mixed) and the per-class launches run the same items, each
+    writing its own outputs: bitwise equal results, on a tree with every
+    class and both sweep frames, and on a batch."""
+    t, rho = flat_forest(9)
+    a, b = wl.small_amr(5), wl.small_amr(11, max_level=3, p_refine=0.3)
+    for trees, r_np in (([t], rho), ([a.trees[0], b.trees[0]], np.concatenate([a.rho, b.rho]))):
+        r = torch.tensor(r_np, dtype=torch.float64, device=DEV)
+        outs = []
+        for kw in (dict(), dict(persistent=True), dict(persistent=True, blocks_per_cu=1)):
+            with fm.Plan(trees, plane_groups=groups, **kw) as p:
+                outs.append([x.clone() for x in p.solve(r)])
+                torch.cuda.synchronize()
+        for o in outs[1:]:
+            assert torch.equal(o[0], outs[0][0]) and torch.equal(o[1], outs[0][1])
+
+
 @pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g1"])
 def test_overlapped_coarse_branch_equals_one_stream(shape):
     """The coarse levels on the second stream (eager and graph) give bitwise
