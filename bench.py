@@ -104,12 +104,14 @@ def time_paper_model(fm, torch, trees, rho_np, precision, steps, warmup, groups,
 
 
 def stage_times(fm, torch, trees, rho_np, precision, steps, warmup, shape):
-    """Eager solves in the given launch shape with HIP events at every stage
+    """Eager solves in the given launch shape, without the overlap's coarse
+    branch (so every class is one launch), with HIP events at every stage
     boundary on the solve's stream."""
     dev = torch.device("cuda:0")
     rho = torch.tensor(rho_np, dtype=torch.float64, device=dev)
     with fm.Plan(trees, precision=precision, timing=True, persistent=bool(shape["persistent"]),
-                 plane_groups=shape["plane_groups"], blocks_per_cu=shape["blocks_per_cu"]) as plan:
+                 plane_groups=shape["plane_groups"], blocks_per_cu=shape["blocks_per_cu"],
+                 overlap=0) as plan:
         phi, g = plan.solve(rho)
         for _ in range(warmup):
             plan.solve(rho, phi, g)
@@ -180,7 +182,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile", action="store_true",
                     help="short run for hardware counters: 3 eager c1 FP64 solves in the launch "
-                         "shape --shape, then a 256 MiB device-to-device copy whose byte "
+                         "shape --shape (no overlap: one launch per class, as in the timing "
+                         "solves), then a 256 MiB device-to-device copy whose byte "
                          "counters calibrate the ones of the solve kernels")
     ap.add_argument("--bpc", type=int, default=0,
                     help="--profile: blocks per CU of the persistent launch (0 = occupancy limit)")
@@ -208,7 +211,7 @@ def main():
         dev = torch.device("cuda:0")
         rho = torch.tensor(c1.rho, dtype=torch.float64, device=dev)
         pers, groups = args.shape.split("_g")
-        with fm.Plan(c1.trees, persistent=pers == "persistent", plane_groups=int(groups),
+        with fm.Plan(c1.trees, persistent=pers == "persistent", plane_groups=int(groups), overlap=0,
                      blocks_per_cu=args.bpc) as plan:
             phi, g = plan.solve(rho)
             for _ in range(2):
@@ -236,18 +239,17 @@ def main():
     stages, launches, eager_ms, st_e = stage_times(fm, torch, c1.trees, c1.rho, "fp64", K, W, shape)
     log(f"  stages {stages}")
     p = st_e["pairs"]
-    # the same-level step runs as one launch per branch (fine levels, and the
-    # coarse levels when the tree splits); the timed stage spans both
+    # the timing solves run without the coarse branch, so the roofline
+    # kernel's stage is exactly one launch
     if shape["persistent"]:
-        kname = (f"k_persist<fp64> (every same-level class; {launches['fused']} launch(es) per solve: "
-                 "fine and coarse branch)")
+        kname = f"k_persist<fp64> (every same-level class of every level; {launches['fused']} launch per solve)"
         flops = algorithmic_flops(st_e)
         kms = stages["fused"]
         units = sum(p) + st_e["pairs_top"]
         tkey = f"k_persist_fp64_c1_g{shape['plane_groups']}_bpc{shape['blocks_per_cu']}"
     else:
         kname = (f"k_class<refined-target multipole, fp64> (classes 1+2; {launches['mp_refined']} "
-                 "launch(es) per solve: fine and coarse branch)")
+                 "launch per solve, all levels)")
         flops = (p[0] + p[1]) * FLOP_PAIR_REFINED
         kms = stages["mp_refined"]
         units = p[0] + p[1]

@@ -238,8 +238,11 @@ fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int o
         return fail(FMMG_EINVAL, "plane_groups must be 1.." + std::to_string(p->max_groups) + " for this plan");
     if (bpc < 0) return fail(FMMG_EINVAL, "blocks_per_cu must be >= 0");
     if (bpc == 0 || bpc > p->max_bpc) bpc = p->max_bpc;
-    if (groups != p->hp.ngroups) {
-        build_items(&p->hp, groups);
+    if (overlap < 0 || overlap > 2) return fail(FMMG_EINVAL, "overlap must be 0, 1 or 2");
+    // without overlap every class is one launch (no coarse branch)
+    const bool split = overlap > 0 && p->hp.split_natural > 0;
+    if (groups != p->hp.ngroups || split != (p->hp.split > 0)) {
+        build_items(&p->hp, groups, split);
         if (p->hp.items_class.size() > p->items_capacity) return fail(FMMG_EINVAL, "work-item capacity exceeded");
         if (!p->hp.items_class.empty()) {
             HIP_TRY(hipMemcpyAsync(p->d_items_class, p->hp.items_class.data(),
@@ -250,7 +253,6 @@ fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int o
         HIP_TRY(hipStreamSynchronize(st), "item upload");
         build_runs(p);
     }
-    if (overlap < 0 || overlap > 2) return fail(FMMG_EINVAL, "overlap must be 0, 1 or 2");
     if (p->hp.split == 0) overlap = 0;
     if (p->shape.persistent != persistent || p->shape.plane_groups != groups || p->shape.blocks_per_cu != bpc ||
         p->shape.overlap != overlap)
@@ -437,7 +439,7 @@ std::string signature(const fmmg_plan* p) {
       << " leaf=" << hp.leaf_sub.size() << " lev=" << hp.max_level << " k3=" << hp.n_slot3
       << " top=" << (p->opt.top_mode == FMMG_TOP_FULL ? "full" : "stencil")
       << " prec=" << (p->opt.precision == FMMG_MIXED ? "mixed" : "fp64") << " cu=" << p->n_cu
-      << " split=" << hp.split << " ovl=" << (p->opt.overlap ? 1 : 0);
+      << " split=" << hp.split_natural << " ovl=" << (p->opt.overlap ? 1 : 0);
     return o.str();
 }
 
@@ -509,7 +511,7 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
     }
     struct Cand { int pers, groups, bpc, ovl; };
     std::vector<Cand> cands;
-    const int max_ov = p->hp.split > 0 ? p->opt.overlap : 0;
+    const int max_ov = p->hp.split_natural > 0 ? p->opt.overlap : 0;
     for (int ov = 0; ov <= max_ov; ++ov)
         for (int gr : {1, 2, 3, 5}) {
             if (gr > p->max_groups) continue;
@@ -650,7 +652,7 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         // partial buffers and item capacity for the plane-group counts this plan may use
         p->max_groups = (o.plane_groups > 0 && !o.autotune) ? o.plane_groups : MAX_GROUPS;
         if (!o.autotune && o.plane_groups == 0) p->max_groups = 2;
-        build_items(&hp, p->max_groups);
+        build_items(&hp, p->max_groups, true);
         p->items_capacity = hp.items_class.size();
         fmmg_status s;
 #define UP(dst, src, cap, what) if ((s = dev_upload(&(dst), (src), (cap), st, what)) != FMMG_OK) { release(p); return s; }

@@ -364,11 +364,11 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
             }
         }
     }
-    build_items(&P, 1);
+    build_items(&P, 1, true);
     return 0;
 }
 
-void build_items(HostPlan* Pp, int ngroups) {
+void build_items(HostPlan* Pp, int ngroups, bool split) {
     HostPlan& P = *Pp;
     if (ngroups < 1) ngroups = 1;
     if (ngroups > MAX_GROUPS) ngroups = MAX_GROUPS;
@@ -440,12 +440,13 @@ void build_items(HostPlan* Pp, int ngroups) {
         lc[size_t(c.level)] += c.cost;
         total += c.cost;
     }
-    P.split = 0;
+    P.split_natural = 0;
     double below = 0;
     for (int s = 1; s <= P.max_level; ++s) {
         below += lc[size_t(s) - 1];
-        if (below <= 0.2 * total) P.split = s;
+        if (below <= 0.2 * total) P.split_natural = s;
     }
+    P.split = split ? P.split_natural : 0;
     auto branch = [&](const Costed& c) { return c.level < P.split ? 1 : 0; };
     // class lists in sub-grid order (measured no slower than largest first,
     // since neighbouring items share sources in the caches); the persistent

@@ -55,7 +55,8 @@ struct HostPlan {
     // same-level work items for a given number of plane groups, in two
     // branches: 0 = levels >= split (fine), 1 = levels < split (coarse)
     int ngroups = 1;
-    int split = 0;
+    int split = 0;                     // split level of the current lists (0: one branch)
+    int split_natural = 0;             // split level the estimates give
     int32_t sweep_y_targets = 0;       // multipole targets whose plane items run along y
     std::vector<Item> items_class;     // grouped by branch, then kind, in list order
     int32_t class_begin[2][IT_KINDS + 1] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
@@ -77,10 +78,11 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
                     HostPlan* out, std::string* err);
 
 // (Re)builds the work-item lists with ngroups (1..MAX_GROUPS) plane groups
-// per refined-target plane item.  The split level is the largest s <=
-// max_level whose levels below s carry at most a fifth of the estimated
-// same-level work (0: no coarse branch).
-void build_items(HostPlan* P, int ngroups);
+// per refined-target plane item.  The natural split level is the largest
+// s <= max_level whose levels below s carry at most a fifth of the estimated
+// same-level work (0: none); the lists use it when split is true (a coarse
+// branch for the overlapped solve), else split = 0 (every class one list).
+void build_items(HostPlan* P, int ngroups, bool split);
 
 // Fills the canonical stencil tables.
 void build_stencil_tables(StencilTables* t);
