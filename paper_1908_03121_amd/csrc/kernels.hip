@@ -593,10 +593,12 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
 // Monopole item: leaf targets of one sub-grid against leaf sources (class 3).
 // Cell pairs lie on the lattice: R = -h d, so phi = -(G/h) sum m/|d| and
 // g = (G/h^2) sum m d/|d|^3 with per-offset kernel values from tables.  The
-// 18^3 box of leaf masses around the sub-grid sits in LDS.  Wave w takes the
-// targets of z parity pz = w & 1 (a lane owns the 4 targets z = pz + 2k of
-// its (x, y) column) and every second stencil column (w >> 1); the two
-// column halves are added in a fixed order.
+// 18^3 box of leaf masses around the sub-grid sits in LDS.  A lane owns the 8
+// targets of its (x, y) column; wave w takes every fourth stencil column
+// starting at w, and the four column parts are added pairwise in a fixed
+// order.  Both z parities of a column read the same N + 6 source masses (the
+// mirrored offsets of odd targets cover the same z range), so one column's
+// LDS reads serve 8N pairs.
 
 // kernel values {|d|^-1, |d|^-3} for |d|^2 = n (uniform: scalar loads)
 template <typename P>
@@ -612,26 +614,26 @@ __device__ __forceinline__ void mono_r<float>(int n, float& a, float& b) {
     b = c_tab.mono_rf[n][1];
 }
 
-template <int PZ, int LO, int N, typename P>
+template <int LO, int N, typename P>
 __device__ __forceinline__ void mono_class(const P* __restrict__ box, int cbeg, int cend,
                                            int cstart, int cstep, int lbase, int sx, int syw, int sy,
-                                           double (&phi)[4], double (&gx)[4], double (&gy)[4],
-                                           double (&gz)[4]) {
-    constexpr int SZ = 1 - 2 * PZ;
-    constexpr int ZMIN = SZ > 0 ? PZ + LO : PZ - (LO + N - 1);  // lowest source z
+                                           double (&phi)[8], double (&gx)[8], double (&gy)[8],
+                                           double (&gz)[8]) {
+    // source z of target z and canonical offset dzc: z + dzc (z even) or
+    // z - dzc (z odd); over z = 0..7 and dzc in [LO, LO + N) it spans
+    // [LO, LO + N + 5] for each of the three column classes
     constexpr int NSRC = N + 6;
-    // two columns per trip: their LDS and table loads are waited for together
-#pragma unroll 2
     for (int c = cbeg + cstart; c < cend; c += cstep) {
         const int pk = c_tab.mono_col[c];
         const int dx = (pk & 255) - 8, dy = ((pk >> 8) & 255) - 8;
-        const P* col = box + lbase + __mul24(sx, dx) + __mul24(syw, dy)
-                       + (ZMIN + REACH) * PSLOTS;
+        const P* col = box + lbase + __mul24(sx, dx) + __mul24(syw, dy) + (LO + REACH) * PSLOTS;
         P m[NSRC];
 #pragma unroll
         for (int j = 0; j < NSRC; ++j) m[j] = col[j * PSLOTS];
         const int rxy = dx * dx + dy * dy;
-        P s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0}, s2[4] = {0, 0, 0, 0};
+        P s0[8], s1[8], s2[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s0[k] = s1[k] = s2[k] = 0;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const int dzc = LO + i;  // canonical dz
@@ -639,9 +641,8 @@ __device__ __forceinline__ void mono_class(const P* __restrict__ box, int cbeg, 
             mono_r<P>(rxy + dzc * dzc, a, b);
             const P cz = P(dzc) * b;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                // target z = PZ + 2k, source z = PZ + 2k + SZ*(LO + i)
-                const P mm = m[PZ + 2 * k + SZ * (LO + i) - ZMIN];
+            for (int k = 0; k < 8; ++k) {
+                const P mm = m[k + ((k & 1) ? -dzc : dzc) - LO];
                 s0[k] += mm * a;
                 s1[k] += mm * b;
                 if (dzc != 0) s2[k] += mm * cz;
@@ -649,24 +650,24 @@ __device__ __forceinline__ void mono_class(const P* __restrict__ box, int cbeg, 
         }
         const double fx = double(sx * dx), fy = double(sy * dy);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 8; ++k) {
             phi[k] += double(s0[k]);
             gx[k] += fx * double(s1[k]);
             gy[k] += fy * double(s1[k]);
-            gz[k] += double(SZ) * double(s2[k]);
+            gz[k] += (k & 1) ? -double(s2[k]) : double(s2[k]);
         }
     }
 }
 
-template <int PZ, typename P>
+template <typename P>
 __device__ __forceinline__ void mono_all(const P* box, int cstart, int cstep, int lbase, int sx,
-                                         int syw, int sy, double (&phi)[4], double (&gx)[4],
-                                         double (&gy)[4], double (&gz)[4]) {
+                                         int syw, int sy, double (&phi)[8], double (&gx)[8],
+                                         double (&gy)[8], double (&gz)[8]) {
     const int b0 = c_tab.mono_class_begin[0], b1 = c_tab.mono_class_begin[1];
     const int b2 = c_tab.mono_class_begin[2], b3 = c_tab.mono_class_begin[3];
-    mono_class<PZ, -4, 10, P>(box, b0, b1, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
-    mono_class<PZ, -2, 6, P>(box, b1, b2, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
-    mono_class<PZ, 0, 2, P>(box, b2, b3, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
+    mono_class<-4, 10, P>(box, b0, b1, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
+    mono_class<-2, 6, P>(box, b1, b2, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
+    mono_class<0, 2, P>(box, b2, b3, cstart, cstep, lbase, sx, syw, sy, phi, gx, gy, gz);
 }
 
 
@@ -726,37 +727,52 @@ __device__ __forceinline__ void mono_item(const Ctx& cx, int sid, unsigned char*
     }
     __syncthreads();
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int pz = w & 1, half = w >> 1;
     const int lane = t & 63, x = lane >> 3, y = lane & 7;  // y fastest (LDS banks)
     const int sx = 1 - 2 * (x & 1), sy = 1 - 2 * (y & 1);
     const int lbase = (y + REACH) * PRS + (x + REACH);
     const int syw = sy * PRS;
-    double phi[4] = {0, 0, 0, 0}, gx[4] = {0, 0, 0, 0}, gy[4] = {0, 0, 0, 0}, gz[4] = {0, 0, 0, 0};
-    if (pz == 0) mono_all<0, P>(box, half, 2, lbase, sx, syw, sy, phi, gx, gy, gz);
-    else mono_all<1, P>(box, half, 2, lbase, sx, syw, sy, phi, gx, gy, gz);
-    // column half 1 hands its partial sums to half 0 through LDS
-    __syncthreads();
-    double* red = reinterpret_cast<double*>(smem);
-    if (half == 1) {
+    double phi[8], gx[8], gy[8], gz[8];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            red[((pz * 16) + 4 * k + 0) * 64 + lane] = phi[k];
-            red[((pz * 16) + 4 * k + 1) * 64 + lane] = gx[k];
-            red[((pz * 16) + 4 * k + 2) * 64 + lane] = gy[k];
-            red[((pz * 16) + 4 * k + 3) * 64 + lane] = gz[k];
+    for (int k = 0; k < 8; ++k) phi[k] = gx[k] = gy[k] = gz[k] = 0;
+    mono_all<P>(box, w, 4, lbase, sx, syw, sy, phi, gx, gy, gz);
+    // column parts combined through LDS: w += w + 2 (waves 0, 1), then
+    // 0 += 1
+    double* red = reinterpret_cast<double*>(smem);
+#pragma unroll
+    for (int sh = 2; sh >= 1; sh /= 2) {
+        __syncthreads();
+        if (w >= sh && w < 2 * sh) {
+            double* r = red + (w - sh) * 32 * 64 + lane;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                r[(4 * k + 0) * 64] = phi[k];
+                r[(4 * k + 1) * 64] = gx[k];
+                r[(4 * k + 2) * 64] = gy[k];
+                r[(4 * k + 3) * 64] = gz[k];
+            }
+        }
+        __syncthreads();
+        if (w < sh) {
+            const double* r = red + w * 32 * 64 + lane;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                phi[k] += r[(4 * k + 0) * 64];
+                gx[k] += r[(4 * k + 1) * 64];
+                gy[k] += r[(4 * k + 2) * 64];
+                gz[k] += r[(4 * k + 3) * 64];
+            }
         }
     }
-    __syncthreads();
-    if (half == 0) {
+    if (w == 0) {
         const double h = T.h, G = cx.G, gh = G / (h * h), gp = -G / h;
         double* out = cx.Lf + size_t(T.idx) * NLEAF * NCELL;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int q = (pz + 2 * k) * 64 + y * 8 + x;
-            out[0 * NCELL + q] = gp * (phi[k] + red[((pz * 16) + 4 * k + 0) * 64 + lane]);
-            out[1 * NCELL + q] = gh * (gx[k] + red[((pz * 16) + 4 * k + 1) * 64 + lane]);
-            out[2 * NCELL + q] = gh * (gy[k] + red[((pz * 16) + 4 * k + 2) * 64 + lane]);
-            out[3 * NCELL + q] = gh * (gz[k] + red[((pz * 16) + 4 * k + 3) * 64 + lane]);
+        for (int k = 0; k < 8; ++k) {
+            const int q = k * 64 + y * 8 + x;
+            out[0 * NCELL + q] = gp * phi[k];
+            out[1 * NCELL + q] = gh * gx[k];
+            out[2 * NCELL + q] = gh * gy[k];
+            out[3 * NCELL + q] = gh * gz[k];
         }
     }
 }
