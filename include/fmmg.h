@@ -112,9 +112,11 @@ typedef struct {
                                    0 = the occupancy limit                              */
     int32_t autotune;           /* 1 = the first solve times the candidate launch shapes
                                    (per-class or persistent, plane groups, blocks per
-                                   CU, overlap) on the caller's data, keeps the fastest, and
-                                   records it in tuning_cache; that solve synchronises
-                                   the stream.  A cached entry for the same plan
+                                   CU, overlap) on the caller's data, each run as the
+                                   plan will run it (captured and replayed when
+                                   use_graph is set), keeps the fastest, and records
+                                   it in tuning_cache; that solve synchronises the
+                                   stream.  A cached entry for the same plan
                                    signature is used without timing.                    */
     const char* tuning_cache;   /* JSON file of tuned launch shapes, or NULL            */
     int32_t overlap;            /* 1 (default) = the coarse levels' passes and

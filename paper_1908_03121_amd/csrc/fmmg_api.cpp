@@ -522,25 +522,64 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(FMMG_EHIP, "hipEventCreate"); }
+    if (p->opt.use_graph && !p->capture_stream &&
+        hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return fail(FMMG_EHIP, "hipStreamCreate");
+    }
     double best = 1e300;
     Cand bc = cands[0];
     fmmg_status status = FMMG_OK;
+    // each candidate runs the way the plan will: graph replays when the plan
+    // uses graphs, else eager launches; it is timed as the best of 3 runs of
+    // enough solves to last about 1 ms
     for (const Cand& c : cands) {
         status = apply_shape(p, c.pers, c.groups, c.bpc, c.ovl, st);
         if (status != FMMG_OK) break;
-        enqueue_solve(p, rho, phi, g, st, nullptr);  // warm
-        double t = 1e300;
-        for (int r = 0; r < 3; ++r) {
+        hipGraph_t cg = nullptr;
+        hipGraphExec_t ce = nullptr;
+        if (p->opt.use_graph) {
+            hipError_t e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                enqueue_solve(p, rho, phi, g, p->capture_stream, nullptr);
+                hipError_t le = hipGetLastError();
+                e = hipStreamEndCapture(p->capture_stream, &cg);
+                if (e == hipSuccess) e = le;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&ce, cg, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                if (cg) (void)hipGraphDestroy(cg);
+                status = hip_fail(e, "tuning capture");
+                break;
+            }
+        }
+        auto run = [&]() {
+            if (ce) (void)hipGraphLaunch(ce, st);
+            else enqueue_solve(p, rho, phi, g, st, nullptr);
+        };
+        auto timed = [&](int n, double* ms_out) {
             (void)hipEventRecord(e0, st);
-            enqueue_solve(p, rho, phi, g, st, nullptr);
+            for (int i = 0; i < n; ++i) run();
             (void)hipEventRecord(e1, st);
             hipError_t e = hipEventSynchronize(e1);
             float ms = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) { status = hip_fail(e, "tuning run"); break; }
-            if (ms < t) t = ms;
+            *ms_out = double(ms) / n;
+            return e;
+        };
+        double t = 1e300, one = 0;
+        run();  // warm
+        hipError_t e = timed(1, &one);
+        const int reps = one > 0 ? std::max(1, std::min(8, int(1.0 / one))) : 8;
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+            double ms = 0;
+            e = timed(reps, &ms);
+            t = std::min(t, ms);
         }
-        if (status != FMMG_OK) break;
+        if (ce) (void)hipGraphExecDestroy(ce);
+        if (cg) (void)hipGraphDestroy(cg);
+        if (e != hipSuccess) { status = hip_fail(e, "tuning run"); break; }
         if (t < best) { best = t; bc = c; }
     }
     (void)hipEventDestroy(e0);
