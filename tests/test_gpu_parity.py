@@ -115,6 +115,36 @@ def test_stencil_mode_refined_top_level(shape):
     assert st["pairs"] == ost["cls"]
 
 
+def deep_chain(levels=19, seed=6):
+    """One refined sub-grid per level down to the deepest level the interface
+    allows (19): 8 children per level, one of them refined further, the path
+    wandering between octants; lognormal densities."""
+    rng = np.random.default_rng(seed)
+    subs, c = [(0, 0, 0, 0)], (0, 0, 0)
+    for lv in range(1, levels + 1):
+        kids = [(lv, 2 * c[0] + a, 2 * c[1] + b, 2 * c[2] + d) for a in (0, 1) for b in (0, 1) for d in (0, 1)]
+        subs += kids
+        c = kids[int(rng.integers(0, 8))][1:]
+    t = wl._desc_from_list(subs, (0.0, 0.0, 0.0), 1.0)
+    return t, rng.lognormal(0.0, 1.0, (t.n_leaves, 8, 8, 8))
+
+
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g1"])
+def test_deep_chain_to_level_19(shape):
+    """Twenty levels (cells from 1/8 down to 2^-22 of the domain), so every
+    pass runs its longest level chain and the split, top and downward logic
+    see many coarse levels."""
+    t, rho = deep_chain()
+    assert int(t.level.max()) == 19
+    for ov in (0, 1):
+        phi, g, st = run([t], rho, overlap=ov, **SHAPES[shape])
+        pr, gr, ost = oracle.solve(t, rho, with_stats=True)
+        errs = field_errors(phi, g, pr, gr)
+        print(f"  overlap {ov}: errors {errs}", flush=True)
+        assert max(errs) < TOL64
+        assert st["pairs"] == ost["cls"] and st["pairs_top"] == ost["top"]
+
+
 def test_correction_off_matches_uncorrected_oracle():
     W = wl.small_amr(2)
     t = W.trees[0]
@@ -198,6 +228,31 @@ def test_batched_trees_equal_each_tree_alone(shape):
         assert max(field_errors(phi[off:off + n], g[off:off + n], pr, gr)) < TOL64
         off += n
     assert st["n_trees"] == 4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c1_full_size_autotuned_graph(tmp_path, precision):
+    """The uniform level-3 field in exactly the configuration the benchmark
+    times (autotuned launch shape with overlap up to 2, graph replays), every
+    leaf cell against the oracle."""
+    W = wl.c1()
+    t = W.trees[0]
+    r = torch.tensor(W.rho, dtype=torch.float64, device=DEV)
+    with fm.Plan([t], precision=precision, autotune=True, tuning_cache=str(tmp_path / "tune.json"),
+                 use_graph=True, overlap=2) as p:
+        phi_t, g_t = p.solve(r)
+        for _ in range(2):
+            p.solve(r, phi_t, g_t)  # replays of the captured graph
+        torch.cuda.synchronize()
+        sh = p.launch_shape()
+    print(f"  c1 {precision} shape {sh}", flush=True)
+    pr, gr = oracle.solve(t, W.rho)
+    errs = field_errors(phi_t.cpu().numpy(), g_t.cpu().numpy(), pr, gr)
+    print(f"  errors {errs}", flush=True)
+    if precision == "fp64":
+        assert max(errs) < TOL64
+    else:
+        assert errs[0] < 2e-6 and max(errs[1:]) < 2e-5
 
 
 def test_c4_full_batch_autotuned_sampled(tmp_path):
