@@ -31,12 +31,18 @@ constexpr int NS = 8;          // cells per sub-grid edge
 constexpr int NCELL = 512;     // cells per sub-grid
 constexpr int REACH = 5;       // max |d_i| of the stencil
 constexpr int PW = NS + 2 * REACH;  // 18: edge of the source window around a sub-grid
-constexpr int PCELLS = PW * PW;     // 324 cells in one source z-plane window
-constexpr int PRS = 20;             // LDS row stride (cells) of windows and boxes: with
+constexpr int PCELLS = PW * PW;     // 324 cells in one source plane window
+constexpr int PRS = 20;             // LDS row stride (cells) of the monopole mass box: with
                                     // lanes y-fastest (lane = x*8 + y), each pass of 32
                                     // lanes reading 8-byte words over 64 banks hits
                                     // distinct banks for every mirrored stencil offset
-constexpr int PSLOTS = PW * PRS;    // 360 LDS cells per plane window
+constexpr int PSLOTS = PW * PRS;    // 360 LDS cells per box plane
+constexpr int MP_PRS = PW;          // 18: row stride of the multipole plane window, whose
+                                    // records sit in 16-byte groups of components: each
+                                    // pass of 16 lanes reading 16-byte groups then hits
+                                    // distinct bank groups (rows of both lane parities
+                                    // differ mod 8, and 2 * 18 = 2 mod 16 spreads them)
+constexpr int MP_SLOTS = PW * MP_PRS;  // 324
 constexpr int NREC = 16;       // record components of a refined cell
 constexpr int NLOC = 19;       // Taylor components of a refined cell
 constexpr int NLEAF = 4;       // phi, gx, gy, gz of a leaf cell

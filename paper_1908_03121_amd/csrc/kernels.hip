@@ -2,12 +2,14 @@
 // (arXiv:1908.03121, Sec. 4.3: upward pass, same-level stencil interactions
 // with order-3 multipoles and the angular-momentum correction, downward pass).
 //
-// Thread mapping of the same-level kernels: a wavefront holds one z-plane of
-// 8x8 target cells (stencil kernels: lane = x*8 + y; top level: y*8 + x).
-// Cells of different parity use mirror images of one canonical stencil, so
-// every lane of a wave walks the same entry list (uniform control flow,
-// scalar table loads) with its own signs.
-// Sources are staged in LDS one z-plane window (18 x 18 cells) at a time.
+// Thread mapping of the same-level kernels: a wavefront holds one plane of
+// 8x8 target cells (multipole items: a z- or y-plane, lane = u*8 + v in the
+// plane's frame; monopole items: a lane owns a z-column of 8 targets; top
+// level: z-plane, lane = y*8 + x).  Cells of different parity use mirror
+// images of one canonical stencil, so every lane of a wave walks the same
+// entry list (uniform control flow, scalar table loads) with its own signs.
+// Sources are staged in LDS one 18 x 18 plane window (multipole items) or
+// the 18^3 box (monopole items) at a time.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -332,12 +334,12 @@ __global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__
 // step 2: same-level interactions as work items of 256 threads (4 waves)
 // ---------------------------------------------------------------------------
 // LDS of one item block: the largest of the multipole plane window (16
-// records x 18 rows of 20 cells + leaf flags), the monopole mass box (18
+// record components x 18 x 18 cells + leaf flags), the monopole mass box (18
 // planes x 18 rows of 20 cells), the 4-wave reduction buffer (doubles) and
 // the top-level source tile, followed by the target's 27 neighbour codes.
 template <typename P>
 struct Smem {
-    static constexpr int PLANE = NREC * PSLOTS * int(sizeof(P)) + PSLOTS;
+    static constexpr int PLANE = NREC * MP_SLOTS * int(sizeof(P)) + MP_SLOTS;
     static constexpr int BOX = PW * PSLOTS * int(sizeof(P));
     static constexpr int RED = 4 * NLOC * 64 * 8;
     static constexpr int TOP = NREC * 256 * int(sizeof(P)) + 4 * 256 * 4;  // top-level source tile
@@ -390,8 +392,12 @@ __device__ __forceinline__ void swap_yz_o(T* o) {
 template <bool LEAF_T, bool MIXED, int SWEEP>
 __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int group, unsigned char* smem) {
     using P = typename std::conditional<MIXED, float, double>::type;
-    P* sh = reinterpret_cast<P*>(smem);
-    unsigned char* leafflag = smem + NREC * PSLOTS * sizeof(P);
+    // the window's records in 16-byte groups of V components: component k of
+    // slot c is element k % V of group (k / V) * MP_SLOTS + c
+    constexpr int V = 16 / int(sizeof(P));
+    using PV = typename std::conditional<MIXED, float4, double2>::type;
+    const PV* shv = reinterpret_cast<const PV*>(smem);
+    unsigned char* leafflag = smem + NREC * MP_SLOTS * sizeof(P);
     int* nb = reinterpret_cast<int*>(smem + Smem<P>::NBR_OFF);
 
     const int t = item_tid(), lane = t & 63;
@@ -442,9 +448,9 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     acc.zero();
     const P hx = P(-h * sx), hy = P(-h * sy);
     // source cell of canonical offset (dx, dy) in the plane window:
-    // c = lbase + sx*dx + (sy*PRS)*dy  (mirror signs per lane)
-    const int lbase = (y + REACH) * PRS + (x + REACH);
-    const int syw = sy * PRS;
+    // c = lbase + sx*dx + (sy*MP_PRS)*dy  (mirror signs per lane)
+    const int lbase = (y + REACH) * MP_PRS + (x + REACH);
+    const int syw = sy * MP_PRS;
 
     for (int gi = i0; gi < i1; ++gi) {
         const int dz = sz * (DZ0 + gi);
@@ -474,7 +480,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
                 const int cr = t + u * 256;
                 if (cr < PCELLS) {
                     const int wx = cr % PW, wy = cr / PW;
-                    const int c = wy * PRS + wx;
+                    const int c = wy * MP_PRS + wx;
                     const int lx = wx - REACH, ly = wy - REACH;
                     const int ox = lx < 0 ? -1 : (lx >= NS ? 1 : 0);
                     const int oy = ly < 0 ? -1 : (ly >= NS ? 1 : 0);
@@ -492,10 +498,18 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
                         swap_yz_q(v + R_Q);
                         swap_yz_o(v + R_O);
                     }
+                    P w[NREC];
 #pragma unroll
                     for (int k = 0; k < NREC; ++k)
-                        sh[k * PSLOTS + c] = kind == 1 ? P(v[k])
-                                             : (k == 0 && kind == 0 && !LEAF_T ? P(mm) : P(0));
+                        w[k] = kind == 1 ? P(v[k]) : (k == 0 && kind == 0 && !LEAF_T ? P(mm) : P(0));
+#pragma unroll
+                    for (int j = 0; j < NREC / V; ++j) {
+                        PV pv;
+                        P* pp = reinterpret_cast<P*>(&pv);
+#pragma unroll
+                        for (int i = 0; i < V; ++i) pp[i] = w[j * V + i];
+                        reinterpret_cast<PV*>(smem)[j * MP_SLOTS + c] = pv;
+                    }
                     if (!LEAF_T) leafflag[c] = kind == 0;
                 }
             }
@@ -515,7 +529,12 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
             const int c = lbase + __mul24(sx, dxc) + __mul24(syw, dyc);
             P src[NREC];
 #pragma unroll
-            for (int k = 0; k < NREC; ++k) src[k] = sh[k * PSLOTS + c];
+            for (int j = 0; j < NREC / V; ++j) {
+                const PV pv = shv[j * MP_SLOTS + c];
+                const P* pp = reinterpret_cast<const P*>(&pv);
+#pragma unroll
+                for (int i = 0; i < V; ++i) src[j * V + i] = pp[i];
+            }
             const P X = hx * P(dxc) + (P(dAx) - src[R_DX]);
             const P Y = hy * P(dyc) + (P(dAy) - src[R_DY]);
             const P Z = zoff + (P(dAz) - src[R_DZ]);
