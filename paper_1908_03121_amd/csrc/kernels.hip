@@ -145,14 +145,14 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
         a.l2[2] = fmaP(md2, XY, a.l2[2]);
         a.l2[3] = fmaP(md2, XZ, a.l2[3]);
         a.l2[4] = fmaP(md2, YZ, a.l2[4]);
-        const P tx = md3 * XX, ty = md3 * YY, m3 = P(3) * md2;
-        const P bx = tx + md2, cy = ty + md2;
-        a.l3[0] = fmaP(X, tx + m3, a.l3[0]);
+        const P m3 = P(3) * md2;
+        const P bx = fmaP(md3, XX, md2), cy = fmaP(md3, YY, md2);
+        a.l3[0] = fmaP(X, fmaP(md3, XX, m3), a.l3[0]);
         a.l3[1] = fmaP(Y, bx, a.l3[1]);
         a.l3[2] = fmaP(Z, bx, a.l3[2]);
         a.l3[3] = fmaP(X, cy, a.l3[3]);
         a.l3[4] = fmaP(md3 * XY, Z, a.l3[4]);
-        a.l3[5] = fmaP(Y, ty + m3, a.l3[5]);
+        a.l3[5] = fmaP(Y, fmaP(md3, YY, m3), a.l3[5]);
         a.l3[6] = fmaP(Z, cy, a.l3[6]);
     }
     // correction terms: always accumulated (no branch in the pair body); the
