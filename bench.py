@@ -176,8 +176,10 @@ def traffic_entry(kernel_name):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    # a c1 solve takes about 0.2 ms: 100 steps keep the timed region long
+    # enough (about 20 ms) that a short host or clock hiccup does not dominate it
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--forms", default="all", choices=["all", "c1"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile", action="store_true",
@@ -269,7 +271,8 @@ def main():
     forms["c1_fp64"]["residual_force_torque"] = residuals(np, c1.trees, c1.rho, g64)
 
     log("c1 fp64, the paper's per-sub-grid launch model (128 streams, eager)")
-    pm = time_paper_model(fm, torch, c1.trees, c1.rho, "fp64", K, W, shape["plane_groups"], (phi64, g64))
+    pm = time_paper_model(fm, torch, c1.trees, c1.rho, "fp64", min(K, 20), min(W, 5), shape["plane_groups"],
+                          (phi64, g64))
     pm["default_shape_speedup"] = pm["ms_per_step"] / head["ms_per_step"]
     log(f"  {pm['ms_per_step']:.3f} ms/step, {pm['launches_per_step']} launches")
     forms["c1_fp64_paper_launch_model"] = pm
@@ -294,7 +297,7 @@ def main():
             forms["c2_" + prec] = r
             if prec == "fp64":
                 log("c2 fp64, the paper's per-sub-grid launch model (128 streams, eager)")
-                pm = time_paper_model(fm, torch, c2.trees, c2.rho, "fp64", K, W,
+                pm = time_paper_model(fm, torch, c2.trees, c2.rho, "fp64", min(K, 10), min(W, 3),
                                       r["launch_shape"]["plane_groups"], ref)
                 pm["default_shape_speedup"] = pm["ms_per_step"] / r["ms_per_step"]
                 log(f"  {pm['ms_per_step']:.3f} ms/step, {pm['launches_per_step']} launches")

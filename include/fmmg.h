@@ -215,6 +215,7 @@ fmmg_status fmmg_leaf_order(const fmmg_plan* plan, int32_t* leaf_desc_index);
  * rho: device float64 [n_leaves][512], finite and >= 0 (not checked here; see
  *      fmmg_check_density);
  * phi: device float64 [n_leaves][512]; g: device float64 [n_leaves][3][512].
+ * The three buffers must not overlap (FMMG_EINVAL).
  * Asynchronous: returns once the work is enqueued. */
 fmmg_status fmmg_solve(fmmg_plan* plan, const double* rho, double* phi, double* g,
                        void* hip_stream);

@@ -790,6 +790,15 @@ fmmg_status fmmg_get_launch_shape(const fmmg_plan* p, fmmg_launch_shape* out) {
 fmmg_status fmmg_solve(fmmg_plan* p, const double* rho, double* phi, double* g, void* hip_stream) {
     if (!p) return fail(FMMG_EINVAL, "fmmg_solve: plan is NULL");
     if (!p->hp.leaf_sub.empty() && (!rho || !phi || !g)) return fail(FMMG_EINVAL, "fmmg_solve: null buffer");
+    {
+        // the kernels read rho while writing phi and g: no two may share memory
+        const uintptr_t n = uintptr_t(p->hp.leaf_sub.size()) * NCELL * sizeof(double);
+        const uintptr_t r0 = reinterpret_cast<uintptr_t>(rho), p0 = reinterpret_cast<uintptr_t>(phi),
+                        g0 = reinterpret_cast<uintptr_t>(g);
+        auto overlap = [](uintptr_t a, uintptr_t na, uintptr_t b, uintptr_t nb) { return a < b + nb && b < a + na; };
+        if (n > 0 && (overlap(r0, n, p0, n) || overlap(r0, n, g0, 3 * n) || overlap(p0, n, g0, 3 * n)))
+            return fail(FMMG_EINVAL, "fmmg_solve: rho, phi and g overlap");
+    }
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
     if (dev != p->device) return fail(FMMG_EINVAL, "fmmg_solve: plan belongs to another device");

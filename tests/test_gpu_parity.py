@@ -476,6 +476,18 @@ def test_density_check_and_argument_errors():
             p.solve(r[:-1].contiguous())
         with pytest.raises(ValueError):
             p.solve(r.float())
+        # overlapping buffers are refused before any launch
+        n = W.rho.shape[0]
+        big = torch.zeros(5 * n * 512, dtype=torch.float64, device=DEV)
+        with pytest.raises(fm.FmmgError) as e:
+            fm.fmmg_solve(p._h, r, r.view(n, 512), big[:3 * n * 512].view(n, 3, 512))
+        assert e.value.status == fm.FMMG_EINVAL and "overlap" in str(e.value)
+        with pytest.raises(fm.FmmgError):
+            fm.fmmg_solve(p._h, r, big[:n * 512].view(n, 512), big[n * 512 - 8:4 * n * 512 - 8].view(n, 3, 512))
+        phi, g = p.solve(r, big[:n * 512].view(n, 512), big[n * 512:4 * n * 512].view(n, 3, 512))
+        torch.cuda.synchronize()
+        pr, gr = oracle.solve(W.trees[0], W.rho)
+        assert max(field_errors(phi.cpu().numpy(), g.cpu().numpy(), pr, gr)) < TOL64
 
 
 @pytest.mark.parametrize("groups", [1, 3])
