@@ -193,8 +193,9 @@ def main():
                     choices=[f"{k}_g{g}" for k in ("per_class", "persistent") for g in (1, 2, 3, 5)])
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
-              "multi-GPU sharding of the octree is described in DESIGN.md but not built.",
+        print(f"bench.py: this library runs on exactly one GPU (asked for {args.gpus}); "
+              "sharding the octree over several GPUs (by sub-grid ranges, with halo exchanges "
+              "per level) is designed but not built.",
               file=sys.stderr)
         sys.exit(2)
 
