@@ -173,3 +173,12 @@ def test_planner_sweep_choice(name):
     st = fm.fmmg_count_pairs([t])
     print(f"  {name}: {n_y} targets along y", flush=True)
     assert st["sweep_y_targets"] == n_y and n_y > 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "exactly one GPU" in r.stderr and r.stdout == ""
