@@ -531,6 +531,12 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
     double best = 1e300;
     Cand bc = cands[0];
     fmmg_status status = FMMG_OK;
+    // the winner's captured graph becomes the plan's graph (it was captured
+    // for these buffers), so the solves replay the very instance that was
+    // timed
+    hipGraph_t best_cg = nullptr;
+    hipGraphExec_t best_ce = nullptr;
+    int64_t best_launches = 0;
     // each candidate runs the way the plan will: graph replays when the plan
     // uses graphs, else eager launches; it is timed as the best of 3 runs of
     // enough solves to last about 1 ms
@@ -539,10 +545,11 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
         if (status != FMMG_OK) break;
         hipGraph_t cg = nullptr;
         hipGraphExec_t ce = nullptr;
+        int64_t launches = 0;
         if (p->opt.use_graph) {
             hipError_t e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                enqueue_solve(p, rho, phi, g, p->capture_stream, nullptr);
+                launches = enqueue_solve(p, rho, phi, g, p->capture_stream, nullptr);
                 hipError_t le = hipGetLastError();
                 e = hipStreamEndCapture(p->capture_stream, &cg);
                 if (e == hipSuccess) e = le;
@@ -577,16 +584,38 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
             e = timed(reps, &ms);
             t = std::min(t, ms);
         }
-        if (ce) (void)hipGraphExecDestroy(ce);
-        if (cg) (void)hipGraphDestroy(cg);
+        const bool better = e == hipSuccess && t < best;
+        if (better) {
+            if (best_ce) (void)hipGraphExecDestroy(best_ce);
+            if (best_cg) (void)hipGraphDestroy(best_cg);
+            best_ce = ce;
+            best_cg = cg;
+            best_launches = launches;
+        } else {
+            if (ce) (void)hipGraphExecDestroy(ce);
+            if (cg) (void)hipGraphDestroy(cg);
+        }
         if (e != hipSuccess) { status = hip_fail(e, "tuning run"); break; }
-        if (t < best) { best = t; bc = c; }
+        if (better) { best = t; bc = c; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (status != FMMG_OK) return status;
+    auto drop_best = [&]() {
+        if (best_ce) (void)hipGraphExecDestroy(best_ce);
+        if (best_cg) (void)hipGraphDestroy(best_cg);
+    };
+    if (status != FMMG_OK) { drop_best(); return status; }
     status = apply_shape(p, bc.pers, bc.groups, bc.bpc, bc.ovl, st);
-    if (status != FMMG_OK) return status;
+    if (status != FMMG_OK) { drop_best(); return status; }
+    if (best_ce) {
+        drop_graph(p);
+        p->graph = best_cg;
+        p->graph_exec = best_ce;
+        p->g_rho = rho;
+        p->g_phi = phi;
+        p->g_g = g;
+        p->launches = best_launches;
+    }
     p->shape.from_cache = 0;
     p->shape.tuned_ms = best;
     p->tuned = true;
