@@ -105,11 +105,13 @@ __device__ __forceinline__ void oct_rr(const P o[7], P oxzz, P oyzz, P XmZ, P Ym
 // factor -G (applied once per target):
 //   L0 += mb D0 + 1/2 q:D2 - 1/6 o:D3,  L1 += mb D1 + 1/2 q:D3,
 //   L2 += mb D2,  L3 += mb D3,
-//   S  += D4:(o_B - (mb/mA) o_A)   (angular-momentum correction, times -G/6)
+//   S  += D4:(o_B - (mb/mA) o_A) / 6   (angular-momentum correction, times -G)
 // With trace-free tensors and D^(n) = sum of R^k delta^j terms these reduce to
 //   q:D2 = d2 RqR,  (q:D3)_i = d3 R_i RqR + 2 d2 (qR)_i,  o:D3 = d3 o:RRR,
 //   (D4:Q)_i = d4 R_i Q:RRR + 3 d3 (Q:RR)_i,
 // where d0 = 1/r, d1 = -1/r^3, d2 = 3/r^5, d3 = -15/r^7, d4 = 105/r^9.
+// Both octupoles arrive divided by 6 (o and oa hold o/6), which folds the
+// 1/6 of L0 into the staged data and leaves S scaled by 1/6.
 // FULL: refined target (L2, L3 and its own octupole oa enter; oa[7], oa[8]
 // hold its dependent components xzz, yzz).
 template <bool FULL, typename P>
@@ -128,12 +130,12 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
     const P ux = fmaP(q[0], X, fmaP(q[2], Y, q[3] * Z));
     const P uy = fmaP(q[2], X, fmaP(q[1], Y, q[4] * Z));
     const P uz = fmaP(q[3], X, fmaP(q[4], Y, qzz * Z));
-    const P RqR = fmaP(X, ux, fmaP(Y, uy, Z * uz));
+    const P hRqR = P(0.5) * fmaP(X, ux, fmaP(Y, uy, Z * uz));
     P wb[3];
     oct_rr(o, -o[0] - o[3], -o[1] - o[5], XmZ, YmZ, XY2, XZ2, YZ2, wb);
-    const P BRRR = fmaP(X, wb[0], fmaP(Y, wb[1], Z * wb[2]));
-    a.l0 = fmaP(mb, d0, fmaP(P(0.5) * d2, RqR, fmaP(P(-1.0 / 6.0) * d3, BRRR, a.l0)));
-    const P c1 = fmaP(mb, d1, P(0.5) * d3 * RqR);
+    const P BRRR = fmaP(X, wb[0], fmaP(Y, wb[1], Z * wb[2]));  // o:RRR / 6
+    a.l0 = fmaP(mb, d0, fmaP(d2, hRqR, fmaP(-d3, BRRR, a.l0)));
+    const P c1 = fmaP(mb, d1, d3 * hRqR);
     a.l1[0] = fmaP(c1, X, fmaP(d2, ux, a.l1[0]));
     a.l1[1] = fmaP(c1, Y, fmaP(d2, uy, a.l1[1]));
     a.l1[2] = fmaP(c1, Z, fmaP(d2, uz, a.l1[2]));
@@ -396,7 +398,6 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     // slot c is element k % V of group (k / V) * MP_SLOTS + c
     constexpr int V = 16 / int(sizeof(P));
     using PV = typename std::conditional<MIXED, float4, double2>::type;
-    const PV* shv = reinterpret_cast<const PV*>(smem);
     unsigned char* leafflag = smem + NREC * MP_SLOTS * sizeof(P);
     int* nb = reinterpret_cast<int*>(smem + Smem<P>::NBR_OFF);
 
@@ -428,7 +429,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         dAy = r[R_DY * NCELL + q];
         dAz = r[R_DZ * NCELL + q];
 #pragma unroll
-        for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q]);
+        for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q] * (1.0 / 6.0));
         if (SWEEP) {
             swap_yz(dAy, dAz);
             swap_yz_o(oa);
@@ -446,11 +447,15 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
 
     Acc<double> acc;
     acc.zero();
-    const P hx = P(-h * sx), hy = P(-h * sy);
-    // source cell of canonical offset (dx, dy) in the plane window:
-    // c = lbase + sx*dx + (sy*MP_PRS)*dy  (mirror signs per lane)
-    const int lbase = (y + REACH) * MP_PRS + (x + REACH);
-    const int syw = sy * MP_PRS;
+    // positions in the frame, relative to the centre of the target sub-grid's
+    // first cell: the target's COM here, the sources' COM in the window, so
+    // that a pair's separation is one subtraction per axis
+    const P tu = P(fma(h, double(x), dAx)), tv = P(fma(h, double(y), dAy));
+    const P tw = P(fma(h, double(zt), dAz));
+    // byte offset of the source cell of canonical offset (dx, dy) in one
+    // component group of the plane window:
+    // lbase + sx * 16 dx + sy * (16 MP_PRS) dy  (mirror signs per lane)
+    const int lbase = ((y + REACH) * MP_PRS + (x + REACH)) * 16;
 
     for (int gi = i0; gi < i1; ++gi) {
         const int dz = sz * (DZ0 + gi);
@@ -498,10 +503,17 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
                         swap_yz_q(v + R_Q);
                         swap_yz_o(v + R_O);
                     }
+                    // the COM offset becomes a position (frame coordinates of the
+                    // cell centre plus the offset) and the octupole is divided by 6
+                    const double pos[3] = {double(lx), double(ly), double(zs)};
                     P w[NREC];
 #pragma unroll
-                    for (int k = 0; k < NREC; ++k)
-                        w[k] = kind == 1 ? P(v[k]) : (k == 0 && kind == 0 && !LEAF_T ? P(mm) : P(0));
+                    for (int k = 0; k < NREC; ++k) {
+                        double val = kind == 1 ? v[k] : (k == 0 && kind == 0 && !LEAF_T ? mm : 0.0);
+                        if (k >= R_DX && k <= R_DZ) val = fma(h, pos[k - R_DX], val);
+                        if (k >= R_O) val *= 1.0 / 6.0;
+                        w[k] = P(val);
+                    }
 #pragma unroll
                     for (int j = 0; j < NREC / V; ++j) {
                         PV pv;
@@ -515,7 +527,6 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
             }
         }
         __syncthreads();
-        const P zoff = P(-h * dz);
         // mixed form: FP32 partial sums per source plane, flushed into the FP64
         // accumulators after the plane; FP64 form: accumulate directly
         Acc<P> part_store;
@@ -525,19 +536,19 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         auto reaches = [&](int e) { return !LEAF_T || ((tab[e] >> 16) & cols) != 0; };
         auto one = [&](int e) {
             const int ent = tab[e];
-            const int dxc = (ent & 255) - 8, dyc = ((ent >> 8) & 255) - 8;
-            const int c = lbase + __mul24(sx, dxc) + __mul24(syw, dyc);
+            const int dx16 = ((ent & 255) - 8) * 16, dy16 = (((ent >> 8) & 255) - 8) * (16 * MP_PRS);
+            const unsigned char* cs = smem + lbase + __mul24(sx, dx16) + __mul24(sy, dy16);
             P src[NREC];
 #pragma unroll
             for (int j = 0; j < NREC / V; ++j) {
-                const PV pv = shv[j * MP_SLOTS + c];
+                const PV pv = *reinterpret_cast<const PV*>(cs + j * (MP_SLOTS * 16));
                 const P* pp = reinterpret_cast<const P*>(&pv);
 #pragma unroll
                 for (int i = 0; i < V; ++i) src[j * V + i] = pp[i];
             }
-            const P X = hx * P(dxc) + (P(dAx) - src[R_DX]);
-            const P Y = hy * P(dyc) + (P(dAy) - src[R_DY]);
-            const P Z = zoff + (P(dAz) - src[R_DZ]);
+            const P X = tu - src[R_DX];
+            const P Y = tv - src[R_DY];
+            const P Z = tw - src[R_DZ];
             pair_terms<!LEAF_T, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], inv_ma, oa, use_corr, part);
         };
         const int fb = c_tab.mp_far_begin[gi], fe = fb + c_tab.mp_far_count[gi];
@@ -556,9 +567,8 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
             for (int e = nbg + w; e < ne; e += 4) {
                 if (!LEAF_T) {
                     const int ent = tab[e];
-                    const int dxc = (ent & 255) - 8, dyc = ((ent >> 8) & 255) - 8;
-                    const int c = lbase + __mul24(sx, dxc) + __mul24(syw, dyc);
-                    if (!leafflag[c]) continue;
+                    const int dx16 = ((ent & 255) - 8) * 16, dy16 = (((ent >> 8) & 255) - 8) * (16 * MP_PRS);
+                    if (!leafflag[(lbase + __mul24(sx, dx16) + __mul24(sy, dy16)) >> 4]) continue;
                 }
                 if (reaches(e)) one(e);
             }
@@ -586,7 +596,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     }
     __syncthreads();
     const double G = cx.G;
-    const double gs = use_corr ? -G / 6.0 : 0.0;
+    const double gs = use_corr ? -G : 0.0;  // S holds the correction / 6
     auto sum4 = [&](int k, int l) {
         return red[(0 * NLOC + k) * 64 + l] + red[(1 * NLOC + k) * 64 + l] +
                red[(2 * NLOC + k) * 64 + l] + red[(3 * NLOC + k) * 64 + l];
@@ -599,7 +609,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
             out[k * NCELL + (l >> 3) * VS + (l & 7)] = (k >= T_S ? gs : -G) * sum4(k, l);
         }
     } else {
-        // own terms from refined sources: phi = -G L0;  g = G L1 + (-G/6) S
+        // own terms from refined sources: phi = -G L0;  g = G L1 - G S
         double* out = cx.Lf3 + size_t(T.slot3) * NLEAF * NCELL + zt * WS;
         if (t < 64) {
             const int o = (t >> 3) * VS + (t & 7);
@@ -819,7 +829,7 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
         dAx = r[R_DX * NCELL + q];
         dAy = r[R_DY * NCELL + q];
         dAz = r[R_DZ * NCELL + q];
-        for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q]);
+        for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q] * (1.0 / 6.0));
         oa[7] = -oa[0] - oa[3];
         oa[8] = -oa[1] - oa[5];
     } else {
@@ -829,7 +839,8 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
     const bool use_corr = cx.corr != 0;
     Acc<P> acc;
     acc.zero();
-    // sources staged through LDS, 256 per tile: 16 record values and the
+    // sources staged through LDS, 256 per tile: 16 record values (octupole
+    // divided by 6, as the pair terms take it) and the
     // global integer cell coordinates (w = 1 for a refined sub-grid's cell)
     P* sv = reinterpret_cast<P*>(smem);
     int* sc = reinterpret_cast<int*>(smem + NREC * 256 * sizeof(P));
@@ -846,7 +857,7 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
             if (S.kind == 1) {
                 const double* r = cx.rec + size_t(S.idx) * NREC * NCELL + cq;
 #pragma unroll
-                for (int k = 0; k < NREC; ++k) sv[k * 256 + t] = P(r[k * NCELL]);
+                for (int k = 0; k < NREC; ++k) sv[k * 256 + t] = P(r[k * NCELL] * (k >= R_O ? 1.0 / 6.0 : 1.0));
             } else {
                 sv[t] = P(cx.mass[size_t(S.idx) * NCELL + cq]);
 #pragma unroll
@@ -952,7 +963,7 @@ __global__ __launch_bounds__(256, 3) void k_persist(Ctx cx, const Item* __restri
 // step 3: downward pass
 // ---------------------------------------------------------------------------
 // Total expansion of a top-level target under the all-pairs rule: the sum of
-// its partial slots in a fixed order, scaled (-G for L0..L3, -G/6 for S).
+// its partial slots in a fixed order, scaled by -G (S holds the correction / 6).
 __device__ __forceinline__ double top_total(const Ctx& cx, const SubDev& T, int k, int q) {
     const TopReduce R = cx.top_reds[T.red];
     const double* base = cx.part + (size_t(R.part_begin) * NLOC + k) * NCELL + q;
@@ -962,7 +973,7 @@ __device__ __forceinline__ double top_total(const Ctx& cx, const SubDev& T, int 
         const double t = base[size_t(p < R.n_part ? p : R.n_part - 1) * (NLOC * NCELL)];
         v += p < R.n_part ? t : 0.0;
     }
-    return (k >= T_S ? (cx.corr ? -cx.G / 6.0 : 0.0) : -cx.G) * v;
+    return (k >= T_S && !cx.corr ? 0.0 : -cx.G) * v;
 }
 
 // Parent expansion (L0, L1, trace-free L2, L3, correction dg) re-expanded at
