@@ -45,16 +45,23 @@ def algorithmic_flops(st):
             + FLOP_PAIR_LEAF_MP * p[3])
 
 
-TUNE_CACHE = os.path.join(os.environ.get("TMPDIR", "/tmp"), "fmmg_tuning.json")
+def parse_shape(spec):
+    """'per_class_g5_b3_o1' or 'persistent_g2_b3_o0' -> Plan keyword arguments."""
+    kind, rest = spec.split("_g")
+    g, b, o = rest.split("_")
+    assert kind in ("per_class", "persistent") and b[0] == "b" and o[0] == "o", spec
+    return dict(persistent=kind == "persistent", plane_groups=int(g), blocks_per_cu=int(b[1:]),
+                overlap=int(o[1:]))
 
 
-def time_form(fm, torch, trees, rho_np, precision, steps, warmup, use_graph=True):
+def time_form(fm, torch, trees, rho_np, precision, steps, warmup, use_graph=True, shape=None):
     """Plans with the launch-shape tuner (its timing runs happen in the first,
-    untimed solve), then times `steps` graph replays."""
+    untimed solve; no cache file, so every run tunes on its own), or in the
+    given shape, then times `steps` graph replays."""
     dev = torch.device("cuda:0")
     rho = torch.tensor(rho_np, dtype=torch.float64, device=dev)
-    with fm.Plan(trees, precision=precision, use_graph=use_graph, autotune=True,
-                 tuning_cache=TUNE_CACHE, overlap=2) as plan:
+    kw = shape if shape is not None else dict(autotune=True, overlap=2)
+    with fm.Plan(trees, precision=precision, use_graph=use_graph, **kw) as plan:
         phi, g = plan.solve(rho)
         shape = plan.launch_shape()
         for _ in range(warmup):
@@ -191,6 +198,10 @@ def main():
                     help="--profile: blocks per CU of the persistent launch (0 = occupancy limit)")
     ap.add_argument("--shape", default="per_class_g2",
                     choices=[f"{k}_g{g}" for k in ("per_class", "persistent") for g in (1, 2, 3, 5)])
+    ap.add_argument("--c1-shape", default=None,
+                    help="launch shape of the c1 FP64 form instead of the tuner's choice, e.g. "
+                         "per_class_g5_b3_o1 or persistent_g2_b3_o0 (a profiled run uses the "
+                         "shape an unprofiled run tuned to)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this library runs on exactly one GPU (asked for {args.gpus}); "
@@ -235,7 +246,8 @@ def main():
     log("generating c1 (uniform level-3 octree, 64^3 leaf cells)")
     c1 = wl.c1()
     log("c1 fp64 (graph)")
-    head, phi64, g64, st64 = time_form(fm, torch, c1.trees, c1.rho, "fp64", K, W)
+    head, phi64, g64, st64 = time_form(fm, torch, c1.trees, c1.rho, "fp64", K, W,
+                                       shape=parse_shape(args.c1_shape) if args.c1_shape else None)
     log(f"  {head['ms_per_step']:.3f} ms/step, {head['cell_interactions_per_s']:.4e} pairs/s")
     shape = head["launch_shape"]
     log(f"c1 fp64 stage timing (eager, HIP events), shape {shape}")
