@@ -660,6 +660,11 @@ __device__ __forceinline__ void mono_class(const P* __restrict__ box, int cbeg, 
 #pragma unroll
         for (int j = 0; j < NSRC; ++j) m[j] = col[j * PSLOTS];
         const int rxy = dx * dx + dy * dy;
+        // FP64: phi and gz accumulate straight into the totals (the sign of
+        // odd targets' mirrored dz folded into the kernel value); the x and y
+        // parts share one column sum, scaled by dx and dy once per column.
+        // FP32: all three are column partial sums, flushed to FP64
+        constexpr bool F64 = sizeof(P) == 8;
         P s0[8], s1[8], s2[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) s0[k] = s1[k] = s2[k] = 0;
@@ -672,18 +677,25 @@ __device__ __forceinline__ void mono_class(const P* __restrict__ box, int cbeg, 
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const P mm = m[k + ((k & 1) ? -dzc : dzc) - LO];
-                s0[k] += mm * a;
                 s1[k] += mm * b;
-                if (dzc != 0) s2[k] += mm * cz;
+                if (F64) {
+                    phi[k] = fmaP(double(mm), double(a), phi[k]);
+                    if (dzc != 0) gz[k] = fmaP(double(mm), double((k & 1) ? -cz : cz), gz[k]);
+                } else {
+                    s0[k] += mm * a;
+                    if (dzc != 0) s2[k] += mm * cz;
+                }
             }
         }
         const double fx = double(sx * dx), fy = double(sy * dy);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            phi[k] += double(s0[k]);
+            if (!F64) {
+                phi[k] += double(s0[k]);
+                gz[k] += (k & 1) ? -double(s2[k]) : double(s2[k]);
+            }
             gx[k] += fx * double(s1[k]);
             gy[k] += fy * double(s1[k]);
-            gz[k] += (k & 1) ? -double(s2[k]) : double(s2[k]);
         }
     }
 }
