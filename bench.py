@@ -30,7 +30,7 @@ PEAK_FP32 = 157.3e12     # MI355X FP32 vector (packed), FLOP/s
 PEAK_HBM = 8.0e12        # bytes/s
 
 # Arithmetic of one ordered pair in the kernels' formulation (FMA = 2 flop):
-FLOP_PAIR_REFINED = 204  # refined target: L0..L3 (order 3) + correction (79 FMA, 36 MUL, 9 ADD, 1 RSQ)
+FLOP_PAIR_REFINED = 203  # refined target: L0..L3 (order 3) + correction (79 FMA, 35 MUL, 9 ADD, 1 RSQ)
 FLOP_PAIR_LEAF_MP = 127  # leaf target, multipole source: L0, L1 + correction (45 FMA, 27 MUL, 9 ADD, 1 RSQ)
 FLOP_PAIR_MONO = 6       # leaf <- leaf monopole, lattice kernel tables: 3 FMA
 

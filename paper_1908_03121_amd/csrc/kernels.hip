@@ -110,13 +110,15 @@ __device__ __forceinline__ void oct_rr(const P o[7], P oxzz, P oyzz, P XmZ, P Ym
 //   q:D2 = d2 RqR,  (q:D3)_i = d3 R_i RqR + 2 d2 (qR)_i,  o:D3 = d3 o:RRR,
 //   (D4:Q)_i = d4 R_i Q:RRR + 3 d3 (Q:RR)_i,
 // where d0 = 1/r, d1 = -1/r^3, d2 = 3/r^5, d3 = -15/r^7, d4 = 105/r^9.
-// Both octupoles arrive divided by 6 (o and oa hold o/6), which folds the
-// 1/6 of L0 into the staged data and leaves S scaled by 1/6.
+// The source octupole arrives divided by 6 (o holds o_B/6), which folds the
+// 1/6 of L0 into the staged data and leaves S scaled by 1/6; the target's
+// arrives divided by 6 mA (oa holds o_A/(6 mA), zero for mA = 0), so that
+// its weight in the correction is -mb.
 // FULL: refined target (L2, L3 and its own octupole oa enter; oa[7], oa[8]
 // hold its dependent components xzz, yzz).
 template <bool FULL, typename P>
 __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], const P o[7],
-                                           P inv_ma, const P oa[9], bool corr, Acc<P>& a) {
+                                           const P oa[9], bool corr, Acc<P>& a) {
     const P XX = X * X, YY = Y * Y, ZZ = Z * Z;
     const P r2 = XX + YY + ZZ;
     const P d0 = rsqrt_full(r2);
@@ -165,10 +167,9 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
         if (FULL) {
             P wa[3];
             oct_rr(oa, oa[7], oa[8], XmZ, YmZ, XY2, XZ2, YZ2, wa);
-            const P nrho = -(mb * inv_ma);
-            Qx = fmaP(nrho, wa[0], Qx);
-            Qy = fmaP(nrho, wa[1], Qy);
-            Qz = fmaP(nrho, wa[2], Qz);
+            Qx = fmaP(-mb, wa[0], Qx);
+            Qy = fmaP(-mb, wa[1], Qy);
+            Qz = fmaP(-mb, wa[2], Qz);
         }
         const P QRRR = fmaP(X, Qx, fmaP(Y, Qy, Z * Qz));
         const P t4 = d4 * QRRR, t3 = P(3) * d3;
@@ -428,8 +429,9 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         dAx = r[R_DX * NCELL + q];
         dAy = r[R_DY * NCELL + q];
         dAz = r[R_DZ * NCELL + q];
+        const double os = mA > 0 ? 1.0 / (6.0 * mA) : 0.0;
 #pragma unroll
-        for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q] * (1.0 / 6.0));
+        for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q] * os);
         if (SWEEP) {
             swap_yz(dAy, dAz);
             swap_yz_o(oa);
@@ -439,7 +441,6 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     } else {
         mA = cx.mass[size_t(tidx) * NCELL + q];
     }
-    const P inv_ma = mA > 0 ? P(1.0 / mA) : P(0);
     const bool use_corr = cx.corr != 0;
     const bool do_near = LEAF_T ? true : ((T.flags & 1) != 0);
     const int ng = LEAF_T ? 1 : cx.ngroups;
@@ -549,7 +550,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
             const P X = tu - src[R_DX];
             const P Y = tv - src[R_DY];
             const P Z = tw - src[R_DZ];
-            pair_terms<!LEAF_T, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], inv_ma, oa, use_corr, part);
+            pair_terms<!LEAF_T, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], oa, use_corr, part);
         };
         const int fb = c_tab.mp_far_begin[gi], fe = fb + c_tab.mp_far_count[gi];
         // two independent pairs per iteration: two dependency chains per wave
@@ -841,13 +842,13 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
         dAx = r[R_DX * NCELL + q];
         dAy = r[R_DY * NCELL + q];
         dAz = r[R_DZ * NCELL + q];
-        for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q] * (1.0 / 6.0));
+        const double os = mA > 0 ? 1.0 / (6.0 * mA) : 0.0;
+        for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q] * os);
         oa[7] = -oa[0] - oa[3];
         oa[8] = -oa[1] - oa[5];
     } else {
         mA = cx.mass[size_t(T.idx) * NCELL + q];
     }
-    const P inv_ma = mA > 0 ? P(1.0 / mA) : P(0);
     const bool use_corr = cx.corr != 0;
     Acc<P> acc;
     acc.zero();
@@ -892,9 +893,9 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
             const P Y = P(-h * dy) + (P(dAy) - src[R_DY]);
             const P Z = P(-h * dz) + (P(dAz) - src[R_DZ]);
             if (tref)
-                pair_terms<true, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], inv_ma, oa, use_corr, acc);
+                pair_terms<true, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], oa, use_corr, acc);
             else
-                pair_terms<false, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], inv_ma, oa, use_corr, acc);
+                pair_terms<false, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], oa, use_corr, acc);
         }
     }
     __syncthreads();
