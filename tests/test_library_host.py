@@ -182,3 +182,21 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "exactly one GPU" in r.stderr and r.stdout == ""
+
+
+def test_bench_c1_shape_spec_parses_to_plan_arguments():
+    """--c1-shape names a launch shape as kind, plane groups, blocks per CU and
+    overlap; malformed names are rejected."""
+    import importlib.util
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    assert bench.parse_shape("per_class_g5_b3_o1") == dict(persistent=False, plane_groups=5,
+                                                          blocks_per_cu=3, overlap=1)
+    assert bench.parse_shape("persistent_g2_b0_o0") == dict(persistent=True, plane_groups=2,
+                                                           blocks_per_cu=0, overlap=0)
+    for bad in ("per_class_5_b3_o1", "fused_g1_b1_o0", "per_class_g5_o1_b3"):
+        with pytest.raises((AssertionError, ValueError)):
+            bench.parse_shape(bad)
