@@ -187,7 +187,9 @@ def main():
     # enough (about 20 ms) that a short host or clock hiccup does not dominate it
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--forms", default="all", choices=["all", "c1"])
+    ap.add_argument("--forms", default="all", choices=["all", "c1", "c2-stages"],
+                    help="c2-stages: only eager, stage-timed c2 FP64 solves in the per-class "
+                         "shape (one launch per class), for a kernel trace of the classes' shares")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile", action="store_true",
                     help="short run for hardware counters: 3 eager c1 FP64 solves in the launch "
@@ -241,6 +243,17 @@ def main():
         print(json.dumps({"profile": "c1_fp64", "shape": args.shape, "bpc": args.bpc, "solves": 3,
                           "pairs": st["pairs"],
                           "pairs_top": st["pairs_top"], "copy_bytes_each_way": n * 8}), flush=True)
+        return
+
+    if args.forms == "c2-stages":
+        log("generating c2 (binary-star AMR field)")
+        c2 = wl.c2()
+        shape = dict(persistent=0, plane_groups=1, blocks_per_cu=0)
+        stages, launches, wall, st = stage_times(fm, torch, c2.trees, c2.rho, "fp64", min(K, 10),
+                                                 min(W, 3), shape)
+        print(json.dumps({"profile": "c2_fp64_stages", "shape": "per_class_g1", "stages_ms": stages,
+                          "launches": launches, "eager_ms_per_step": wall, "pairs": st["pairs"],
+                          "pairs_top": st["pairs_top"]}), flush=True)
         return
 
     log("generating c1 (uniform level-3 octree, 64^3 leaf cells)")
