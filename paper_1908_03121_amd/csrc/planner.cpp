@@ -306,15 +306,29 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
     P.level_leaves.assign(size_t(P.max_level) + 1, 0);
     for (const SubDev& S : P.subs)
         if (S.kind == 0) P.level_leaves[size_t(S.level)]++;
+    // downward tasks, one launch per (level, child kind).  Sibling children
+    // read halves of the same lines of their parent's coefficients, and
+    // work-groups go to the 8 XCDs (each with its own L2) in turn by block
+    // index: each parent's children are therefore placed on one lane
+    // (position mod 8), parents spread over the lanes by load
     P.l2l_begin.assign(size_t(2 * P.max_level) + 1, 0);
     for (int l = 0; l < P.max_level; ++l) {
         for (int kind = 1; kind >= 0; --kind) {
             P.l2l_begin[size_t(2 * l + (1 - kind))] = int32_t(P.l2l_tasks.size());
+            std::vector<int32_t> lane[8];
             for (int i = P.level_ref_begin[size_t(l)]; i < P.level_ref_begin[size_t(l) + 1]; ++i) {
                 const int32_t ps = P.ref_by_level[size_t(i)];
+                int j = 0;
+                for (int k = 1; k < 8; ++k)
+                    if (lane[k].size() < lane[j].size()) j = k;
                 for (int e = 0; e < 8; ++e)
-                    if (P.subs[size_t(P.subs[size_t(ps)].child[e])].kind == kind) P.l2l_tasks.push_back(ps * 8 + e);
+                    if (P.subs[size_t(P.subs[size_t(ps)].child[e])].kind == kind) lane[j].push_back(ps * 8 + e);
             }
+            size_t longest = 0;
+            for (const auto& v : lane) longest = std::max(longest, v.size());
+            for (size_t r = 0; r < longest; ++r)
+                for (const auto& v : lane)
+                    if (r < v.size()) P.l2l_tasks.push_back(v[r]);
         }
     }
     P.l2l_begin[size_t(2 * P.max_level)] = int32_t(P.l2l_tasks.size());
