@@ -62,9 +62,10 @@ def lib():
         L.oracle_solve_sampled.argtypes = tree + [_f64p, C.c_double, C.c_int, C.c_int, C.c_int,
                                                   _i32p, _i32p, _f64p, _f64p]
         L.oracle_solve_sampled.restype = C.c_int
-        L.oracle_same_level_subset.argtypes = tree + [_f64p, C.c_double, C.c_int, C.c_int,
-                                                      C.c_int, _i32p, C.POINTER(C.c_double)]
-        L.oracle_same_level_subset.restype = C.c_int64
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_set_threads.restype = C.c_int
+        L.oracle_max_threads.argtypes = []
+        L.oracle_max_threads.restype = C.c_int
         L.oracle_direct_sum.argtypes = tree + [_f64p, C.c_double, _f64p, _f64p]
         L.oracle_direct_sum.restype = C.c_int
         L.oracle_direct_sum_sampled.argtypes = tree + [_f64p, C.c_double, C.c_int, _i32p, _i32p,
@@ -165,15 +166,14 @@ def solve_sampled(tree, rho, leaf_idx, cell_idx, G=1.0, top_all_pairs=True, corr
     return phi, g.reshape(ns, 3)
 
 
-def same_level_subset(tree, rho, targets, G=1.0, top_all_pairs=True, correction=True):
-    targets = np.ascontiguousarray(targets, dtype=np.int32)
-    cs = C.c_double(0.0)
-    pairs = lib().oracle_same_level_subset(*_tree_args(tree), np.ascontiguousarray(rho, np.float64),
-                                           float(G), int(top_all_pairs), int(correction),
-                                           targets.shape[0], targets, C.byref(cs))
-    if pairs < 0:
-        raise RuntimeError(f"oracle_same_level_subset failed with code {pairs}")
-    return int(pairs), cs.value
+def set_threads(n: int) -> int:
+    """OpenMP team size of the oracle's loops (n < 1: the runtime default);
+    returns the size now in effect."""
+    return int(lib().oracle_set_threads(int(n)))
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())
 
 
 def direct_sum(tree, rho, G=1.0):

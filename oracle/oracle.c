@@ -29,6 +29,9 @@
 #include "oracle.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -664,35 +667,27 @@ int oracle_solve_sampled(int n, const int32_t* level, const int32_t* coord,
     return 0;
 }
 
-int64_t oracle_same_level_subset(int n, const int32_t* level, const int32_t* coord,
-                                 const double origin[3], double L0, const double* rho,
-                                 double G, int top_all_pairs, int correction,
-                                 int n_targets, const int32_t* targets, double* out_checksum) {
-    tree_t t;
-    int rc = tree_build(&t, n, level, coord, origin, L0);
-    if (rc) return rc;
-    if (check_rho(&t, rho) || n_targets < 0 || (n_targets > 0 && !targets)) { tree_free(&t); return -1; }
-    for (int i = 0; i < n_targets; ++i)
-        if (targets[i] < 0 || targets[i] >= n) { tree_free(&t); return -1; }
-    moments_t mo;
-    if (moments_alloc(&mo, n)) { tree_free(&t); return -3; }
-    upward(&t, rho, &mo);
-    int64_t pairs = 0;
-    double sum = 0.0;
-    #pragma omp parallel for schedule(dynamic, 16) reduction(+ : pairs, sum)
-    for (long long idx = 0; idx < (long long)n_targets * NCELL; ++idx) {
-        int s = targets[idx / NCELL], q = (int)(idx % NCELL);
-        local_t own;
-        cnt_t k;
-        memset(&k, 0, sizeof(k));
-        cell_own(&t, &mo, G, top_all_pairs, correction, s, q, &own, &k);
-        pairs += k.lev;
-        sum += fabs(own.L0);
-    }
-    if (out_checksum) *out_checksum = sum;
-    moments_free(&mo);
-    tree_free(&t);
-    return pairs;
+/* OpenMP team size of the parallel loops (the solve loops over target
+ * cells); n < 1 restores the runtime default.  Used to report the thread
+ * count a timing ran with and to time the oracle on one core. */
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+    static int dflt = 0;
+    if (!dflt) dflt = omp_get_max_threads();
+    omp_set_num_threads(n >= 1 ? n : dflt);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+int oracle_max_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* ------------------------------------------------------------------------ */

@@ -80,13 +80,11 @@ int oracle_solve_sampled(int n, const int32_t* level, const int32_t* coord,
                          const int32_t* sample_leaf, const int32_t* sample_cell,
                          double* phi, double* g);
 
-/* Same-level step only, for the listed target sub-grids (descriptor indices);
- * returns the number of pairs evaluated.  Used to time the oracle on a
- * bounded sample of a workload.  out_checksum receives sum of |L0|. */
-int64_t oracle_same_level_subset(int n, const int32_t* level, const int32_t* coord,
-                                 const double origin[3], double L0, const double* rho,
-                                 double G, int top_all_pairs, int correction,
-                                 int n_targets, const int32_t* targets, double* out_checksum);
+/* OpenMP threads of the solve loops: oracle_set_threads(n) sets the team
+ * size (n < 1: the runtime default) and returns it; oracle_max_threads()
+ * returns the current one. */
+int oracle_set_threads(int n);
+int oracle_max_threads(void);
 
 /* O(N^2) direct sum over leaf cells as point masses (self excluded). */
 int oracle_direct_sum(int n, const int32_t* level, const int32_t* coord, const double origin[3],

@@ -418,6 +418,23 @@ def test_sampled_solve_matches_full_solve():
     assert np.abs(gs - g[li, :, ci]).max() < 1e-13 * np.abs(g).max()
 
 
+def test_thread_count_changes_nothing():
+    """Each target cell's sums run in a fixed order on one thread, so the
+    solve is bitwise the same on one thread as on all of them (the CPU
+    baseline is timed both ways)."""
+    W = wl.small_amr(2)
+    t = W.trees[0]
+    full = oracle.solve(t, W.rho)
+    assert oracle.set_threads(1) == 1
+    try:
+        one = oracle.solve(t, W.rho)
+        assert oracle.max_threads() == 1
+    finally:
+        n = oracle.set_threads(0)
+    assert n >= 1 and oracle.max_threads() == n
+    assert np.array_equal(one[0], full[0]) and np.array_equal(one[1], full[1])
+
+
 def test_sampled_direct_sum_matches_full_direct_sum():
     W = wl.small_amr(3)
     t = W.trees[0]
