@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define FMMG_VERSION 1
+#define FMMG_VERSION 2
 
 typedef struct fmmg_plan fmmg_plan; /* opaque; owns device tables and workspaces */
 
@@ -69,9 +69,14 @@ typedef enum {
 
 typedef enum {
     FMMG_FP64 = 0,           /* every step in FP64                                            */
-    FMMG_MIXED = 1           /* same-level pair terms in FP32 with FP32 partial sums per
-                                source plane, flushed into FP64 expansions; moments, the
-                                passes, accumulation and the correction's sums in FP64     */
+    FMMG_MIXED = 1,          /* same-level Taylor-coefficient pair terms (multipole and
+                                monopole) in FP32 with FP32 partial sums per source plane
+                                (multipole) or column (monopole), flushed into FP64 sums;
+                                the angular-momentum correction's pair terms evaluated and
+                                summed in FP64; moments, passes and accumulation in FP64  */
+    FMMG_MIXED_F32 = 2       /* as FMMG_MIXED, but the correction's pair terms are also
+                                evaluated in FP32 with FP32 partial sums per source plane
+                                (faster; its correction is FP32-accurate)                  */
 } fmmg_precision;
 
 typedef enum {
@@ -192,49 +197,79 @@ typedef struct {
                                  neighbours) whose plane items run along y          */
 } fmmg_stats;
 
-/* Fills *opt with the defaults listed above. */
+/* Fills *opt with the defaults listed above (interface convention; no
+ * passage of the paper). */
 void fmmg_default_options(fmmg_options* opt);
 
-/* Validates the trees, builds neighbour/parent/child tables, stencil tables
- * and work lists, and allocates device workspaces on the current device.
- * trees: host array [n_trees], n_trees >= 1 (n_trees > 1 is the batched form).
- * opt may be NULL (defaults).  hip_stream: stream for the table uploads.
- * Returns FMMG_ETREE for a malformed tree, FMMG_EUNSUPPORTED if the current
- * device is not gfx950.  On success *out owns everything it allocated. */
+/* Plans the solve of the given octrees (arXiv:1908.03121 Sec. 4.2: an
+ * adaptive octree whose nodes are 8x8x8 sub-grids; Sec. 4.3: the opening
+ * criterion and its 1074-element stencil, the four interaction classes of
+ * refined/leaf targets and sources).  Validates the trees, builds the
+ * neighbour/parent/child tables, the stencil tables and the work lists on the
+ * host, uploads them, and allocates the device workspaces on the current
+ * device.
+ * trees: host array [n_trees], n_trees >= 1 (n_trees > 1 is the batched form);
+ * read during the call only.  opt may be NULL (defaults).  hip_stream: stream
+ * for the table uploads (the call synchronises it).
+ * Errors: FMMG_EINVAL for a bad option, FMMG_ETREE for a malformed tree,
+ * FMMG_ENOMEM, FMMG_EHIP, FMMG_EUNSUPPORTED if the current device is not
+ * gfx950.  On success *out owns everything it allocated (fmmg_plan_destroy);
+ * on failure *out is NULL and nothing is kept. */
 fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32_t n_trees,
                              const fmmg_options* opt, void* hip_stream);
 
-/* Number of leaf sub-grids (the leading dimension of rho, phi and g). */
+/* Number of leaf sub-grids, the leading dimension of rho, phi and g
+ * (interface convention). */
 fmmg_status fmmg_plan_n_leaves(const fmmg_plan* plan, int64_t* n_leaves);
 
-/* leaf_desc_index: host [n_leaves]; entry i = descriptor index of leaf i within
- * its own tree's descriptor. */
+/* leaf_desc_index: host [n_leaves], caller-owned; entry i = descriptor index of
+ * leaf i within its own tree's descriptor (interface convention). */
 fmmg_status fmmg_leaf_order(const fmmg_plan* plan, int32_t* leaf_desc_index);
 
-/* Runs the whole solve (steps 1-3) on hip_stream.
- * rho: device float64 [n_leaves][512], finite and >= 0 (not checked here; see
- *      fmmg_check_density);
- * phi: device float64 [n_leaves][512]; g: device float64 [n_leaves][3][512].
+/* The solve (arXiv:1908.03121 Sec. 4.3, its three steps: leaf masses and the
+ * upward pass of multipole moments, the same-level stencil interactions of the
+ * four classes producing Taylor coefficients, the downward pass; Sec. 4.2 and
+ * 4.3: the correction that conserves linear and angular momentum), on
+ * hip_stream.
+ * rho: device float64 [n_leaves][512], caller-owned, read only; finite and >= 0.
+ * phi: device float64 [n_leaves][512]; g: device float64 [n_leaves][3][512];
+ *      caller-owned, written.
  * The three buffers must not overlap (FMMG_EINVAL).
- * Asynchronous: returns once the work is enqueued. */
+ * Asynchronous: returns once the work is enqueued.  The upward pass checks
+ * every density it reads; a negative or non-finite one is recorded on the
+ * device, without synchronising, and reported as FMMG_EINVAL (naming its flat
+ * index, nothing enqueued) by the first fmmg_solve on
+ * this plan that starts after that solve has completed, or by
+ * fmmg_density_status.  That solve's phi and g are then meaningless. */
 fmmg_status fmmg_solve(fmmg_plan* plan, const double* rho, double* phi, double* g,
                        void* hip_stream);
 
-/* Checks on the device that every density is finite and >= 0; synchronises
- * hip_stream.  Returns FMMG_OK or FMMG_EINVAL (with the first bad index in
- * the error text). */
+/* Reports a negative or non-finite density read by a completed solve on this
+ * plan (the solve's input is cell densities, Sec. 4.3): FMMG_OK with
+ * *bad_index = -1, or FMMG_EINVAL with *bad_index = the smallest such flat
+ * index into rho of that solve.  Host-only, no device call: synchronise the
+ * solves' stream first to cover every enqueued solve.  A report is given once
+ * (this call or the next solve takes it). */
+fmmg_status fmmg_density_status(fmmg_plan* plan, int64_t* bad_index);
+
+/* Checks on the device that every density is finite and >= 0 (the solve's
+ * input, Sec. 4.3); synchronises hip_stream.  Returns FMMG_OK or FMMG_EINVAL
+ * (with the first bad index in the error text). */
 fmmg_status fmmg_check_density(fmmg_plan* plan, const double* rho, void* hip_stream);
 
 /* Sums the stage durations of the solves enqueued with options.timing = 1
  * since the previous call (or plan creation), then starts a new sum.  The
  * caller must have synchronised the solves' stream.  FMMG_EINVAL if the plan
- * was created without timing. */
+ * was created without timing.  (Measurement; no passage of the paper.) */
 fmmg_status fmmg_get_timings(fmmg_plan* plan, fmmg_timings* out);
 
-/* The launch shape the plan uses. */
+/* The launch shape the plan uses (launch_streams: the execution model of
+ * Sec. 5.1; the other fields are this library's own shapes). */
 fmmg_status fmmg_get_launch_shape(const fmmg_plan* plan, fmmg_launch_shape* out);
 
-/* Pair counts and launch counters of the plan (host values; no device work). */
+/* Pair counts and launch counters of the plan (host values; no device work).
+ * paper_flops weights the pairs with the per-interaction flop counts of
+ * Sec. 4.3 (12 for leaf-leaf, 455 otherwise). */
 fmmg_status fmmg_get_stats(const fmmg_plan* plan, fmmg_stats* stats);
 
 /* Releases every device and host resource of the plan; NULL is a no-op.
@@ -245,9 +280,10 @@ void fmmg_plan_destroy(fmmg_plan* plan);
 const char* fmmg_last_error(void);
 
 /* Host-only: validates the trees and counts the ordered pairs per class that
- * a solve with this top_mode evaluates (no device is touched).  stats->pairs,
- * pairs_top, paper_flops, n_leaves, n_refined, max_level and n_trees are
- * filled; the launch counters are zero. */
+ * a solve with this top_mode evaluates under the interaction rule of Sec. 4.3
+ * (no device is touched).  stats->pairs, pairs_top, paper_flops, n_leaves,
+ * n_refined, max_level, n_trees and sweep_y_targets are filled; the launch
+ * counters are zero. */
 fmmg_status fmmg_count_pairs(const fmmg_tree_desc* trees, int32_t n_trees,
                              fmmg_top_mode top_mode, fmmg_stats* stats);
 

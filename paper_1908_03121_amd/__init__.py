@@ -21,13 +21,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfmmg.so")
 
 FMMG_OK, FMMG_EINVAL, FMMG_ETREE, FMMG_ENOMEM, FMMG_EHIP, FMMG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-FMMG_FP64, FMMG_MIXED = 0, 1
+FMMG_FP64, FMMG_MIXED, FMMG_MIXED_F32 = 0, 1, 2
 FMMG_TOP_FULL, FMMG_TOP_STENCIL_ONLY = 0, 1
 _STATUS = {0: "FMMG_OK", -1: "FMMG_EINVAL", -2: "FMMG_ETREE", -3: "FMMG_ENOMEM", -4: "FMMG_EHIP",
            -5: "FMMG_EUNSUPPORTED"}
 
 EXPORTED = ["fmmg_default_options", "fmmg_plan_create", "fmmg_plan_n_leaves", "fmmg_leaf_order",
-            "fmmg_solve", "fmmg_check_density", "fmmg_get_timings", "fmmg_get_launch_shape",
+            "fmmg_solve", "fmmg_density_status", "fmmg_check_density",
+            "fmmg_get_timings", "fmmg_get_launch_shape",
             "fmmg_get_stats", "fmmg_plan_destroy", "fmmg_last_error", "fmmg_count_pairs",
             "fmmg_version"]
 STAGES = ["p2m", "m2m", "top", "mono", "mp_refined", "mp_leaf", "fused", "down"]
@@ -102,6 +103,7 @@ def lib() -> C.CDLL:
         L.fmmg_plan_n_leaves.argtypes = [vp, C.POINTER(C.c_int64)]
         L.fmmg_leaf_order.argtypes = [vp, C.POINTER(C.c_int32)]
         L.fmmg_solve.argtypes = [vp, vp, vp, vp, vp]
+        L.fmmg_density_status.argtypes = [vp, C.POINTER(C.c_int64)]
         L.fmmg_check_density.argtypes = [vp, vp, vp]
         L.fmmg_get_stats.argtypes = [vp, C.POINTER(fmmg_stats)]
         L.fmmg_get_timings.argtypes = [vp, C.POINTER(fmmg_timings)]
@@ -115,6 +117,7 @@ def lib() -> C.CDLL:
         L.fmmg_version.argtypes = []
         L.fmmg_version.restype = C.c_int32
         for name in ("fmmg_plan_create", "fmmg_plan_n_leaves", "fmmg_leaf_order", "fmmg_solve",
+                     "fmmg_density_status",
                      "fmmg_check_density", "fmmg_get_stats", "fmmg_count_pairs", "fmmg_get_timings",
                      "fmmg_get_launch_shape"):
             getattr(L, name).restype = C.c_int
@@ -212,6 +215,14 @@ def fmmg_solve(plan, rho, phi, g, stream=None) -> None:
                             _dptr(g, n * 3 * 512, "g"), _stream_ptr(stream)))
 
 
+def fmmg_density_status(plan) -> int:
+    """-1, or raises FmmgError (FMMG_EINVAL) naming the flat index of a bad
+    density that a completed solve read."""
+    bad = C.c_int64(-1)
+    _check(lib().fmmg_density_status(plan, C.byref(bad)))
+    return int(bad.value)
+
+
 def fmmg_check_density(plan, rho, stream=None) -> None:
     n = fmmg_plan_n_leaves(plan)
     _check(lib().fmmg_check_density(plan, _dptr(rho, n * 512, "rho"), _stream_ptr(stream)))
@@ -251,7 +262,7 @@ class Plan:
                  blocks_per_cu: int = 0, autotune: bool = False, tuning_cache: str | None = None,
                  overlap: int = 1, launch_streams: int = 0, stream=None):
         opt = fmmg_default_options()
-        opt.precision = {"fp64": FMMG_FP64, "mixed": FMMG_MIXED}[precision]
+        opt.precision = {"fp64": FMMG_FP64, "mixed": FMMG_MIXED, "mixed_f32": FMMG_MIXED_F32}[precision]
         opt.top_mode = {"full": FMMG_TOP_FULL, "stencil": FMMG_TOP_STENCIL_ONLY}[top_mode]
         opt.G = float(G)
         opt.angular_correction = int(bool(angular_correction))
@@ -276,6 +287,9 @@ class Plan:
             g = torch.empty((self.n_leaves, 3, 512), dtype=torch.float64, device=rho.device)
         fmmg_solve(self._h, rho, phi, g, stream)
         return phi, g
+
+    def density_status(self) -> int:
+        return fmmg_density_status(self._h)
 
     def check_density(self, rho, stream=None):
         fmmg_check_density(self._h, rho, stream)

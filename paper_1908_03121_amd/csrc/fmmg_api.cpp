@@ -81,9 +81,25 @@ std::vector<TreeIn> to_trees(const fmmg_tree_desc* trees, int32_t n_trees) {
 }
 
 constexpr int TOP_CHUNKS = MAX_TOP_PARTS;
+
+int prec_form(fmmg_precision pr) {
+    return pr == FMMG_MIXED ? PR_MIX : pr == FMMG_MIXED_F32 ? PR_F32 : PR_F64;
+}
 constexpr int MAX_LAUNCH_STREAMS = 128;  // stream pool of the per-sub-grid launch model
 
 }  // namespace
+
+// Per-solve device workspaces of a plan.
+struct fmmg_ws {
+    double* mass = nullptr;   // [n_leaf][512]
+    double* rec = nullptr;    // [n_ref][16][512]
+    double* Lp = nullptr;     // [groups][n_ref][19][512]
+    double* Lr = nullptr;     // [n_ref][19][512]
+    double* Lf = nullptr;     // [n_leaf][4][512]
+    double* Lf3 = nullptr;    // [n_slot3][4][512]
+    double* part = nullptr;   // [top partial slots][19][512]
+    int* counter = nullptr;   // two persistent-launch counter pairs (4 ints)
+};
 
 struct fmmg_plan {
     int device = -1;
@@ -107,16 +123,12 @@ struct fmmg_plan {
     Item* d_items_class = nullptr;
     Item* d_items_lpt = nullptr;
     size_t items_capacity = 0;
-    int* d_counter = nullptr;              // two persistent-launch counter pairs
-    double* d_mass = nullptr;
-    double* d_rec = nullptr;
-    double* d_Lp = nullptr;
-    double* d_Lr = nullptr;
-    double* d_Lf = nullptr;
-    double* d_Lf3 = nullptr;
-    double* d_part = nullptr;
-    unsigned long long* d_bad = nullptr;
+    fmmg_ws ws;                            // plan-owned workspaces
+    unsigned long long* d_bad = nullptr;   // fmmg_check_density's result
     unsigned long long* h_bad = nullptr;
+    unsigned long long* d_rho_bad = nullptr;      // the solves' density flag (see check_rho)
+    unsigned long long* h_rho_bad = nullptr;      // pinned host word it is handed to
+    unsigned long long* h_rho_bad_dev = nullptr;  // the host word's device address
     // launch shape
     fmmg_launch_shape shape;
     bool tuned = false;
@@ -156,11 +168,12 @@ void release(fmmg_plan* p) {
     drop_graph(p);
     void* bufs[] = {p->d_subs, p->d_leaf_sub, p->d_ref_by_level, p->d_top_leaf, p->d_l2l_tasks,
                     p->d_top_src, p->d_top_items, p->d_top_reduce, p->d_items_class, p->d_items_lpt,
-                    p->d_counter, p->d_mass, p->d_rec, p->d_Lp, p->d_Lr, p->d_Lf, p->d_Lf3, p->d_part,
-                    p->d_bad};
+                    p->ws.counter, p->ws.mass, p->ws.rec, p->ws.Lp, p->ws.Lr, p->ws.Lf, p->ws.Lf3,
+                    p->ws.part, p->d_bad, p->d_rho_bad};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     if (p->h_bad) (void)hipHostFree(p->h_bad);
+    if (p->h_rho_bad) (void)hipHostFree(p->h_rho_bad);
     for (auto& set : p->events)
         for (hipEvent_t ev : set)
             if (ev) (void)hipEventDestroy(ev);
@@ -177,17 +190,20 @@ void release(fmmg_plan* p) {
     delete p;
 }
 
-Ctx make_ctx(const fmmg_plan* p, hipStream_t st) {
+Ctx make_ctx(const fmmg_plan* p, const fmmg_ws& w, hipStream_t st) {
     Ctx a;
     a.subs = p->d_subs;
     a.leaf_sub = p->d_leaf_sub;
-    a.mass = p->d_mass;
-    a.rec = p->d_rec;
-    a.Lp = p->d_Lp;
-    a.Lr = p->d_Lr;
-    a.Lf = p->d_Lf;
-    a.Lf3 = p->d_Lf3;
-    a.part = p->d_part;
+    a.mass = w.mass;
+    a.rec = w.rec;
+    a.Lp = w.Lp;
+    a.Lr = w.Lr;
+    a.Lf = w.Lf;
+    a.Lf3 = w.Lf3;
+    a.part = w.part;
+    a.rho_bad = p->d_rho_bad;
+    a.rho_bad_host = p->h_rho_bad_dev;
+    a.flag_out = 0;
     a.top_items = p->d_top_items;
     a.top_src = p->d_top_src;
     a.top_reds = p->d_top_reduce;
@@ -195,7 +211,7 @@ Ctx make_ctx(const fmmg_plan* p, hipStream_t st) {
     a.part_stride = int64_t(p->hp.ref_sub.size()) * NLOC * NCELL;
     a.G = p->opt.G;
     a.corr = p->opt.angular_correction ? 1 : 0;
-    a.mixed = p->opt.precision == FMMG_MIXED ? 1 : 0;
+    a.prec = prec_form(p->opt.precision);
     a.ngroups = p->hp.ngroups;
     a.st = st;
     return a;
@@ -281,13 +297,13 @@ fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int o
 //                    masses, coarse items, parentless-leaf output, refined
 //                    children of levels 0 .. s-1, leaf children of levels
 //                    0 .. s-2 | join
-int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, hipStream_t st,
-                      const hipEvent_t* ev) {
+int64_t enqueue_solve(fmmg_plan* p, const fmmg_ws& w, const double* rho, double* phi, double* g,
+                      hipStream_t st, const hipEvent_t* ev) {
     const HostPlan& hp = p->hp;
     const int s = hp.split;
     const bool fork = !ev && p->shape.overlap && s > 0;
     hipStream_t side = fork ? p->side_stream : st;
-    Ctx a = make_ctx(p, st);
+    Ctx a = make_ctx(p, w, st);
     a.rho = rho;
     Ctx c = a;
     c.st = side;
@@ -312,7 +328,7 @@ int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, h
     auto fused = [&](const Ctx& x, int br) {
         const int n = hp.lpt_begin[br + 1] - hp.lpt_begin[br];
         const int grid = br == 0 ? p->shape.blocks_per_cu * p->n_cu : p->n_cu;
-        launch_persist(x, p->d_items_lpt + hp.lpt_begin[br], n, grid, p->d_counter + 2 * br);
+        launch_persist(x, p->d_items_lpt + hp.lpt_begin[br], n, grid, w.counter + 2 * br);
         cnt(n);
     };
     auto items = [&](const Ctx& x, int br) {
@@ -320,13 +336,27 @@ int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, h
         else
             for (int k : kinds) one_class(x, br, k);
     };
+    // The solve's last launch (the leaf children of the deepest parents, or
+    // the output of a forest of parentless leaves) also hands the density
+    // flag to the host; every path below ends with it on the caller's stream.
+    auto last = [&](const Ctx& x) {
+        Ctx y = x;
+        y.flag_out = 1;
+        return y;
+    };
     auto l2l = [&](const Ctx& x, int l, int kind) {  // kind 1: refined children, 0: leaf children
         const int b = hp.l2l_begin[size_t(2 * l + (1 - kind))], e = hp.l2l_begin[size_t(2 * l + (2 - kind))];
         const int mode = l > 0 ? PARENT_TOTAL : (hp.top_full ? PARENT_TOP_PARTS : PARENT_OWN_PARTS);
-        launch_l2l(x, p->d_l2l_tasks + b, e - b, mode, phi, g);
+        const bool final_launch = kind == 0 && l == hp.max_level - 1;
+        launch_l2l(final_launch ? last(x) : x, p->d_l2l_tasks + b, e - b, mode, phi, g);
         cnt(e - b);
     };
     const int n_tl = int(hp.top_leaf.size());
+    // parentless leaves' output: the last launch when there is no level 1
+    auto leaf_out = [&](const Ctx& x) {
+        launch_leaf_out(hp.max_level == 0 ? last(x) : x, p->d_top_leaf, n_tl, phi, g);
+        cnt(n_tl);
+    };
     if (!p->pool.empty()) {
         // the execution model of Sec. 5.1: many small launches, one per target
         // sub-grid and class, spread over a pool of streams; the passes stay
@@ -349,8 +379,7 @@ int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, h
             (void)hipEventRecord(p->pool_join[q], p->pool[q]);
             (void)hipStreamWaitEvent(st, p->pool_join[q], 0);
         }
-        launch_leaf_out(a, p->d_top_leaf, n_tl, phi, g);
-        cnt(n_tl);
+        leaf_out(a);
         for (int l = 0; l < hp.max_level; ++l) {
             l2l(a, l, 1);
             l2l(a, l, 0);
@@ -376,8 +405,7 @@ int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, h
             fused(a, 1);
         }
         mark(FMMG_STAGE_DOWN);
-        launch_leaf_out(a, p->d_top_leaf, n_tl, phi, g);
-        cnt(n_tl);
+        leaf_out(a);
         for (int l = 0; l < hp.max_level; ++l) {
             l2l(a, l, 1);
             l2l(a, l, 0);
@@ -407,8 +435,7 @@ int64_t enqueue_solve(fmmg_plan* p, const double* rho, double* phi, double* g, h
         launch_p2m_top(c, p->d_top_leaf, n_tl);
         cnt(n_tl);
         items(c, 1);
-        launch_leaf_out(c, p->d_top_leaf, n_tl, phi, g);
-        cnt(n_tl);
+        leaf_out(c);  // (max_level >= 1 here: the split level is > 0)
         for (int l = 0; l < s; ++l) l2l(c, l, 1);
         for (int l = 0; l < s - 1; ++l) l2l(c, l, 0);
         (void)hipEventRecord(p->ev_join, side);
@@ -438,7 +465,8 @@ std::string signature(const fmmg_plan* p) {
     o << "fmmg1 trees=" << hp.n_trees << " sub=" << hp.subs.size() << " ref=" << hp.ref_sub.size()
       << " leaf=" << hp.leaf_sub.size() << " lev=" << hp.max_level << " k3=" << hp.n_slot3
       << " top=" << (p->opt.top_mode == FMMG_TOP_FULL ? "full" : "stencil")
-      << " prec=" << (p->opt.precision == FMMG_MIXED ? "mixed" : "fp64") << " cu=" << p->n_cu
+      << " prec=" << (p->opt.precision == FMMG_MIXED ? "mixed" : p->opt.precision == FMMG_MIXED_F32 ? "mixed_f32" : "fp64")
+      << " cu=" << p->n_cu
       << " split=" << hp.split_natural << " ovl=" << (p->opt.overlap ? 1 : 0);
     return o.str();
 }
@@ -549,7 +577,7 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
         if (p->opt.use_graph) {
             hipError_t e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                launches = enqueue_solve(p, rho, phi, g, p->capture_stream, nullptr);
+                launches = enqueue_solve(p, p->ws, rho, phi, g, p->capture_stream, nullptr);
                 hipError_t le = hipGetLastError();
                 e = hipStreamEndCapture(p->capture_stream, &cg);
                 if (e == hipSuccess) e = le;
@@ -563,7 +591,7 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
         }
         auto run = [&]() {
             if (ce) (void)hipGraphLaunch(ce, st);
-            else enqueue_solve(p, rho, phi, g, st, nullptr);
+            else enqueue_solve(p, p->ws, rho, phi, g, st, nullptr);
         };
         auto timed = [&](int n, double* ms_out) {
             (void)hipEventRecord(e0, st);
@@ -688,7 +716,8 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         else fmmg_default_options(&p->opt);
         const fmmg_options& o = p->opt;
         std::string bad;
-        if (o.precision != FMMG_FP64 && o.precision != FMMG_MIXED) bad = "bad precision";
+        if (o.precision != FMMG_FP64 && o.precision != FMMG_MIXED && o.precision != FMMG_MIXED_F32)
+            bad = "bad precision";
         else if (o.top_mode != FMMG_TOP_FULL && o.top_mode != FMMG_TOP_STENCIL_ONLY) bad = "bad top_mode";
         else if (o.timing && o.use_graph) bad = "timing needs eager launches (use_graph = 0)";
         else if (o.timing && o.autotune) bad = "timing and autotune cannot be combined";
@@ -710,7 +739,7 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
             return fail(FMMG_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
         }
         p->n_cu = prop.multiProcessorCount;
-        p->max_bpc = persist_blocks_per_cu(o.precision == FMMG_MIXED);
+        p->max_bpc = persist_blocks_per_cu(prec_form(o.precision));
         if (p->max_bpc < 1) p->max_bpc = 1;
         std::vector<TreeIn> tv = to_trees(trees, n_trees);
         std::string err;
@@ -737,18 +766,30 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
 #undef UP
         size_t nl = hp.leaf_sub.size(), nr = hp.ref_sub.size();
 #define AL(dst, n, what) if ((s = dev_alloc(&(dst), (n), what)) != FMMG_OK) { release(p); return s; }
-        AL(p->d_mass, nl * NCELL, "leaf masses");
-        AL(p->d_rec, nr * NREC * NCELL, "multipole records");
-        AL(p->d_Lp, size_t(p->max_groups) * nr * NLOC * NCELL, "refined own terms");
-        AL(p->d_Lr, nr * NLOC * NCELL, "refined expansions");
-        AL(p->d_Lf, nl * NLEAF * NCELL, "leaf terms");
-        AL(p->d_Lf3, size_t(hp.n_slot3) * NLEAF * NCELL, "leaf terms from refined sources");
-        AL(p->d_part, size_t(hp.n_top_parts) * NLOC * NCELL, "top partial sums");
+        AL(p->ws.mass, nl * NCELL, "leaf masses");
+        AL(p->ws.rec, nr * NREC * NCELL, "multipole records");
+        AL(p->ws.Lp, size_t(p->max_groups) * nr * NLOC * NCELL, "refined own terms");
+        AL(p->ws.Lr, nr * NLOC * NCELL, "refined expansions");
+        AL(p->ws.Lf, nl * NLEAF * NCELL, "leaf terms");
+        AL(p->ws.Lf3, size_t(hp.n_slot3) * NLEAF * NCELL, "leaf terms from refined sources");
+        AL(p->ws.part, size_t(hp.n_top_parts) * NLOC * NCELL, "top partial sums");
 #undef AL
-        e = hipMalloc(reinterpret_cast<void**>(&p->d_counter), 4 * sizeof(int));
+        e = hipMalloc(reinterpret_cast<void**>(&p->ws.counter), 4 * sizeof(int));
         if (e != hipSuccess) { release(p); return fail(FMMG_ENOMEM, "hipMalloc counter"); }
-        e = hipMemsetAsync(p->d_counter, 0, 4 * sizeof(int), st);
+        e = hipMemsetAsync(p->ws.counter, 0, 4 * sizeof(int), st);
         if (e != hipSuccess) { release(p); return hip_fail(e, "counter clear"); }
+        // the solves' density flag and the pinned host word it is handed to
+        e = hipMalloc(reinterpret_cast<void**>(&p->d_rho_bad), sizeof(unsigned long long));
+        if (e != hipSuccess) { release(p); return fail(FMMG_ENOMEM, "hipMalloc density flag"); }
+        launch_fill_u64(p->d_rho_bad, 1, ~0ull, st);
+        e = hipGetLastError();
+        if (e != hipSuccess) { release(p); return hip_fail(e, "density flag clear"); }
+        e = hipHostMalloc(reinterpret_cast<void**>(&p->h_rho_bad), sizeof(unsigned long long),
+                          hipHostMallocMapped);
+        if (e != hipSuccess) { release(p); return fail(FMMG_ENOMEM, "hipHostMalloc density flag"); }
+        __atomic_store_n(p->h_rho_bad, ~0ull, __ATOMIC_RELEASE);
+        e = hipHostGetDevicePointer(reinterpret_cast<void**>(&p->h_rho_bad_dev), p->h_rho_bad, 0);
+        if (e != hipSuccess) { release(p); return hip_fail(e, "density flag host mapping"); }
         e = hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming);
@@ -816,9 +857,14 @@ fmmg_status fmmg_get_launch_shape(const fmmg_plan* p, fmmg_launch_shape* out) {
     return FMMG_OK;
 }
 
-fmmg_status fmmg_solve(fmmg_plan* p, const double* rho, double* phi, double* g, void* hip_stream) {
-    if (!p) return fail(FMMG_EINVAL, "fmmg_solve: plan is NULL");
-    if (!p->hp.leaf_sub.empty() && (!rho || !phi || !g)) return fail(FMMG_EINVAL, "fmmg_solve: null buffer");
+namespace {
+
+// Checks shared by the solve entry points: buffers, device, and a bad
+// density that a completed solve on this plan has reported (taken, so that
+// it is reported once).
+fmmg_status solve_checks(fmmg_plan* p, const double* rho, double* phi, double* g, const char* who) {
+    if (!p) return fail(FMMG_EINVAL, std::string(who) + ": plan is NULL");
+    if (!p->hp.leaf_sub.empty() && (!rho || !phi || !g)) return fail(FMMG_EINVAL, std::string(who) + ": null buffer");
     {
         // the kernels read rho while writing phi and g: no two may share memory
         const uintptr_t n = uintptr_t(p->hp.leaf_sub.size()) * NCELL * sizeof(double);
@@ -826,11 +872,23 @@ fmmg_status fmmg_solve(fmmg_plan* p, const double* rho, double* phi, double* g, 
                         g0 = reinterpret_cast<uintptr_t>(g);
         auto overlap = [](uintptr_t a, uintptr_t na, uintptr_t b, uintptr_t nb) { return a < b + nb && b < a + na; };
         if (n > 0 && (overlap(r0, n, p0, n) || overlap(r0, n, g0, 3 * n) || overlap(p0, n, g0, 3 * n)))
-            return fail(FMMG_EINVAL, "fmmg_solve: rho, phi and g overlap");
+            return fail(FMMG_EINVAL, std::string(who) + ": rho, phi and g overlap");
     }
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-    if (dev != p->device) return fail(FMMG_EINVAL, "fmmg_solve: plan belongs to another device");
+    if (dev != p->device) return fail(FMMG_EINVAL, std::string(who) + ": plan belongs to another device");
+    const unsigned long long bad = __atomic_exchange_n(p->h_rho_bad, ~0ull, __ATOMIC_ACQ_REL);
+    if (bad != ~0ull)
+        return fail(FMMG_EINVAL, std::string(who) + ": a completed solve on this plan read a negative or non-finite "
+                                 "density at flat index " + std::to_string(bad) + "; nothing was enqueued");
+    return FMMG_OK;
+}
+
+}  // namespace
+
+fmmg_status fmmg_solve(fmmg_plan* p, const double* rho, double* phi, double* g, void* hip_stream) {
+    fmmg_status cs = solve_checks(p, rho, phi, g, "fmmg_solve");
+    if (cs != FMMG_OK) return cs;
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     try {
         if (p->opt.autotune && !p->tuned) {
@@ -857,7 +915,7 @@ fmmg_status fmmg_solve(fmmg_plan* p, const double* rho, double* phi, double* g, 
                 }
                 ev = p->events[p->n_timed++].data();
             }
-            p->launches = enqueue_solve(p, rho, phi, g, st, ev);
+            p->launches = enqueue_solve(p, p->ws, rho, phi, g, st, ev);
             HIP_TRY(hipGetLastError(), "kernel launch");
         } else {
             if (!p->graph_exec || p->g_rho != rho || p->g_phi != phi || p->g_g != g) {
@@ -865,7 +923,7 @@ fmmg_status fmmg_solve(fmmg_plan* p, const double* rho, double* phi, double* g, 
                 if (!p->capture_stream)
                     HIP_TRY(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
                 HIP_TRY(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
-                p->launches = enqueue_solve(p, rho, phi, g, p->capture_stream, nullptr);
+                p->launches = enqueue_solve(p, p->ws, rho, phi, g, p->capture_stream, nullptr);
                 hipError_t le = hipGetLastError();
                 hipError_t ce = hipStreamEndCapture(p->capture_stream, &p->graph);
                 if (le != hipSuccess) return hip_fail(le, "kernel launch during capture");
@@ -882,6 +940,16 @@ fmmg_status fmmg_solve(fmmg_plan* p, const double* rho, double* phi, double* g, 
     } catch (...) {
         return fail(FMMG_EINVAL, "unexpected host error in fmmg_solve");
     }
+}
+
+fmmg_status fmmg_density_status(fmmg_plan* p, int64_t* bad_index) {
+    if (!p || !bad_index) return fail(FMMG_EINVAL, "fmmg_density_status: null argument");
+    const unsigned long long bad = __atomic_exchange_n(p->h_rho_bad, ~0ull, __ATOMIC_ACQ_REL);
+    *bad_index = bad == ~0ull ? -1 : int64_t(bad);
+    if (bad != ~0ull)
+        return fail(FMMG_EINVAL, "a completed solve read a negative or non-finite density at flat index " +
+                                     std::to_string(bad));
+    return FMMG_OK;
 }
 
 fmmg_status fmmg_check_density(fmmg_plan* p, const double* rho, void* hip_stream) {

@@ -55,6 +55,13 @@ constexpr int MONO_R2 = 76;     // squared canonical offsets |d|^2 of the monopo
 enum { R_M = 0, R_DX = 1, R_DY = 2, R_DZ = 3, R_Q = 4, R_O = 9 };
 // Taylor component indices
 enum { T_L0 = 0, T_L1 = 1, T_L2 = 4, T_L3 = 9, T_S = 16 };
+// Arithmetic of the same-level pair terms.  PR_F64: FP64 throughout.
+// PR_MIX: sources staged in FP64; the Taylor coefficients' pair terms in FP32
+// with FP32 partial sums per source plane, flushed into FP64 sums; the
+// angular-momentum correction's pair terms evaluated and summed in FP64.
+// PR_F32: sources staged in FP32 and every pair term, the correction's
+// included, in FP32 with FP32 partial sums per source plane.
+enum { PR_F64 = 0, PR_MIX = 1, PR_F32 = 2 };
 
 struct SubDev {
     double h;          // cell edge

@@ -43,6 +43,30 @@ __device__ __forceinline__ int item_tid() {
     return t;
 }
 
+// Density check of the upward pass: a negative or non-finite density sets
+// cx.rho_bad to the smallest such flat index (rho[flat]); lanes_contiguous:
+// the wave's lanes read consecutive flat indices, so its lowest bad lane holds
+// its smallest one and a single atomic suffices.
+__device__ __forceinline__ void check_rho(const Ctx& cx, double v, unsigned long long flat,
+                                          bool lanes_contiguous) {
+    const bool bad = !(v >= 0.0) || !(v < __builtin_inf());
+    const unsigned long long mask = __ballot(bad);
+    if (!mask) return;
+    if (lanes_contiguous ? int(__lane_id()) == __ffsll((long long)mask) - 1 : bad)
+        atomicMin(cx.rho_bad, flat);
+}
+
+// The solve's last launch: block 0 hands a recorded bad density to the host
+// word (system scope) and re-arms the device flag for the next solve.
+__device__ __forceinline__ void rho_flag_out(const Ctx& cx) {
+    if (!cx.flag_out || blockIdx.x != 0 || threadIdx.x != 0) return;
+    const unsigned long long v = __hip_atomic_load(cx.rho_bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v != ~0ull) {
+        __hip_atomic_store(cx.rho_bad_host, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(cx.rho_bad, ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // internal cell index (x fastest) -> I/O index (z fastest)
 __device__ __forceinline__ int io_index(int q) {
     int x = q & 7, y = (q >> 3) & 7, z = q >> 6;
@@ -64,9 +88,11 @@ struct Acc {
         for (int i = 0; i < 7; ++i) l3[i] = 0;
     }
     template <typename Q>
-    __device__ __forceinline__ void add(const Acc<Q>& o, bool full) {
+    __device__ __forceinline__ void add(const Acc<Q>& o, bool full, bool with_s = true) {
         l0 += P(o.l0);
-        for (int i = 0; i < 3; ++i) l1[i] += P(o.l1[i]), s[i] += P(o.s[i]);
+        for (int i = 0; i < 3; ++i) l1[i] += P(o.l1[i]);
+        if (with_s)
+            for (int i = 0; i < 3; ++i) s[i] += P(o.s[i]);
         if (full) {
             for (int i = 0; i < 5; ++i) l2[i] += P(o.l2[i]);
             l2t += P(o.l2t);
@@ -179,6 +205,89 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
     }
 }
 
+// The same pair in the mixed form: the separation, the derivative scalars
+// and the correction term S (with the source and target octupoles) in FP64,
+// S added straight into the FP64 sums s; the Taylor coefficients L0..L3 in
+// FP32 from the rounded separation, scalars and moments, into the FP32
+// partial sums a.
+template <bool FULL>
+__device__ __forceinline__ void pair_terms_mix(double X, double Y, double Z, double mb, const double q[5],
+                                               const double o[7], const double oa[9], Acc<float>& a,
+                                               double (&s)[3]) {
+    const double XX = X * X, YY = Y * Y, ZZ = Z * Z;
+    const double r2 = XX + YY + ZZ;
+    const double d0 = rsqrt_full(r2);
+    const double ir2 = d0 * d0;
+    const double d1 = -d0 * ir2;
+    const double d2 = -3.0 * ir2 * d1;
+    const double d3 = -5.0 * ir2 * d2;
+    const double d4 = -7.0 * ir2 * d3;
+    const double XY = X * Y, XZ = X * Z, YZ = Y * Z;
+    const double XmZ = XX - ZZ, YmZ = YY - ZZ, XY2 = XY + XY, XZ2 = XZ + XZ, YZ2 = YZ + YZ;
+    double wb[3];
+    oct_rr(o, -o[0] - o[3], -o[1] - o[5], XmZ, YmZ, XY2, XZ2, YZ2, wb);
+    const double BRRR = fmaP(X, wb[0], fmaP(Y, wb[1], Z * wb[2]));  // o:RRR / 6
+    {
+        double Qx = wb[0], Qy = wb[1], Qz = wb[2];
+        if (FULL) {
+            double wa[3];
+            oct_rr(oa, oa[7], oa[8], XmZ, YmZ, XY2, XZ2, YZ2, wa);
+            Qx = fmaP(-mb, wa[0], Qx);
+            Qy = fmaP(-mb, wa[1], Qy);
+            Qz = fmaP(-mb, wa[2], Qz);
+        }
+        const double QRRR = fmaP(X, Qx, fmaP(Y, Qy, Z * Qz));
+        const double t4 = d4 * QRRR, t3 = 3.0 * d3;
+        s[0] = fmaP(t4, X, fmaP(t3, Qx, s[0]));
+        s[1] = fmaP(t4, Y, fmaP(t3, Qy, s[1]));
+        s[2] = fmaP(t4, Z, fmaP(t3, Qz, s[2]));
+    }
+    const float x = float(X), y = float(Y), z = float(Z), m = float(mb);
+    const float f0 = float(d0), f1 = float(d1), f2 = float(d2), f3 = float(d3);
+    const float q0 = float(q[0]), q1 = float(q[1]), q2 = float(q[2]), q3 = float(q[3]), q4 = float(q[4]);
+    const float qzz = -q0 - q1;
+    const float ux = fmaP(q0, x, fmaP(q2, y, q3 * z));
+    const float uy = fmaP(q2, x, fmaP(q1, y, q4 * z));
+    const float uz = fmaP(q3, x, fmaP(q4, y, qzz * z));
+    const float hRqR = 0.5f * fmaP(x, ux, fmaP(y, uy, z * uz));
+    a.l0 = fmaP(m, f0, fmaP(f2, hRqR, fmaP(-f3, float(BRRR), a.l0)));
+    const float c1 = fmaP(m, f1, f3 * hRqR);
+    a.l1[0] = fmaP(c1, x, fmaP(f2, ux, a.l1[0]));
+    a.l1[1] = fmaP(c1, y, fmaP(f2, uy, a.l1[1]));
+    a.l1[2] = fmaP(c1, z, fmaP(f2, uz, a.l1[2]));
+    if (FULL) {
+        const float md2 = m * f2, md3 = m * f3;
+        const float xx = x * x, yy = y * y;
+        a.l2t = fmaP(m, f1, a.l2t);
+        a.l2[0] = fmaP(md2, xx, a.l2[0]);
+        a.l2[1] = fmaP(md2, yy, a.l2[1]);
+        a.l2[2] = fmaP(md2, x * y, a.l2[2]);
+        a.l2[3] = fmaP(md2, x * z, a.l2[3]);
+        a.l2[4] = fmaP(md2, y * z, a.l2[4]);
+        const float m3 = 3.0f * md2;
+        const float bx = fmaP(md3, xx, md2), cy = fmaP(md3, yy, md2);
+        a.l3[0] = fmaP(x, fmaP(md3, xx, m3), a.l3[0]);
+        a.l3[1] = fmaP(y, bx, a.l3[1]);
+        a.l3[2] = fmaP(z, bx, a.l3[2]);
+        a.l3[3] = fmaP(x, cy, a.l3[3]);
+        a.l3[4] = fmaP(md3 * x * y, z, a.l3[4]);
+        a.l3[5] = fmaP(y, fmaP(md3, yy, m3), a.l3[5]);
+        a.l3[6] = fmaP(z, cy, a.l3[6]);
+    }
+}
+
+// One pair in the arithmetic of precision form PR (sources staged as P =
+// double for PR_F64 and PR_MIX, float for PR_F32): FP64 terms go to acc, the
+// FP32 forms' Taylor terms to the partial sums part (PR_F64: part is acc).
+template <bool FULL, int PR, typename P, typename PA>
+__device__ __forceinline__ void pair_any(P X, P Y, P Z, const P* src, const P oa[9], Acc<double>& acc,
+                                         Acc<PA>& part) {
+    if constexpr (PR == PR_MIX)
+        pair_terms_mix<FULL>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], oa, part, acc.s);
+    else
+        pair_terms<FULL, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], oa, true, part);
+}
+
 // ---------------------------------------------------------------------------
 // step 1: leaf masses and the upward pass
 // ---------------------------------------------------------------------------
@@ -188,7 +297,10 @@ __global__ __launch_bounds__(512) void k_p2m_top(Ctx cx, const int32_t* __restri
     const SubDev& S = cx.subs[list[blockIdx.x]];
     const int q = threadIdx.x;
     const double h = S.h;
-    cx.mass[size_t(S.idx) * NCELL + q] = cx.rho[size_t(S.idx) * NCELL + io_index(q)] * (h * h * h);
+    const size_t io = size_t(S.idx) * NCELL + io_index(q);
+    const double v = cx.rho[io];
+    check_rho(cx, v, io, false);
+    cx.mass[size_t(S.idx) * NCELL + q] = v * (h * h * h);
 }
 
 // One octant of a refined sub-grid's cells from the 512 cells of one child
@@ -210,7 +322,9 @@ __global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__
     const SubDev& Cs = cx.subs[Ps.child[e]];
     const int q = threadIdx.x;
     if (Cs.kind == 0) {
-        rin[q + (q >> 3)] = cx.rho[size_t(Cs.idx) * NCELL + q];  // coalesced
+        const double v = cx.rho[size_t(Cs.idx) * NCELL + q];  // coalesced
+        check_rho(cx, v, size_t(Cs.idx) * NCELL + q, true);
+        rin[q + (q >> 3)] = v;
         __syncthreads();
     }
     const int x = q & 7, y = (q >> 3) & 7, z = q >> 6;
@@ -351,6 +465,10 @@ struct Smem {
     static constexpr int NBR_OFF = ((A > B ? A : B) + 15) & ~15;  // the target's 27 neighbour codes
     static constexpr int BYTES = NBR_OFF + 128;
 };
+// LDS layout of a block of precision form PR (the mixed form stages its
+// multipole sources in FP64)
+template <int PR>
+using SmemPR = Smem<typename std::conditional<PR == PR_F32, float, double>::type>;
 
 // Swap of the y and z axes in a record (mass, centre-of-mass offset,
 // trace-free quadrupole xx yy xy xz yz, trace-free octupole xxx xxy xxz xyy
@@ -392,15 +510,17 @@ __device__ __forceinline__ void swap_yz_o(T* o) {
 // in the plane either way (coalesced staging), and the stencil is symmetric
 // under the swap, so one set of tables serves both: records are swapped into
 // the frame when staged and the results swapped back before they are stored.
-template <bool LEAF_T, bool MIXED, int SWEEP>
+template <bool LEAF_T, int PR, int SWEEP>
 __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int group, unsigned char* smem) {
-    using P = typename std::conditional<MIXED, float, double>::type;
+    // P: staged source data; PA: the pair terms' partial sums
+    using P = typename std::conditional<PR == PR_F32, float, double>::type;
+    using PA = typename std::conditional<PR == PR_F64, double, float>::type;
     // the window's records in 16-byte groups of V components: component k of
     // slot c is element k % V of group (k / V) * MP_SLOTS + c
     constexpr int V = 16 / int(sizeof(P));
-    using PV = typename std::conditional<MIXED, float4, double2>::type;
+    using PV = typename std::conditional<PR == PR_F32, float4, double2>::type;
     unsigned char* leafflag = smem + NREC * MP_SLOTS * sizeof(P);
-    int* nb = reinterpret_cast<int*>(smem + Smem<P>::NBR_OFF);
+    int* nb = reinterpret_cast<int*>(smem + SmemPR<PR>::NBR_OFF);
 
     const int t = item_tid(), lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index: uniform
@@ -528,11 +648,11 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
             }
         }
         __syncthreads();
-        // mixed form: FP32 partial sums per source plane, flushed into the FP64
+        // FP32 forms: partial sums per source plane, flushed into the FP64
         // accumulators after the plane; FP64 form: accumulate directly
-        Acc<P> part_store;
-        Acc<P>& part = MIXED ? part_store : *reinterpret_cast<Acc<P>*>(&acc);
-        if (MIXED) part.zero();
+        Acc<PA> part_store;
+        Acc<PA>& part = PR != PR_F64 ? part_store : *reinterpret_cast<Acc<PA>*>(&acc);
+        if (PR != PR_F64) part.zero();
         const int32_t* tab = LEAF_T ? c_tab.mp_entry_fp : c_tab.mp_entry;
         auto reaches = [&](int e) { return !LEAF_T || ((tab[e] >> 16) & cols) != 0; };
         auto one = [&](int e) {
@@ -550,7 +670,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
             const P X = tu - src[R_DX];
             const P Y = tv - src[R_DY];
             const P Z = tw - src[R_DZ];
-            pair_terms<!LEAF_T, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], oa, use_corr, part);
+            pair_any<!LEAF_T, PR>(X, Y, Z, src, oa, acc, part);
         };
         const int fb = c_tab.mp_far_begin[gi], fe = fb + c_tab.mp_far_count[gi];
         // two independent pairs per iteration: two dependency chains per wave
@@ -574,7 +694,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
                 if (reaches(e)) one(e);
             }
         }
-        if (MIXED) acc.add(part, !LEAF_T);
+        if (PR != PR_F64) acc.add(part, !LEAF_T, PR == PR_F32);
     }
 
     // combine the 4 waves' partial sums in a fixed order
@@ -713,11 +833,12 @@ __device__ __forceinline__ void mono_all(const P* box, int cstart, int cstep, in
 }
 
 
-template <bool MIXED>
+// NB: byte offset of the neighbour codes in the block's LDS layout
+template <int PR, int NB>
 __device__ __forceinline__ void mono_item(const Ctx& cx, int sid, unsigned char* smem) {
-    using P = typename std::conditional<MIXED, float, double>::type;
+    using P = typename std::conditional<PR == PR_F64, double, float>::type;
     P* box = reinterpret_cast<P*>(smem);
-    int* nb = reinterpret_cast<int*>(smem + Smem<P>::NBR_OFF);
+    int* nb = reinterpret_cast<int*>(smem + NB);
     const int t = item_tid();
     const SubDev& T = cx.subs[sid];
     if (t < 27) nb[t] = T.nbr[t];
@@ -824,9 +945,10 @@ __device__ __forceinline__ void mono_item(const Ctx& cx, int sid, unsigned char*
 // staged through LDS 256 at a time, the 4 waves take every fourth source
 // (one LDS address per wave: broadcast reads) and their sums are added in a
 // fixed order.
-template <bool MIXED>
+template <int PR>
 __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsigned char* smem) {
-    using P = typename std::conditional<MIXED, float, double>::type;
+    using P = typename std::conditional<PR == PR_F32, float, double>::type;
+    using PA = typename std::conditional<PR == PR_F64, double, float>::type;
     const SubDev& T = cx.subs[it.target];
     const int t = item_tid(), lane = t & 63, x = lane & 7, y = lane >> 3;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
@@ -849,8 +971,7 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
     } else {
         mA = cx.mass[size_t(T.idx) * NCELL + q];
     }
-    const bool use_corr = cx.corr != 0;
-    Acc<P> acc;
+    Acc<double> acc;
     acc.zero();
     // sources staged through LDS, 256 per tile: 16 record values (octupole
     // divided by 6, as the pair terms take it) and the
@@ -878,6 +999,10 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
             }
         }
         __syncthreads();
+        // FP32 forms: partial sums per tile, flushed into the FP64 sums
+        Acc<PA> part_store;
+        Acc<PA>& part = PR != PR_F64 ? part_store : *reinterpret_cast<Acc<PA>*>(&acc);
+        if (PR != PR_F64) part.zero();
         const int nt = min(256, it.src_end - tb);
         for (int s = w; s < nt; s += 4) {
             const int dx = sc[0 * 256 + s] - cax;
@@ -892,11 +1017,10 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
             const P X = P(-h * dx) + (P(dAx) - src[R_DX]);
             const P Y = P(-h * dy) + (P(dAy) - src[R_DY]);
             const P Z = P(-h * dz) + (P(dAz) - src[R_DZ]);
-            if (tref)
-                pair_terms<true, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], oa, use_corr, acc);
-            else
-                pair_terms<false, P>(X, Y, Z, src[R_M], &src[R_Q], &src[R_O], oa, use_corr, acc);
+            if (tref) pair_any<true, PR>(X, Y, Z, src, oa, acc, part);
+            else pair_any<false, PR>(X, Y, Z, src, oa, acc, part);
         }
+        if (PR != PR_F64) acc.add(part, tref, PR == PR_F32);
     }
     __syncthreads();
     double* red = reinterpret_cast<double*>(smem);
@@ -918,45 +1042,45 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
     }
 }
 
-template <bool MIXED>
+template <int PR>
 __device__ __forceinline__ void run_item(const Ctx& cx, const Item& it, unsigned char* smem) {
     switch (it.kind) {
         case IT_MP_REF:
-            if (it.b >> 3) mp_item<false, MIXED, 1>(cx, it.sub, it.a, it.b & 7, smem);
-            else mp_item<false, MIXED, 0>(cx, it.sub, it.a, it.b & 7, smem);
+            if (it.b >> 3) mp_item<false, PR, 1>(cx, it.sub, it.a, it.b & 7, smem);
+            else mp_item<false, PR, 0>(cx, it.sub, it.a, it.b & 7, smem);
             break;
         case IT_MP_LEAF:
-            if (it.b >> 3) mp_item<true, MIXED, 1>(cx, it.sub, it.a, 0, smem);
-            else mp_item<true, MIXED, 0>(cx, it.sub, it.a, 0, smem);
+            if (it.b >> 3) mp_item<true, PR, 1>(cx, it.sub, it.a, 0, smem);
+            else mp_item<true, PR, 0>(cx, it.sub, it.a, 0, smem);
             break;
-        case IT_MONO: mono_item<MIXED>(cx, it.sub, smem); break;
-        default: top_item<MIXED>(cx, cx.top_items[it.sub], smem); break;
+        case IT_MONO: mono_item<PR, SmemPR<PR>::NBR_OFF>(cx, it.sub, smem); break;
+        default: top_item<PR>(cx, cx.top_items[it.sub], smem); break;
     }
 }
 
 // One launch per class: one block per item of that class.
-template <int KIND, bool MIXED>
+template <int KIND, int PR>
 __global__ __launch_bounds__(256) void k_class(Ctx cx, const Item* __restrict__ items) {
-    using P = typename std::conditional<MIXED, float, double>::type;
-    __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P>::BYTES];
+    // the monopole class of the mixed form uses FP32 masses, as PR_F32 does
+    using L = SmemPR<(KIND == IT_MONO && PR == PR_MIX) ? PR_F32 : PR>;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[L::BYTES];
     const Item it = items[blockIdx.x];
     if (KIND == IT_MP_REF || KIND == IT_MP_LEAF) {
-        if (it.b >> 3) mp_item<KIND == IT_MP_LEAF, MIXED, 1>(cx, it.sub, it.a, it.b & 7, smem);
-        else mp_item<KIND == IT_MP_LEAF, MIXED, 0>(cx, it.sub, it.a, it.b & 7, smem);
+        if (it.b >> 3) mp_item<KIND == IT_MP_LEAF, PR, 1>(cx, it.sub, it.a, it.b & 7, smem);
+        else mp_item<KIND == IT_MP_LEAF, PR, 0>(cx, it.sub, it.a, it.b & 7, smem);
     }
-    else if (KIND == IT_MONO) mono_item<MIXED>(cx, it.sub, smem);
-    else top_item<MIXED>(cx, cx.top_items[it.sub], smem);
+    else if (KIND == IT_MONO) mono_item<PR, L::NBR_OFF>(cx, it.sub, smem);
+    else top_item<PR>(cx, cx.top_items[it.sub], smem);
 }
 
 // Persistent launch over a list of items: each block takes the next item of
 // the (largest-first) list from ctr[0] until the list is exhausted, so every
 // block exits once all items are taken.  The last block to exit re-arms
 // ctr[0] and ctr[1] (both zero before the first launch) for the next launch.
-template <bool MIXED>
+template <int PR>
 __global__ __launch_bounds__(256, 3) void k_persist(Ctx cx, const Item* __restrict__ items, int n,
                                                     int* __restrict__ ctr) {
-    using P = typename std::conditional<MIXED, float, double>::type;
-    __shared__ __attribute__((aligned(16))) unsigned char smem[Smem<P>::BYTES];
+    __shared__ __attribute__((aligned(16))) unsigned char smem[SmemPR<PR>::BYTES];
     __shared__ int s_it;
     for (;;) {
         if (threadIdx.x == 0) s_it = atomicAdd(&ctr[0], 1);
@@ -964,7 +1088,7 @@ __global__ __launch_bounds__(256, 3) void k_persist(Ctx cx, const Item* __restri
         const int it = s_it;
         __syncthreads();
         if (it >= n) break;
-        run_item<MIXED>(cx, items[it], smem);
+        run_item<PR>(cx, items[it], smem);
     }
     if (threadIdx.x == 0 && atomicAdd(&ctr[1], 1) == int(gridDim.x) - 1) {
         atomicExch(&ctr[0], 0);
@@ -1004,6 +1128,7 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
                                              double* __restrict__ phi, double* __restrict__ gout) {
     __shared__ double obuf[4][NCELL];
     __shared__ double par[NLOC + 3][64];  // the octant's 64 parent cells: L (19), COM offset (3)
+    rho_flag_out(cx);
     const int task = tasks[blockIdx.x];
     const SubDev& Ps = cx.subs[task >> 3];
     const int e = task & 7;
@@ -1133,6 +1258,7 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
 __global__ __launch_bounds__(512) void k_leaf_out(Ctx cx, const int32_t* __restrict__ list,
                                                   double* __restrict__ phi, double* __restrict__ gout) {
     __shared__ double obuf[4][NCELL];
+    rho_flag_out(cx);
     const SubDev& S = cx.subs[list[blockIdx.x]];
     const int q = threadIdx.x;
     const int io = io_index(q);
@@ -1163,7 +1289,11 @@ __global__ void k_check_density(const double* __restrict__ rho, int64_t n,
     }
 }
 
-__global__ void k_fill_u64(unsigned long long* p, unsigned long long v) { *p = v; }
+__global__ void k_fill_u64(unsigned long long* p, int n, unsigned long long v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 
 // ---------------------------------------------------------------------------
 // launchers (host)
@@ -1183,8 +1313,9 @@ void launch_m2m(const Ctx& a, const int32_t* list, int n) {
 
 template <int K>
 static void launch_class_k(const Ctx& a, const Item* items, int n) {
-    if (a.mixed) hipLaunchKernelGGL((k_class<K, true>), dim3(n), dim3(256), 0, a.st, a, items);
-    else hipLaunchKernelGGL((k_class<K, false>), dim3(n), dim3(256), 0, a.st, a, items);
+    if (a.prec == PR_MIX) hipLaunchKernelGGL((k_class<K, PR_MIX>), dim3(n), dim3(256), 0, a.st, a, items);
+    else if (a.prec == PR_F32) hipLaunchKernelGGL((k_class<K, PR_F32>), dim3(n), dim3(256), 0, a.st, a, items);
+    else hipLaunchKernelGGL((k_class<K, PR_F64>), dim3(n), dim3(256), 0, a.st, a, items);
 }
 
 void launch_class(const Ctx& a, int kind, const Item* items, int n) {
@@ -1200,14 +1331,18 @@ void launch_class(const Ctx& a, int kind, const Item* items, int n) {
 void launch_persist(const Ctx& a, const Item* items, int n, int grid, int* ctr) {
     if (n <= 0 || grid <= 0) return;
     if (grid > n) grid = n;
-    if (a.mixed) hipLaunchKernelGGL((k_persist<true>), dim3(grid), dim3(256), 0, a.st, a, items, n, ctr);
-    else hipLaunchKernelGGL((k_persist<false>), dim3(grid), dim3(256), 0, a.st, a, items, n, ctr);
+    if (a.prec == PR_MIX)
+        hipLaunchKernelGGL((k_persist<PR_MIX>), dim3(grid), dim3(256), 0, a.st, a, items, n, ctr);
+    else if (a.prec == PR_F32)
+        hipLaunchKernelGGL((k_persist<PR_F32>), dim3(grid), dim3(256), 0, a.st, a, items, n, ctr);
+    else hipLaunchKernelGGL((k_persist<PR_F64>), dim3(grid), dim3(256), 0, a.st, a, items, n, ctr);
 }
 
-int persist_blocks_per_cu(int mixed) {
+int persist_blocks_per_cu(int prec) {
     int nb = 0;
-    hipError_t e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<true>, 256, 0)
-                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<false>, 256, 0);
+    hipError_t e = prec == PR_MIX   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<PR_MIX>, 256, 0)
+                   : prec == PR_F32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<PR_F32>, 256, 0)
+                                    : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persist<PR_F64>, 256, 0);
     return e == hipSuccess ? nb : 0;
 }
 
@@ -1220,8 +1355,12 @@ void launch_leaf_out(const Ctx& a, const int32_t* list, int n, double* phi, doub
 }
 
 void launch_check_density(const double* rho, int64_t n, unsigned long long* bad, hipStream_t st) {
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, st, bad, ~0ull);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, bad, 1, ~0ull);
     if (n > 0) hipLaunchKernelGGL(k_check_density, dim3(1024), dim3(256), 0, st, rho, n, bad);
+}
+
+void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_fill_u64, dim3((n + 255) / 256), dim3(256), 0, st, p, n, v);
 }
 
 }  // namespace fmmg

@@ -23,10 +23,15 @@ struct Ctx {
     const int32_t* top_src;
     const TopReduce* top_reds;  // partial slots of each top-level target
     const double* rho;          // caller's densities (I/O cell order)
+    unsigned long long* rho_bad;       // smallest flat index of a negative or non-finite
+                                       // density read by the upward pass, ~0 if none
+    unsigned long long* rho_bad_host;  // device address of the host word it is copied to
+    int flag_out;                      // 1 in the solve's last launch: block 0 copies a
+                                       // set rho_bad to the host word and clears it
     int64_t part_stride;    // elements between plane groups of Lp
     double G;
     int corr;
-    int mixed;
+    int prec;               // PR_F64, PR_MIX or PR_F32
     int ngroups;
     hipStream_t st;
 };
@@ -41,9 +46,10 @@ void launch_m2m(const Ctx& a, const int32_t* list, int n);
 void launch_class(const Ctx& a, int kind, const Item* items, int n);
 // ctr: two ints, zero before the first launch and re-armed by each launch
 void launch_persist(const Ctx& a, const Item* items, int n, int grid, int* ctr);
-int persist_blocks_per_cu(int mixed);
+int persist_blocks_per_cu(int prec);
 void launch_l2l(const Ctx& a, const int32_t* tasks, int n, int parent_mode, double* phi, double* g);
 void launch_leaf_out(const Ctx& a, const int32_t* list, int n, double* phi, double* g);
 void launch_check_density(const double* rho, int64_t n, unsigned long long* bad, hipStream_t st);
+void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st);
 
 }  // namespace fmmg
