@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(fm.EXPORTED)
     for n in names:
         assert hasattr(L, n), n
-    assert fm.fmmg_version() == 1
+    assert fm.fmmg_version() == 2
 
 
 def test_default_options():
@@ -40,6 +40,7 @@ def test_default_options():
     {"launch_streams": 129}, {"launch_streams": -1}, {"launch_streams": 4, "timing": 1},
     {"launch_streams": 4, "autotune": 1}, {"overlap": 3}, {"plane_groups": 6},
     {"timing": 1, "use_graph": 1}, {"timing": 1, "autotune": 1}, {"blocks_per_cu": -1},
+    {"precision": 3},
 ])
 def test_bad_options_are_rejected_before_any_device_call(bad):
     # option checks come first, so they answer the same with or without a GPU
