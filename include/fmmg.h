@@ -193,8 +193,7 @@ typedef struct {
     int64_t n_refined;
     int32_t max_level;
     int32_t n_trees;
-    int32_t sweep_y_targets;  /* multipole targets (refined, or leaves with refined
-                                 neighbours) whose plane items run along y          */
+    int32_t sweep_y_targets;  /* refined targets whose plane items run along y     */
 } fmmg_stats;
 
 /* Fills *opt with the defaults listed above (interface convention; no

@@ -86,22 +86,29 @@ constexpr int MAX_GROUPS = 5;   // source-plane groups of a refined-target item 
 struct Item {
     int32_t kind;
     int32_t sub;   // target sub-grid (IT_TOP: index into the top items)
-    int32_t a;     // IT_MP_*: target plane along the sweep axis
-    int32_t b;     // IT_MP_REF: plane group in bits 0..2; IT_MP_*: sweep in bit 3
+    int32_t a;     // IT_MP_REF: target plane along the sweep axis
+    int32_t b;     // IT_MP_REF: plane group in bits 0..2, sweep in bit 3
                    // (0: planes along z, lanes on (x, y); 1: along y, lanes on (x, z))
 };
+
+// Leaf targets with refined sources (class 4) are grouped by target parent
+// cell: the rule selects a leaf target's partners by the offset D of the two
+// parent cells alone (|D|^2 <= 8), so the 8 children of one parent cell share
+// one partner set, the 8 children of each partner parent.  Per neighbour
+// slot, the source parents within reach form a slab of 2 or 4 parent cells
+// per axis (2 on the side facing the target, 4 along a shared face), at most
+// C4_SLAB of them.
+constexpr int C4_SLAB = 32;        // source parents of a face neighbour's slab (2 x 4 x 4)
+constexpr int C4_MAX_TASKS = 3584; // (target parent, source parent) pairs over the 26 slots: 3560
+constexpr int C4_MAX_GROUPS = 448; // (slot, target parent) groups: 6 x 32 + 12 x 16 + 8 x 4
 
 // Canonical stencil tables (parity (0,0,0); other parities are mirror images:
 // a cell of parity p uses offset (sx*dx, sy*dy, sz*dz) with s = 1 - 2p).
 struct StencilTables {
-    // multipole kernels: entries (dx + 8) | (dy + 8) << 8 | footprint << 16,
-    // the footprint being the 9-bit set of in-plane neighbour columns the 64
-    // lanes of a plane reach; grouped by canonical dz (DZ0..DZ0+NDZ-1),
-    // far entries first, then near ones.  mp_entry_fp holds the same groups
-    // with each sorted by footprint (the leaf-target kernel skips entries
-    // whose footprint misses the refined neighbours, in runs)
+    // refined-target multipole kernel: entries (dx + 8) | (dy + 8) << 8,
+    // grouped by canonical dz (DZ0..DZ0+NDZ-1), far entries first, then near
+    // ones
     int32_t mp_entry[743];
-    int32_t mp_entry_fp[743];
     int32_t mp_far_begin[NDZ], mp_far_count[NDZ];
     int32_t mp_near_begin[NDZ], mp_near_count[NDZ];
     // monopole kernel: the 100 columns (dx, dy) of the canonical stencil fall
@@ -114,6 +121,18 @@ struct StencilTables {
     int32_t mono_class_begin[4];
     double mono_r[MONO_R2][2];
     float mono_rf[MONO_R2][2];
+    // class 4 by target parent cell.  Neighbour slot o = (ox+1)*9 + (oy+1)*3 +
+    // (oz+1): c4_slab[o] = nx | ny << 4 | nz << 8 | x0 << 12 | y0 << 14 |
+    // z0 << 16, the slab's extent (2 or 4) and first parent coordinate (0 or
+    // 2) per axis in the neighbour's 4^3 parent cells, slab parent index
+    // (ix * ny + iy) * nz + iz.  Groups [c4_grp_begin[o], c4_grp_begin[o+1])
+    // (largest first): c4_grp[g] = pt | first << 6 | count << 18, the target
+    // parent pt = (px * 4 + py) * 4 + pz of the leaf and its partner parents
+    // c4_task[first .. first + count) as slab parent indices.
+    int32_t c4_slab[27];
+    int32_t c4_grp_begin[28];
+    int32_t c4_grp[C4_MAX_GROUPS];
+    int16_t c4_task[C4_MAX_TASKS];
 };
 
 // Top-level (all pairs) tile: 64 target cells (plane zt of sub-grid target)

@@ -452,15 +452,18 @@ __global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__
 // ---------------------------------------------------------------------------
 // LDS of one item block: the largest of the multipole plane window (16
 // record components x 18 x 18 cells + leaf flags), the monopole mass box (18
-// planes x 18 rows of 20 cells), the 4-wave reduction buffer (doubles) and
-// the top-level source tile, followed by the target's 27 neighbour codes.
+// planes x 18 rows of 20 cells), the class-4 source slab and totals, the
+// 4-wave reduction buffer (doubles) and the top-level source tile, followed by
+// the target's 27 neighbour codes.
 template <typename P>
 struct Smem {
     static constexpr int PLANE = NREC * MP_SLOTS * int(sizeof(P)) + MP_SLOTS;
     static constexpr int BOX = PW * PSLOTS * int(sizeof(P));
     static constexpr int RED = 4 * NLOC * 64 * 8;
     static constexpr int TOP = NREC * 256 * int(sizeof(P)) + 4 * 256 * 4;  // top-level source tile
-    static constexpr int A = PLANE > BOX ? PLANE : BOX;
+    static constexpr int C4 = NREC * C4_SLAB * 8 * int(sizeof(P)) + NLEAF * NCELL * 8;  // class-4 slab + totals
+    static constexpr int A0 = PLANE > BOX ? PLANE : BOX;
+    static constexpr int A = A0 > C4 ? A0 : C4;
     static constexpr int B = RED > TOP ? RED : TOP;
     static constexpr int NBR_OFF = ((A > B ? A : B) + 15) & ~15;  // the target's 27 neighbour codes
     static constexpr int BYTES = NBR_OFF + 128;
@@ -497,12 +500,11 @@ __device__ __forceinline__ void swap_yz_o(T* o) {
     o[6] = -o1 - o5;
 }
 
-// Multipole item: 64 target cells (one plane of sub-grid sid) against the
-// source planes of one group of canonical plane offsets.  All 4 waves hold
-// the same 64 targets and split each plane's entry list.  Refined targets:
-// every existing source over the far entries, leaf sources also over the
-// near entries (classes 1 + 2).  Leaf targets: refined sources over all
-// entries (class 4).
+// Refined-target item: 64 target cells (one plane of refined sub-grid sid)
+// against the source planes of one group of canonical plane offsets.  All 4
+// waves hold the same 64 targets and split each plane's entry list: every
+// existing source over the far entries, leaf sources also over the near
+// entries (classes 1 + 2).
 // The sweep frame (u, v, w) puts the target plane at w = zt and the lanes on
 // (u, v): sweep 0 is (x, y, z); sweep 1 is (x, z, y), chosen by the planner
 // for targets whose sources lie mostly beside them in y, so that whole source
@@ -510,7 +512,7 @@ __device__ __forceinline__ void swap_yz_o(T* o) {
 // in the plane either way (coalesced staging), and the stencil is symmetric
 // under the swap, so one set of tables serves both: records are swapped into
 // the frame when staged and the results swapped back before they are stored.
-template <bool LEAF_T, int PR, int SWEEP>
+template <int PR, int SWEEP>
 __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int group, unsigned char* smem) {
     // P: staged source data; PA: the pair terms' partial sums
     using P = typename std::conditional<PR == PR_F32, float, double>::type;
@@ -541,29 +543,24 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     const int sx = 1 - 2 * (x & 1), sy = 1 - 2 * (y & 1), sz = 1 - 2 * (zt & 1);
 
     // target data
-    double mA, dAx = 0, dAy = 0, dAz = 0;
-    P oa[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (!LEAF_T) {
-        const double* r = cx.rec + size_t(tidx) * NREC * NCELL;
-        mA = r[R_M * NCELL + q];
-        dAx = r[R_DX * NCELL + q];
-        dAy = r[R_DY * NCELL + q];
-        dAz = r[R_DZ * NCELL + q];
+    P oa[9];
+    const double* rt = cx.rec + size_t(tidx) * NREC * NCELL;
+    const double mA = rt[R_M * NCELL + q];
+    double dAx = rt[R_DX * NCELL + q], dAy = rt[R_DY * NCELL + q], dAz = rt[R_DZ * NCELL + q];
+    {
         const double os = mA > 0 ? 1.0 / (6.0 * mA) : 0.0;
 #pragma unroll
-        for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q] * os);
+        for (int k = 0; k < 7; ++k) oa[k] = P(rt[(R_O + k) * NCELL + q] * os);
         if (SWEEP) {
             swap_yz(dAy, dAz);
             swap_yz_o(oa);
         }
         oa[7] = -oa[0] - oa[3];
         oa[8] = -oa[1] - oa[5];
-    } else {
-        mA = cx.mass[size_t(tidx) * NCELL + q];
     }
     const bool use_corr = cx.corr != 0;
-    const bool do_near = LEAF_T ? true : ((T.flags & 1) != 0);
-    const int ng = LEAF_T ? 1 : cx.ngroups;
+    const bool do_near = (T.flags & 1) != 0;
+    const int ng = cx.ngroups;
     const int i0 = group * NDZ / ng, i1 = (group + 1) * NDZ / ng;
 
     Acc<double> acc;
@@ -582,19 +579,12 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         const int dz = sz * (DZ0 + gi);
         const int zs = zt + dz;
         const int oz = zs < 0 ? -1 : (zs >= NS ? 1 : 0);
-        // in-plane neighbour columns (bit (o_u + 1) * 3 + o_v + 1) holding
-        // usable sources: refined ones for leaf targets, any for refined
-        // targets.  A plane without any is skipped (uniform over the block);
-        // leaf targets also skip the entries whose footprint (the columns
-        // their 64 lanes reach) misses them.  (For refined targets the entry
-        // test costs more than it saves.)
-        int cols = 0;
+        // a source plane whose nine neighbour sub-grids at its offset are all
+        // absent is skipped (uniform over the block)
+        bool any = false;
 #pragma unroll
-        for (int o = 0; o < 9; ++o) {
-            const int code = T.nbr[(o / 3) * 9 + (o % 3) * VN + (oz + 1) * WN];
-            cols |= (LEAF_T ? (code >= 0 && (code & 1)) : (code >= 0)) << o;
-        }
-        if (!cols) continue;
+        for (int o = 0; o < 9; ++o) any |= T.nbr[(o / 3) * 9 + (o % 3) * VN + (oz + 1) * WN] >= 0;
+        if (!any) continue;
         __syncthreads();
         // stage the 18x18 source window of plane zs: each thread takes up to
         // two cells and issues all loads of a cell at once (record and mass
@@ -630,7 +620,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
                     P w[NREC];
 #pragma unroll
                     for (int k = 0; k < NREC; ++k) {
-                        double val = kind == 1 ? v[k] : (k == 0 && kind == 0 && !LEAF_T ? mm : 0.0);
+                        double val = kind == 1 ? v[k] : (k == 0 && kind == 0 ? mm : 0.0);
                         if (k >= R_DX && k <= R_DZ) val = fma(h, pos[k - R_DX], val);
                         if (k >= R_O) val *= 1.0 / 6.0;
                         w[k] = P(val);
@@ -643,7 +633,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
                         for (int i = 0; i < V; ++i) pp[i] = w[j * V + i];
                         reinterpret_cast<PV*>(smem)[j * MP_SLOTS + c] = pv;
                     }
-                    if (!LEAF_T) leafflag[c] = kind == 0;
+                    leafflag[c] = kind == 0;
                 }
             }
         }
@@ -653,8 +643,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         Acc<PA> part_store;
         Acc<PA>& part = PR != PR_F64 ? part_store : *reinterpret_cast<Acc<PA>*>(&acc);
         if (PR != PR_F64) part.zero();
-        const int32_t* tab = LEAF_T ? c_tab.mp_entry_fp : c_tab.mp_entry;
-        auto reaches = [&](int e) { return !LEAF_T || ((tab[e] >> 16) & cols) != 0; };
+        const int32_t* tab = c_tab.mp_entry;
         auto one = [&](int e) {
             const int ent = tab[e];
             const int dx16 = ((ent & 255) - 8) * 16, dy16 = (((ent >> 8) & 255) - 8) * (16 * MP_PRS);
@@ -670,31 +659,26 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
             const P X = tu - src[R_DX];
             const P Y = tv - src[R_DY];
             const P Z = tw - src[R_DZ];
-            pair_any<!LEAF_T, PR>(X, Y, Z, src, oa, acc, part);
+            pair_any<true, PR>(X, Y, Z, src, oa, acc, part);
         };
         const int fb = c_tab.mp_far_begin[gi], fe = fb + c_tab.mp_far_count[gi];
         // two independent pairs per iteration: two dependency chains per wave
-        // (entries are sorted by footprint, so the two mostly share it)
         int e = fb + w;
         for (; e + 4 < fe; e += 8) {
-            if (reaches(e) || reaches(e + 4)) {
-                one(e);
-                one(e + 4);
-            }
+            one(e);
+            one(e + 4);
         }
-        if (e < fe && reaches(e)) one(e);
+        if (e < fe) one(e);
         if (do_near) {
             const int nbg = c_tab.mp_near_begin[gi], ne = nbg + c_tab.mp_near_count[gi];
             for (int e = nbg + w; e < ne; e += 4) {
-                if (!LEAF_T) {
-                    const int ent = tab[e];
-                    const int dx16 = ((ent & 255) - 8) * 16, dy16 = (((ent >> 8) & 255) - 8) * (16 * MP_PRS);
-                    if (!leafflag[(lbase + __mul24(sx, dx16) + __mul24(sy, dy16)) >> 4]) continue;
-                }
-                if (reaches(e)) one(e);
+                const int ent = tab[e];
+                const int dx16 = ((ent & 255) - 8) * 16, dy16 = (((ent >> 8) & 255) - 8) * (16 * MP_PRS);
+                if (!leafflag[(lbase + __mul24(sx, dx16) + __mul24(sy, dy16)) >> 4]) continue;
+                one(e);
             }
         }
-        if (PR != PR_F64) acc.add(part, !LEAF_T, PR == PR_F32);
+        if (PR != PR_F64) acc.add(part, true, PR == PR_F32);
     }
 
     // combine the 4 waves' partial sums in a fixed order
@@ -723,21 +707,127 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
                red[(2 * NLOC + k) * 64 + l] + red[(3 * NLOC + k) * 64 + l];
     };
     // reduction slot l = v*8 + u holds target cell zt*WS + v*VS + u
-    if (!LEAF_T) {
-        double* out = cx.Lp + size_t(group) * size_t(cx.part_stride) + size_t(tidx) * NLOC * NCELL + zt * WS;
-        for (int i = t; i < NLOC * 64; i += 256) {
-            const int k = i >> 6, l = i & 63;
-            out[k * NCELL + (l >> 3) * VS + (l & 7)] = (k >= T_S ? gs : -G) * sum4(k, l);
+    double* out = cx.Lp + size_t(group) * size_t(cx.part_stride) + size_t(tidx) * NLOC * NCELL + zt * WS;
+    for (int i = t; i < NLOC * 64; i += 256) {
+        const int k = i >> 6, l = i & 63;
+        out[k * NCELL + (l >> 3) * VS + (l & 7)] = (k >= T_S ? gs : -G) * sum4(k, l);
+    }
+}
+
+// Leaf-target item (class 4): the 512 leaf cells of sub-grid sid against the
+// refined cells of its refined neighbours.  A leaf target takes every partner
+// whose parent cell lies within |D|^2 <= 8 of its own parent, so the 8
+// children of one target parent share one partner set: the 8 children of
+// each partner parent.  A wave works on one target parent at a time with
+// lane = target child * 8 + source child and one partner parent per step, so
+// every lane of every step evaluates a real pair.  The partner parents in one
+// refined neighbour (its slab, at most 32 parents) are staged in LDS, one
+// neighbour at a time in slot order; the waves take the target parents of
+// that neighbour in turn, add the 8 source-child sums of each target across
+// lanes in a fixed order, and accumulate them into the item's LDS totals
+// (one wave per target parent and neighbour, so the order is fixed).
+template <int PR>
+__device__ __forceinline__ void c4_item(const Ctx& cx, int sid, unsigned char* smem) {
+    using P = typename std::conditional<PR == PR_F32, float, double>::type;
+    using PA = typename std::conditional<PR == PR_F64, double, float>::type;
+    constexpr int V = 16 / int(sizeof(P));
+    using PV = typename std::conditional<PR == PR_F32, float4, double2>::type;
+    constexpr int SLOTS = C4_SLAB * 8;
+    // LDS: staged slab records [NREC / V groups][SLOTS] of 16 bytes, then the
+    // totals [4][512] (L0, and L1 - S or L1)
+    double* tot = reinterpret_cast<double*>(smem + NREC * SLOTS * sizeof(P));
+    const int t = item_tid(), lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int c = lane & 7, tc = lane >> 3;
+    const SubDev& T = cx.subs[sid];
+    const double h = T.h;
+    const double sfac = cx.corr ? -1.0 : 0.0;  // S holds the correction / 6
+    for (int i = t; i < NLEAF * NCELL; i += 256) tot[i] = 0.0;
+    const P oa[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // leaf targets carry no octupole
+    for (int o = 0; o < 27; ++o) {
+        const int code = T.nbr[o];
+        if (o == 13 || code < 0 || !(code & 1)) continue;
+        const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
+        const int sl = c_tab.c4_slab[o];
+        const int ny = (sl >> 4) & 15, nz = (sl >> 8) & 15, nslab = (sl & 15) * ny * nz * 8;
+        const int px0 = (sl >> 12) & 3, py0 = (sl >> 14) & 3, pz0 = (sl >> 16) & 3;
+        __syncthreads();  // the previous neighbour's slab is no longer read
+        // stage: thread t holds child t & 7 of slab parent t >> 3; its position
+        // in the frame of the target sub-grid (centre of its cell (0,0,0)),
+        // octupole divided by 6
+        if (t < nslab) {
+            const int sp = t >> 3, ch = t & 7;
+            const int ix = sp / (ny * nz), iy = (sp / nz) % ny, iz = sp % nz;
+            const int lx = 2 * (px0 + ix) + (ch >> 2), ly = 2 * (py0 + iy) + ((ch >> 1) & 1);
+            const int lz = 2 * (pz0 + iz) + (ch & 1);
+            const double* r = cx.rec + size_t(code >> 1) * NREC * NCELL + (lz * NS + ly) * NS + lx;
+            double v[NREC];
+#pragma unroll
+            for (int k = 0; k < NREC; ++k) v[k] = r[k * NCELL];
+            v[R_DX] = fma(h, double(NS * ox + lx), v[R_DX]);
+            v[R_DY] = fma(h, double(NS * oy + ly), v[R_DY]);
+            v[R_DZ] = fma(h, double(NS * oz + lz), v[R_DZ]);
+#pragma unroll
+            for (int k = R_O; k < NREC; ++k) v[k] *= 1.0 / 6.0;
+#pragma unroll
+            for (int j = 0; j < NREC / V; ++j) {
+                PV pv;
+                P* pp = reinterpret_cast<P*>(&pv);
+#pragma unroll
+                for (int i = 0; i < V; ++i) pp[i] = P(v[j * V + i]);
+                reinterpret_cast<PV*>(smem)[j * SLOTS + t] = pv;
+            }
         }
-    } else {
-        // own terms from refined sources: phi = -G L0;  g = G L1 - G S
-        double* out = cx.Lf3 + size_t(T.slot3) * NLEAF * NCELL + zt * WS;
-        if (t < 64) {
-            const int o = (t >> 3) * VS + (t & 7);
-            out[0 * NCELL + o] = -G * sum4(0, t);
-            for (int a = 0; a < 3; ++a) out[(1 + a) * NCELL + o] = G * sum4(T_L1 + a, t) + gs * sum4(T_S + a, t);
+        __syncthreads();
+        const int gb = c_tab.c4_grp_begin[o], ge = c_tab.c4_grp_begin[o + 1];
+        for (int g = gb + w; g < ge; g += 4) {
+            const int gi = c_tab.c4_grp[g];
+            const int pt = gi & 63, first = (gi >> 6) & 4095, cnt = gi >> 18;
+            const int tx = 2 * (pt >> 4) + (tc >> 2), ty = 2 * ((pt >> 2) & 3) + ((tc >> 1) & 1);
+            const int tz = 2 * (pt & 3) + (tc & 1);
+            const P X0 = P(h * tx), Y0 = P(h * ty), Z0 = P(h * tz);
+            Acc<double> acc;
+            acc.zero();
+            Acc<PA> part_store;
+            Acc<PA>& part = PR != PR_F64 ? part_store : *reinterpret_cast<Acc<PA>*>(&acc);
+            if (PR != PR_F64) part.zero();
+            for (int k = first; k < first + cnt; ++k) {
+                const int sp = c_tab.c4_task[k];
+                const unsigned char* cs = smem + (sp * 8 + c) * 16;
+                P src[NREC];
+#pragma unroll
+                for (int j = 0; j < NREC / V; ++j) {
+                    const PV pv = *reinterpret_cast<const PV*>(cs + j * (SLOTS * 16));
+                    const P* pp = reinterpret_cast<const P*>(&pv);
+#pragma unroll
+                    for (int i = 0; i < V; ++i) src[j * V + i] = pp[i];
+                }
+                pair_any<false, PR>(X0 - src[R_DX], Y0 - src[R_DY], Z0 - src[R_DZ], src, oa, acc, part);
+            }
+            if (PR != PR_F64) acc.add(part, false, PR == PR_F32);
+            // the 8 source-child sums of each target, added across lanes
+            double v[7] = {acc.l0, acc.l1[0], acc.l1[1], acc.l1[2], acc.s[0], acc.s[1], acc.s[2]};
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                v[k] += __shfl_xor(v[k], 1);
+                v[k] += __shfl_xor(v[k], 2);
+                v[k] += __shfl_xor(v[k], 4);
+            }
+            if (c == 0) {
+                const int q = (tz * NS + ty) * NS + tx;
+                // a target without mass gets no correction term
+                const double sf = cx.mass[size_t(T.idx) * NCELL + q] > 0 ? sfac : 0.0;
+                tot[q] += v[0];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) tot[(1 + a) * NCELL + q] += fma(sf, v[4 + a], v[1 + a]);
+            }
         }
     }
+    __syncthreads();
+    // own terms from refined sources: phi = -G L0;  g = G (L1 - S)
+    const double G = cx.G;
+    double* out = cx.Lf3 + size_t(T.slot3) * NLEAF * NCELL;
+    for (int i = t; i < NLEAF * NCELL; i += 256) out[i] = (i < NCELL ? -G : G) * tot[i];
 }
 
 // Monopole item: leaf targets of one sub-grid against leaf sources (class 3).
@@ -1046,13 +1136,10 @@ template <int PR>
 __device__ __forceinline__ void run_item(const Ctx& cx, const Item& it, unsigned char* smem) {
     switch (it.kind) {
         case IT_MP_REF:
-            if (it.b >> 3) mp_item<false, PR, 1>(cx, it.sub, it.a, it.b & 7, smem);
-            else mp_item<false, PR, 0>(cx, it.sub, it.a, it.b & 7, smem);
+            if (it.b >> 3) mp_item<PR, 1>(cx, it.sub, it.a, it.b & 7, smem);
+            else mp_item<PR, 0>(cx, it.sub, it.a, it.b & 7, smem);
             break;
-        case IT_MP_LEAF:
-            if (it.b >> 3) mp_item<true, PR, 1>(cx, it.sub, it.a, 0, smem);
-            else mp_item<true, PR, 0>(cx, it.sub, it.a, 0, smem);
-            break;
+        case IT_MP_LEAF: c4_item<PR>(cx, it.sub, smem); break;
         case IT_MONO: mono_item<PR, SmemPR<PR>::NBR_OFF>(cx, it.sub, smem); break;
         default: top_item<PR>(cx, cx.top_items[it.sub], smem); break;
     }
@@ -1065,10 +1152,11 @@ __global__ __launch_bounds__(256) void k_class(Ctx cx, const Item* __restrict__ 
     using L = SmemPR<(KIND == IT_MONO && PR == PR_MIX) ? PR_F32 : PR>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[L::BYTES];
     const Item it = items[blockIdx.x];
-    if (KIND == IT_MP_REF || KIND == IT_MP_LEAF) {
-        if (it.b >> 3) mp_item<KIND == IT_MP_LEAF, PR, 1>(cx, it.sub, it.a, it.b & 7, smem);
-        else mp_item<KIND == IT_MP_LEAF, PR, 0>(cx, it.sub, it.a, it.b & 7, smem);
+    if (KIND == IT_MP_REF) {
+        if (it.b >> 3) mp_item<PR, 1>(cx, it.sub, it.a, it.b & 7, smem);
+        else mp_item<PR, 0>(cx, it.sub, it.a, it.b & 7, smem);
     }
+    else if (KIND == IT_MP_LEAF) c4_item<PR>(cx, it.sub, smem);
     else if (KIND == IT_MONO) mono_item<PR, L::NBR_OFF>(cx, it.sub, smem);
     else top_item<PR>(cx, cx.top_items[it.sub], smem);
 }

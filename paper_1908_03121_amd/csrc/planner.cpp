@@ -101,15 +101,46 @@ int64_t top_far_pairs(int ox, int oy, int oz) {
 
 }  // namespace
 
-// 3-bit set (bit o + 1) of the sub-grid sides o in {-1, 0, 1} that the 8 lanes
-// of a row reach with canonical offset d (odd lanes mirror d)
-static int side_set(int d) {
-    int m = 0;
-    for (int u = 0; u < NS; ++u) {
-        const int us = u + ((u & 1) ? -d : d);
-        m |= 1 << ((us < 0 ? -1 : (us >= NS ? 1 : 0)) + 1);
+// Class-4 tables: for every neighbour slot o, the slab of source parents
+// within reach and, per target parent of the leaf, its partner parents in the
+// slab (|D|^2 <= 8 for the parent offset D; every such pair of parents gives
+// the 64 cell pairs of their children, none of them the self pair).
+static void build_c4_tables(StencilTables* t) {
+    int ng = 0, nt = 0;
+    for (int o = 0; o < 27; ++o) {
+        t->c4_grp_begin[o] = ng;
+        t->c4_slab[o] = 0;
+        if (o == 13) continue;
+        const int off[3] = {o / 9 - 1, (o / 3) % 3 - 1, o % 3 - 1};
+        int n[3], p0[3];
+        for (int a = 0; a < 3; ++a) {
+            n[a] = off[a] ? 2 : 4;
+            p0[a] = off[a] < 0 ? 2 : 0;
+        }
+        t->c4_slab[o] = n[0] | (n[1] << 4) | (n[2] << 8) | (p0[0] << 12) | (p0[1] << 14) | (p0[2] << 16);
+        struct Grp { int pt; std::vector<int> src; };
+        std::vector<Grp> grp;
+        for (int pt = 0; pt < 64; ++pt) {
+            const int tp[3] = {pt >> 4, (pt >> 2) & 3, pt & 3};
+            Grp g{pt, {}};
+            for (int sp = 0; sp < n[0] * n[1] * n[2]; ++sp) {
+                const int ip[3] = {sp / (n[1] * n[2]), (sp / n[2]) % n[1], sp % n[2]};
+                int d2 = 0;
+                for (int a = 0; a < 3; ++a) {
+                    const int D = 4 * off[a] + p0[a] + ip[a] - tp[a];
+                    d2 += D * D;
+                }
+                if (d2 <= 8) g.src.push_back(sp);
+            }
+            if (!g.src.empty()) grp.push_back(std::move(g));
+        }
+        std::stable_sort(grp.begin(), grp.end(), [](const Grp& a, const Grp& b) { return a.src.size() > b.src.size(); });
+        for (const Grp& g : grp) {
+            t->c4_grp[ng++] = g.pt | (nt << 6) | (int(g.src.size()) << 18);
+            for (int sp : g.src) t->c4_task[nt++] = int16_t(sp);
+        }
     }
-    return m;
+    t->c4_grp_begin[27] = ng;
 }
 
 void build_stencil_tables(StencilTables* t) {
@@ -124,18 +155,8 @@ void build_stencil_tables(StencilTables* t) {
                 if (c.dz[e] != dz || c.far[e] != (pass == 0)) continue;
                 // footprint: the in-plane neighbour columns (o_u, o_v) that the
                 // 64 lanes of a plane reach, bit (o_u + 1) * 3 + (o_v + 1)
-                const int su = side_set(c.dx[e]), sv = side_set(c.dy[e]);
-                int fp = 0;
-                for (int a = 0; a < 3; ++a)
-                    for (int b = 0; b < 3; ++b)
-                        if (((su >> a) & 1) && ((sv >> b) & 1)) fp |= 1 << (a * 3 + b);
-                t->mp_entry[pos++] = (c.dx[e] + 8) | ((c.dy[e] + 8) << 8) | (fp << 16);
+                t->mp_entry[pos++] = (c.dx[e] + 8) | ((c.dy[e] + 8) << 8);
             }
-            // the same group with equal footprints next to each other, so that
-            // the leaf-target kernel's entry skipping drops them in runs
-            std::copy(t->mp_entry + begin, t->mp_entry + pos, t->mp_entry_fp + begin);
-            std::stable_sort(t->mp_entry_fp + begin, t->mp_entry_fp + pos,
-                             [](int32_t a, int32_t b) { return (a >> 16) < (b >> 16); });
             if (pass == 0) { t->mp_far_begin[g] = begin; t->mp_far_count[g] = pos - begin; }
             else { t->mp_near_begin[g] = begin; t->mp_near_count[g] = pos - begin; }
         }
@@ -156,6 +177,7 @@ void build_stencil_tables(StencilTables* t) {
             }
     }
     t->mono_class_begin[3] = nc;
+    build_c4_tables(t);
     for (int n2 = 1; n2 < MONO_R2; ++n2) {
         const double a = 1.0 / sqrt(double(n2)), b = 1.0 / (double(n2) * sqrt(double(n2)));
         t->mono_r[n2][0] = a;
@@ -395,51 +417,55 @@ void build_items(HostPlan* Pp, int ngroups, bool split) {
     // a source plane with no usable neighbour among the 9 at its offset along
     // the sweep axis (z for sweep 0, y for sweep 1) is skipped by the kernels;
     // the estimates count the planes they visit
-    auto plane_used = [&](const SubDev& S, int sweep, int ws, bool refined_only) {
+    auto plane_used = [&](const SubDev& S, int sweep, int ws) {
         const int ow = ws < 0 ? -1 : (ws >= NS ? 1 : 0);
         const int VN = sweep ? 1 : 3, WN = sweep ? 3 : 1;
-        for (int o = 0; o < 9; ++o) {
-            const int code = S.nbr[(o / 3) * 9 + (o % 3) * VN + (ow + 1) * WN];
-            if (code >= 0 && (!refined_only || (code & 1))) return true;
-        }
+        for (int o = 0; o < 9; ++o)
+            if (S.nbr[(o / 3) * 9 + (o % 3) * VN + (ow + 1) * WN] >= 0) return true;
         return false;
     };
     // stencil entries that target plane zt visits over the canonical plane
     // offsets [i0, i1)
-    auto visited = [&](const SubDev& S, int sweep, int zt, int i0, int i1, bool leaf_t, bool nearc) {
+    auto visited = [&](const SubDev& S, int sweep, int zt, int i0, int i1, bool nearc) {
         double n = 0;
         for (int i = i0; i < i1; ++i)
-            if (plane_used(S, sweep, zt + (1 - 2 * (zt & 1)) * (DZ0 + i), leaf_t))
+            if (plane_used(S, sweep, zt + (1 - 2 * (zt & 1)) * (DZ0 + i)))
                 n += tab.mp_far_count[i] + (nearc ? tab.mp_near_count[i] : 0);
         return n;
     };
     // the sweep of a target: the frame that visits fewer entries (z on a tie)
-    auto best_sweep = [&](const SubDev& S, bool leaf_t, bool nearc) {
+    auto best_sweep = [&](const SubDev& S, bool nearc) {
         double n[2] = {0, 0};
         for (int sw = 0; sw < 2; ++sw)
-            for (int zt = 0; zt < NS; ++zt) n[sw] += visited(S, sw, zt, 0, NDZ, leaf_t, nearc);
+            for (int zt = 0; zt < NS; ++zt) n[sw] += visited(S, sw, zt, 0, NDZ, nearc);
         return n[1] < n[0] ? 1 : 0;
     };
     P.sweep_y_targets = 0;
     for (int32_t s : P.mp_ref) {
         const SubDev& S = P.subs[size_t(s)];
         const bool nearc = (S.flags & 1) != 0;
-        const int sw = best_sweep(S, false, nearc);
+        const int sw = best_sweep(S, nearc);
         P.sweep_y_targets += sw;
         for (int zt = 0; zt < NS; ++zt)
             for (int g = 0; g < ngroups; ++g) {
-                const double n = visited(S, sw, zt, g * NDZ / ngroups, (g + 1) * NDZ / ngroups, false, nearc);
+                const double n = visited(S, sw, zt, g * NDZ / ngroups, (g + 1) * NDZ / ngroups, nearc);
                 all.push_back({Item{IT_MP_REF, s, zt, g | (sw << 3)}, 64.0 * n + 2000.0, S.level});
             }
     }
+    // one class-4 item per leaf with refined neighbours: its cost is its
+    // (target parent, source parent) steps of 64 pairs each, plus the staging
+    // of every refined neighbour's slab
+    int c4_steps[27];
+    for (int o = 0; o < 27; ++o) {
+        c4_steps[o] = 0;
+        for (int g = tab.c4_grp_begin[o]; g < tab.c4_grp_begin[o + 1]; ++g) c4_steps[o] += tab.c4_grp[g] >> 18;
+    }
     for (int32_t s : P.mp_leaf) {
         const SubDev& S = P.subs[size_t(s)];
-        const int sw = best_sweep(S, true, true);
-        P.sweep_y_targets += sw;
-        for (int zt = 0; zt < NS; ++zt) {
-            const double n = visited(S, sw, zt, 0, NDZ, true, true);
-            all.push_back({Item{IT_MP_LEAF, s, zt, sw << 3}, 64.0 * n * 0.68 + 2000.0, S.level});
-        }
+        double cost = 2000.0;
+        for (int o = 0; o < 27; ++o)
+            if (o != 13 && S.nbr[o] >= 0 && (S.nbr[o] & 1)) cost += 64.0 * 0.65 * c4_steps[o] + 1500.0;
+        all.push_back({Item{IT_MP_LEAF, s, 0, 0}, cost, S.level});
     }
     for (int32_t s : P.mono_leaf)
         all.push_back({Item{IT_MONO, s, 0, 0}, 512.0 * 743.0 * 0.025 + 4000.0, P.subs[size_t(s)].level});

@@ -52,6 +52,51 @@ int main(int argc, char** argv) {
     fclose(f);
     StencilTables st;
     build_stencil_tables(&st);
+    // class-4 tables against a brute-force count: for every neighbour slot,
+    // the (target parent, source parent) steps must cover each leaf-target /
+    // source cell pair of the rule (parents within |D|^2 <= 8) exactly once
+    bool ok = st.c4_grp_begin[0] == 0 && st.c4_grp_begin[27] <= C4_MAX_GROUPS;
+    for (int o = 0; o < 27 && ok; ++o) {
+        const int off[3] = {o / 9 - 1, (o / 3) % 3 - 1, o % 3 - 1};
+        std::vector<int> seen(size_t(NCELL) * NCELL, 0);
+        if (o == 13) {
+            ok = st.c4_grp_begin[14] == st.c4_grp_begin[13];
+            continue;
+        }
+        const int sl = st.c4_slab[o];
+        const int n[3] = {sl & 15, (sl >> 4) & 15, (sl >> 8) & 15};
+        const int p0[3] = {(sl >> 12) & 3, (sl >> 14) & 3, (sl >> 16) & 3};
+        if (n[0] * n[1] * n[2] > C4_SLAB) ok = false;
+        for (int g = st.c4_grp_begin[o]; g < st.c4_grp_begin[o + 1] && ok; ++g) {
+            const int pt = st.c4_grp[g] & 63, first = (st.c4_grp[g] >> 6) & 4095, cnt = st.c4_grp[g] >> 18;
+            if (first + cnt > C4_MAX_TASKS) { ok = false; break; }
+            for (int k = first; k < first + cnt; ++k) {
+                const int sp = st.c4_task[k];
+                const int ip[3] = {sp / (n[1] * n[2]), (sp / n[2]) % n[1], sp % n[2]};
+                for (int tc = 0; tc < 8; ++tc)
+                    for (int sc = 0; sc < 8; ++sc) {
+                        const int tq = ((2 * (pt & 3) + (tc & 1)) * 8 + 2 * ((pt >> 2) & 3) + ((tc >> 1) & 1)) * 8 +
+                                       2 * (pt >> 4) + (tc >> 2);
+                        const int scl[3] = {sc >> 2, (sc >> 1) & 1, sc & 1};
+                        int cs[3];
+                        for (int a = 0; a < 3; ++a) cs[a] = 2 * (p0[a] + ip[a]) + scl[a];
+                        const int sq = (cs[2] * 8 + cs[1]) * 8 + cs[0];
+                        seen[size_t(tq) * NCELL + size_t(sq)]++;
+                    }
+            }
+        }
+        for (int tq = 0; tq < NCELL && ok; ++tq)
+            for (int sq = 0; sq < NCELL; ++sq) {
+                const int t[3] = {tq & 7, (tq >> 3) & 7, tq >> 6}, s[3] = {sq & 7, (sq >> 3) & 7, sq >> 6};
+                int d2 = 0;
+                for (int a = 0; a < 3; ++a) {
+                    const int D = 4 * off[a] + (s[a] >> 1) - (t[a] >> 1);  // parent offset
+                    d2 += D * D;
+                }
+                if (seen[size_t(tq) * NCELL + size_t(sq)] != (d2 <= 8 ? 1 : 0)) { ok = false; break; }
+            }
+    }
+    printf("%s\n", ok ? "c4 tables ok" : "c4 tables WRONG");
     printf("done\n");
     return 0;
 }

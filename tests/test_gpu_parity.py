@@ -468,8 +468,8 @@ def test_mixed_amr_error_bounds(shape, precision):
 def flat_forest(seed):
     """A 3 x 1 x 3 forest of refined level-0 sub-grids (level 1 is 6 x 2 x 6
     sub-grids, one side in y always absent), a few level-1 sub-grids refined
-    once more: multipole targets whose sources lie beside them in y, the case
-    where plane items run along y."""
+    once more: refined targets whose sources lie beside them in y, the case
+    where plane items run along y, and leaf targets beside refined ones."""
     rng = np.random.default_rng(seed)
     subs = [(0, x, 0, z) for x in range(3) for z in range(3)]
     l1 = [(1, x, y, z) for x in range(6) for y in range(2) for z in range(6)]
@@ -490,7 +490,7 @@ def test_y_sweep_targets_fp64(shape):
     errs = field_errors(phi, g, pr, gr)
     f, tq = residuals(t, rho, g, centre=(0.75, 0.0625, 0.75))
     print(f"  {n_y} y-sweep targets, errors {errs}, force {f:.3e} torque {tq:.3e}", flush=True)
-    assert n_y >= 8 and st["pairs"][3] > 0
+    assert n_y >= 3 and st["pairs"][3] > 0
     assert max(errs) < TOL64
     assert st["pairs"] == ost["cls"]
     assert f < 1e-13 and tq < 1e-13

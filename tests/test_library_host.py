@@ -135,13 +135,13 @@ def _plane_visits(usable, sweep, near, far_by_w, near_by_w):
     return n
 
 
-@pytest.mark.parametrize("name", ["c2", "amr11"])
+@pytest.mark.parametrize("name", ["c2", "amr3"])
 def test_planner_sweep_choice(name):
-    """The planner runs a multipole target's plane items along y exactly when
+    """The planner runs a refined target's plane items along y exactly when
     that frame visits fewer stencil entries than the z frame; recounted here
     from the interaction rule and the tree alone."""
     import itertools
-    W = wl.c2() if name == "c2" else wl.small_amr(11, max_level=3, p_refine=0.3)
+    W = wl.c2() if name == "c2" else wl.small_amr(3, max_level=3, p_refine=0.3)
     t = W.trees[0]
     far = np.zeros(10, int)
     near = np.zeros(10, int)
@@ -163,12 +163,9 @@ def test_planner_sweep_choice(name):
                 nb[o[0] + 1, o[1] + 1, o[2] + 1] = 1 if ref[j] else 0
         others = nb.copy()
         others[1, 1, 1] = -1
-        if ref[s]:
-            usable, near_on = nb >= 0, bool((others == 0).any())
-        elif (others == 1).any():
-            usable, near_on = nb == 1, True
-        else:
-            continue
+        if not ref[s]:
+            continue                      # leaf targets are grouped by parent cell, not by plane
+        usable, near_on = nb >= 0, bool((others == 0).any())
         v = [_plane_visits(usable, sw, near_on, far, near) for sw in (0, 1)]
         n_y += v[1] < v[0]
     st = fm.fmmg_count_pairs([t])
@@ -201,3 +198,4 @@ def test_bench_c1_shape_spec_parses_to_plan_arguments():
     for bad in ("per_class_5_b3_o1", "fused_g1_b1_o0", "per_class_g5_o1_b3"):
         with pytest.raises((AssertionError, ValueError)):
             bench.parse_shape(bad)
+

@@ -52,16 +52,16 @@ def test_planner_clean_under_sanitizers(tmp_path):
         sets[f"amr{s}"] = wl.small_amr(s, max_level=3).trees
     dump = str(tmp_path / "trees.bin")
     _dump(dump, sets)
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0:verify_asan_link_order=0",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
-    env.pop("LD_PRELOAD", None)
     r = subprocess.run([exe, dump], capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0, (r.stdout[-1000:], r.stderr[-3000:])
     assert "runtime error" not in r.stderr and "ERROR: AddressSanitizer" not in r.stderr, r.stderr[-3000:]
     lines = r.stdout.strip().splitlines()
     assert lines[-1] == "done"
+    assert lines[-2] == "c4 tables ok", lines[-2]
     rows = {}
-    for ln in lines[:-1]:
+    for ln in lines[:-2]:
         name, top_full, *v = ln.split()
         rows[(name, int(top_full))] = [int(x) for x in v]
     assert len(rows) == 2 * len(sets)
