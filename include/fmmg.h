@@ -256,6 +256,24 @@ fmmg_status fmmg_density_status(fmmg_plan* plan, int64_t* bad_index);
  * (with the first bad index in the error text). */
 fmmg_status fmmg_check_density(fmmg_plan* plan, const double* rho, void* hip_stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The check
+ * of fmmg_check_density without a plan: records, on hip_stream, in the
+ * caller's device word *bad_index the smallest flat index i < n with rho[i]
+ * negative or not finite, or -1.  Allocates nothing, does not synchronise and
+ * copies nothing to the host (read *bad_index after the stream has reached
+ * it).  Its partial results live in a static device array of the library
+ * (512 KiB per GPU, held until the process ends) shared by every call on that
+ * GPU: calls that overlap in time on one GPU race and must be serialised by
+ * the caller.
+ * rho: device float64 [n], caller-owned, read only (may be NULL when n = 0).
+ * bad_index: device int64 [1], caller-owned, written.
+ * Errors: FMMG_EINVAL for n < 0, n > FMMG_NOALLOC_MAX_DENSITIES or a null
+ * pointer (nothing enqueued); FMMG_EHIP if a HIP call fails. */
+#define FMMG_NOALLOC_MAX_DENSITIES ((int64_t)65536 * 4096)
+fmmg_status fmmg_check_density_noalloc(const double* rho, int64_t n, int64_t* bad_index,
+                                       void* hip_stream);
+
 /* Sums the stage durations of the solves enqueued with options.timing = 1
  * since the previous call (or plan creation), then starts a new sum.  The
  * caller must have synchronised the solves' stream.  FMMG_EINVAL if the plan

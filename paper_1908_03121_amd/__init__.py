@@ -23,11 +23,12 @@ LIB_PATH = os.path.join(_HERE, "libfmmg.so")
 FMMG_OK, FMMG_EINVAL, FMMG_ETREE, FMMG_ENOMEM, FMMG_EHIP, FMMG_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 FMMG_FP64, FMMG_MIXED, FMMG_MIXED_F32 = 0, 1, 2
 FMMG_TOP_FULL, FMMG_TOP_STENCIL_ONLY = 0, 1
+FMMG_NOALLOC_MAX_DENSITIES = 65536 * 4096  # fmmg_check_density_noalloc: its static array's reach
 _STATUS = {0: "FMMG_OK", -1: "FMMG_EINVAL", -2: "FMMG_ETREE", -3: "FMMG_ENOMEM", -4: "FMMG_EHIP",
            -5: "FMMG_EUNSUPPORTED"}
 
 EXPORTED = ["fmmg_default_options", "fmmg_plan_create", "fmmg_plan_n_leaves", "fmmg_leaf_order",
-            "fmmg_solve", "fmmg_density_status", "fmmg_check_density",
+            "fmmg_solve", "fmmg_density_status", "fmmg_check_density", "fmmg_check_density_noalloc",
             "fmmg_get_timings", "fmmg_get_launch_shape",
             "fmmg_get_stats", "fmmg_plan_destroy", "fmmg_last_error", "fmmg_count_pairs",
             "fmmg_version"]
@@ -105,6 +106,7 @@ def lib() -> C.CDLL:
         L.fmmg_solve.argtypes = [vp, vp, vp, vp, vp]
         L.fmmg_density_status.argtypes = [vp, C.POINTER(C.c_int64)]
         L.fmmg_check_density.argtypes = [vp, vp, vp]
+        L.fmmg_check_density_noalloc.argtypes = [vp, C.c_int64, vp, vp]
         L.fmmg_get_stats.argtypes = [vp, C.POINTER(fmmg_stats)]
         L.fmmg_get_timings.argtypes = [vp, C.POINTER(fmmg_timings)]
         L.fmmg_get_launch_shape.argtypes = [vp, C.POINTER(fmmg_launch_shape)]
@@ -118,7 +120,8 @@ def lib() -> C.CDLL:
         L.fmmg_version.restype = C.c_int32
         for name in ("fmmg_plan_create", "fmmg_plan_n_leaves", "fmmg_leaf_order", "fmmg_solve",
                      "fmmg_density_status",
-                     "fmmg_check_density", "fmmg_get_stats", "fmmg_count_pairs", "fmmg_get_timings",
+                     "fmmg_check_density", "fmmg_check_density_noalloc", "fmmg_get_stats",
+                     "fmmg_count_pairs", "fmmg_get_timings",
                      "fmmg_get_launch_shape"):
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -226,6 +229,21 @@ def fmmg_density_status(plan) -> int:
 def fmmg_check_density(plan, rho, stream=None) -> None:
     n = fmmg_plan_n_leaves(plan)
     _check(lib().fmmg_check_density(plan, _dptr(rho, n * 512, "rho"), _stream_ptr(stream)))
+
+
+def fmmg_check_density_noalloc(rho, n, bad_index, stream=None) -> None:
+    """rho: contiguous float64 CUDA tensor of at least n elements; bad_index:
+    int64 CUDA tensor of one element that receives -1 or the smallest bad flat
+    index when the stream reaches the check."""
+    import torch
+    if not isinstance(rho, torch.Tensor) or rho.dtype != torch.float64 or not rho.is_cuda \
+            or not rho.is_contiguous() or rho.numel() < n:
+        raise ValueError(f"rho must be a contiguous float64 CUDA tensor of at least {n} elements")
+    if not isinstance(bad_index, torch.Tensor) or bad_index.dtype != torch.int64 or not bad_index.is_cuda \
+            or bad_index.numel() < 1:
+        raise ValueError("bad_index must be an int64 CUDA tensor of one element")
+    _check(lib().fmmg_check_density_noalloc(rho.data_ptr() if n > 0 else None, int(n), bad_index.data_ptr(),
+                                            _stream_ptr(stream)))
 
 
 def fmmg_get_stats(plan) -> dict:

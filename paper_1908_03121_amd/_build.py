@@ -24,6 +24,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 SOURCES = [
     ("kernels.hip", "hip"),
+    ("noalloc.hip", "hip"),
     ("fmmg_api.cpp", "host"),
     ("planner.cpp", "host"),
 ]

@@ -965,6 +965,20 @@ fmmg_status fmmg_check_density(fmmg_plan* p, const double* rho, void* hip_stream
     return FMMG_OK;
 }
 
+fmmg_status fmmg_check_density_noalloc(const double* rho, int64_t n, int64_t* bad_index, void* hip_stream) {
+    if (n < 0) return fail(FMMG_EINVAL, "fmmg_check_density_noalloc: negative size");
+    if (n > FMMG_NOALLOC_MAX_DENSITIES)
+        return fail(FMMG_EINVAL, "fmmg_check_density_noalloc: " + std::to_string(n) +
+                                     " densities exceed the maximum of " + std::to_string(FMMG_NOALLOC_MAX_DENSITIES) +
+                                     " that its static array covers");
+    if (!bad_index || (!rho && n > 0)) return fail(FMMG_EINVAL, "fmmg_check_density_noalloc: null argument");
+    static_assert(FMMG_NOALLOC_MAX_DENSITIES == int64_t(NOALLOC_SLOTS) * NOALLOC_CHUNK, "static array size");
+    std::string what;
+    const hipError_t e = noalloc_check_density(rho, n, bad_index, reinterpret_cast<hipStream_t>(hip_stream), &what);
+    if (e != hipSuccess) return hip_fail(e, what.c_str());
+    return FMMG_OK;
+}
+
 fmmg_status fmmg_get_timings(fmmg_plan* p, fmmg_timings* out) {
     if (!p || !out) return fail(FMMG_EINVAL, "null argument");
     if (!p->opt.timing) return fail(FMMG_EINVAL, "plan was created without timing");

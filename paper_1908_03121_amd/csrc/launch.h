@@ -4,6 +4,8 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "fmmg_internal.h"
 
 namespace fmmg {
@@ -51,5 +53,14 @@ void launch_l2l(const Ctx& a, const int32_t* tasks, int n, int parent_mode, doub
 void launch_leaf_out(const Ctx& a, const int32_t* list, int n, double* phi, double* g);
 void launch_check_density(const double* rho, int64_t n, unsigned long long* bad, hipStream_t st);
 void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st);
+
+// Density check without allocation (noalloc.hip): partial results in a
+// static device array of NOALLOC_SLOTS words, one per chunk of NOALLOC_CHUNK
+// densities, so n <= NOALLOC_SLOTS * NOALLOC_CHUNK.  On failure *err names
+// the failing step.
+constexpr int NOALLOC_SLOTS = 65536;
+constexpr int NOALLOC_CHUNK = 4096;
+hipError_t noalloc_check_density(const double* rho, int64_t n, int64_t* out, hipStream_t st,
+                                 std::string* err);
 
 }  // namespace fmmg

@@ -199,3 +199,13 @@ def test_bench_c1_shape_spec_parses_to_plan_arguments():
         with pytest.raises((AssertionError, ValueError)):
             bench.parse_shape(bad)
 
+
+def test_noalloc_density_check_refuses_bad_sizes_before_any_device_call():
+    """The allocation-free density check validates its size and pointers on the
+    host; these calls return FMMG_EINVAL without touching a device."""
+    L = fm.lib()
+    dummy = ctypes.c_void_p(16)
+    for n, rho, out in ((-1, dummy, dummy), (fm.FMMG_NOALLOC_MAX_DENSITIES + 1, dummy, dummy),
+                        (8, None, dummy), (8, dummy, None)):
+        assert L.fmmg_check_density_noalloc(rho, n, out, None) == fm.FMMG_EINVAL
+    assert "maximum" in fm.fmmg_last_error() or "null" in fm.fmmg_last_error()
