@@ -17,7 +17,8 @@
 //   Lf   [n_leaf][4][512]         leaf cells' own potential and acceleration
 //                                 from leaf sources (or the top level)
 //   Lf3  [n_slot3][4][512]        the same from refined sources, for leaves
-//                                 that have refined neighbours
+//                                 that have refined neighbours: one slot per
+//                                 class-4 item, a leaf's slots consecutive
 // Trace-free storage is exact here: every contraction of the method is with a
 // derivative tensor of 1/r, which is harmonic (trace-free), and trace parts
 // of children's moments contribute only trace parts to the parent's.
@@ -75,9 +76,10 @@ struct SubDev {
     int32_t child[8];  // refined: child sub-grid ids, slot ex*4 + ey*2 + ez
     int32_t coord[3];
     int32_t flags;     // bit0: has a leaf neighbour; bit1: has a refined neighbour
-    int32_t slot3;     // leaf with refined neighbours: its Lf3 slot, else -1
+    int32_t slot3;     // leaf with refined neighbours: its first Lf3 slot, else -1
     int32_t red;       // top level under the all-pairs rule: its TopReduce index, else -1
-    int32_t pad;
+    int32_t n3;        // leaf with refined neighbours: its number of Lf3 slots (one per
+                       // class-4 item), else 0
 };
 
 // Same-level work items.  A block of 256 threads (4 waves) runs one item.
@@ -86,9 +88,11 @@ constexpr int MAX_GROUPS = 5;   // source-plane groups of a refined-target item 
 struct Item {
     int32_t kind;
     int32_t sub;   // target sub-grid (IT_TOP: index into the top items)
-    int32_t a;     // IT_MP_REF: target plane along the sweep axis
+    int32_t a;     // IT_MP_REF: target plane along the sweep axis;
+                   // IT_MP_LEAF: neighbour slots [a & 255, a >> 8)
     int32_t b;     // IT_MP_REF: plane group in bits 0..2, sweep in bit 3
-                   // (0: planes along z, lanes on (x, y); 1: along y, lanes on (x, z))
+                   // (0: planes along z, lanes on (x, y); 1: along y, lanes on (x, z));
+                   // IT_MP_LEAF: its Lf3 slot
 };
 
 // Leaf targets with refined sources (class 4) are grouped by target parent
@@ -101,6 +105,10 @@ struct Item {
 constexpr int C4_SLAB = 32;        // source parents of a face neighbour's slab (2 x 4 x 4)
 constexpr int C4_MAX_TASKS = 3584; // (target parent, source parent) pairs over the 26 slots: 3560
 constexpr int C4_MAX_GROUPS = 448; // (slot, target parent) groups: 6 x 32 + 12 x 16 + 8 x 4
+// A leaf's refined neighbours are taken in slot order and cut into items of
+// at least this many (target parent, source parent) steps (a face neighbour
+// has 444, an edge 70, a corner 7), each with its own Lf3 slot.
+constexpr int C4_ITEM_STEPS = 400;
 
 // Canonical stencil tables (parity (0,0,0); other parities are mirror images:
 // a cell of parity p uses offset (sx*dx, sy*dy, sz*dz) with s = 1 - 2p).

@@ -305,11 +305,13 @@ __global__ __launch_bounds__(512) void k_p2m_top(Ctx cx, const int32_t* __restri
 
 // One octant of a refined sub-grid's cells from the 512 cells of one child
 // sub-grid (leaf: point masses m = rho h^3 at the cell centres, also stored
-// for the same-level step; refined: their records).  Each thread takes one
-// child cell and forms its contribution about the parent cell centre c
-// (r0 = child COM - c):  m, m r0, q + m r0 r0, o + sym(q r0) + m r0 r0 r0.
-// The 8 siblings of a parent cell are summed (lane shuffles across x and y
-// parity, LDS across z parity); the sums are then moved to the parent COM
+// for the same-level step; refined: their records).  The contribution of a
+// child cell about the parent cell centre c (r0 = child COM - c) is
+//   m, m r0, q + m r0 r0, o + sym(q r0) + m r0 r0 r0.
+// Refined children: each thread takes one child cell and the 8 siblings of a
+// parent cell are summed (lane shuffles across x and y parity, LDS across z
+// parity).  Leaf children: one thread per parent cell sums its 8 point masses
+// in closed form.  The sums are then moved to the parent COM
 // offset d = S1/m (binomial shift with M1 = m d):
 //   M2 = S2 - m d d,   M3 = S3 - sym(S2 d) + 2 m d d d,
 // and stored trace-free (children's trace parts only feed trace parts).
@@ -329,71 +331,107 @@ __global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__
     }
     const int x = q & 7, y = (q >> 3) & 7, z = q >> 6;
     const double hc = Cs.h;
-    double w, dx = 0, dy = 0, dz = 0;
-    double qxx = 0, qyy = 0, qxy = 0, qxz = 0, qyz = 0;
-    double o0 = 0, o1 = 0, o2 = 0, o3 = 0, o4 = 0, o5 = 0, o6 = 0;
-    if (Cs.kind == 1) {
-        const double* r = cx.rec + size_t(Cs.idx) * NREC * NCELL + q;
-        w = r[R_M * NCELL];
-        dx = r[R_DX * NCELL];
-        dy = r[R_DY * NCELL];
-        dz = r[R_DZ * NCELL];
-        qxx = r[(R_Q + 0) * NCELL];
-        qyy = r[(R_Q + 1) * NCELL];
-        qxy = r[(R_Q + 2) * NCELL];
-        qxz = r[(R_Q + 3) * NCELL];
-        qyz = r[(R_Q + 4) * NCELL];
-        o0 = r[(R_O + 0) * NCELL];
-        o1 = r[(R_O + 1) * NCELL];
-        o2 = r[(R_O + 2) * NCELL];
-        o3 = r[(R_O + 3) * NCELL];
-        o4 = r[(R_O + 4) * NCELL];
-        o5 = r[(R_O + 5) * NCELL];
-        o6 = r[(R_O + 6) * NCELL];
-    } else {
-        const int io = io_index(q);
-        w = rin[io + (io >> 3)] * (hc * hc * hc);
-        cx.mass[size_t(Cs.idx) * NCELL + q] = w;
-    }
-    const double rx = ((x & 1) - 0.5) * hc + dx, ry = ((y & 1) - 0.5) * hc + dy, rz = ((z & 1) - 0.5) * hc + dz;
-    const double qzz = -qxx - qyy;
     double v[20];
-    v[0] = w;
-    v[1] = w * rx;
-    v[2] = w * ry;
-    v[3] = w * rz;
-    v[4] = qxx + w * rx * rx;
-    v[5] = qyy + w * ry * ry;
-    v[6] = qzz + w * rz * rz;
-    v[7] = qxy + w * rx * ry;
-    v[8] = qxz + w * rx * rz;
-    v[9] = qyz + w * ry * rz;
-    v[10] = o0 + 3 * qxx * rx + w * rx * rx * rx;
-    v[11] = o1 + qxx * ry + 2 * qxy * rx + w * rx * rx * ry;
-    v[12] = o2 + qxx * rz + 2 * qxz * rx + w * rx * rx * rz;
-    v[13] = o3 + 2 * qxy * ry + qyy * rx + w * rx * ry * ry;
-    v[14] = o4 + qxy * rz + qxz * ry + qyz * rx + w * rx * ry * rz;
-    v[15] = (-o0 - o3) + 2 * qxz * rz + qzz * rx + w * rx * rz * rz;
-    v[16] = o5 + 3 * qyy * ry + w * ry * ry * ry;
-    v[17] = o6 + qyy * rz + 2 * qyz * ry + w * ry * ry * rz;
-    v[18] = (-o1 - o5) + 2 * qyz * rz + qzz * ry + w * ry * rz * rz;
-    v[19] = (-o2 - o6) + 3 * qzz * rz + w * rz * rz * rz;
-    // siblings across x parity (lane ^ 1) and y parity (lane ^ 8)
+    if (Cs.kind == 0) {
+        // leaf child: point masses at the cell centres, r0 = s a with sign
+        // vector s in {-1, 1}^3 and a = h/2, so the sums need only the 8
+        // signed mass sums M, S_i = sum s_i m, S_ij = sum s_i s_j m (i != j),
+        // S_xyz; one thread per parent cell (the even-even-even child)
+        const double h3 = hc * hc * hc;
+        {
+            const int io = io_index(q);
+            cx.mass[size_t(Cs.idx) * NCELL + q] = rin[io + (io >> 3)] * h3;
+        }
+        if ((x | y | z) & 1) return;
+        double mc[2][2][2];
 #pragma unroll
-    for (int k = 0; k < 20; ++k) {
-        v[k] += __shfl_xor(v[k], 1);
-        v[k] += __shfl_xor(v[k], 8);
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int io = ((x + i) * NS + (y + j)) * NS + (z + k);
+                    mc[i][j][k] = rin[io + (io >> 3)] * h3;
+                }
+        double p[2][2], d[2][2];  // along z: sum and difference
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                p[i][j] = mc[i][j][1] + mc[i][j][0];
+                d[i][j] = mc[i][j][1] - mc[i][j][0];
+            }
+        double pp[2], pd[2], dp[2], dd[2];  // then along y
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            pp[i] = p[i][1] + p[i][0];
+            pd[i] = p[i][1] - p[i][0];
+            dp[i] = d[i][1] + d[i][0];
+            dd[i] = d[i][1] - d[i][0];
+        }
+        const double M = pp[1] + pp[0], Sx = pp[1] - pp[0], Sy = pd[1] + pd[0], Sxy = pd[1] - pd[0];
+        const double Sz = dp[1] + dp[0], Sxz = dp[1] - dp[0], Syz = dd[1] + dd[0], Sxyz = dd[1] - dd[0];
+        const double a1 = 0.5 * hc, a2 = a1 * a1, a3 = a2 * a1;
+        v[0] = M;
+        v[1] = a1 * Sx;
+        v[2] = a1 * Sy;
+        v[3] = a1 * Sz;
+        v[4] = v[5] = v[6] = a2 * M;
+        v[7] = a2 * Sxy;
+        v[8] = a2 * Sxz;
+        v[9] = a2 * Syz;
+        v[10] = v[13] = v[15] = a3 * Sx;  // xxx, xyy, xzz
+        v[11] = v[16] = v[18] = a3 * Sy;  // xxy, yyy, yzz
+        v[12] = v[17] = v[19] = a3 * Sz;  // xxz, yyz, zzz
+        v[14] = a3 * Sxyz;
+    } else {
+        const double* r = cx.rec + size_t(Cs.idx) * NREC * NCELL + q;
+        const double w = r[R_M * NCELL];
+        const double dx = r[R_DX * NCELL], dy = r[R_DY * NCELL], dz = r[R_DZ * NCELL];
+        const double qxx = r[(R_Q + 0) * NCELL], qyy = r[(R_Q + 1) * NCELL], qxy = r[(R_Q + 2) * NCELL];
+        const double qxz = r[(R_Q + 3) * NCELL], qyz = r[(R_Q + 4) * NCELL];
+        const double o0 = r[(R_O + 0) * NCELL], o1 = r[(R_O + 1) * NCELL], o2 = r[(R_O + 2) * NCELL];
+        const double o3 = r[(R_O + 3) * NCELL], o4 = r[(R_O + 4) * NCELL], o5 = r[(R_O + 5) * NCELL];
+        const double o6 = r[(R_O + 6) * NCELL];
+        const double rx = ((x & 1) - 0.5) * hc + dx, ry = ((y & 1) - 0.5) * hc + dy, rz = ((z & 1) - 0.5) * hc + dz;
+        const double qzz = -qxx - qyy;
+        v[0] = w;
+        v[1] = w * rx;
+        v[2] = w * ry;
+        v[3] = w * rz;
+        v[4] = qxx + w * rx * rx;
+        v[5] = qyy + w * ry * ry;
+        v[6] = qzz + w * rz * rz;
+        v[7] = qxy + w * rx * ry;
+        v[8] = qxz + w * rx * rz;
+        v[9] = qyz + w * ry * rz;
+        v[10] = o0 + 3 * qxx * rx + w * rx * rx * rx;
+        v[11] = o1 + qxx * ry + 2 * qxy * rx + w * rx * rx * ry;
+        v[12] = o2 + qxx * rz + 2 * qxz * rx + w * rx * rx * rz;
+        v[13] = o3 + 2 * qxy * ry + qyy * rx + w * rx * ry * ry;
+        v[14] = o4 + qxy * rz + qxz * ry + qyz * rx + w * rx * ry * rz;
+        v[15] = (-o0 - o3) + 2 * qxz * rz + qzz * rx + w * rx * rz * rz;
+        v[16] = o5 + 3 * qyy * ry + w * ry * ry * ry;
+        v[17] = o6 + qyy * rz + 2 * qyz * ry + w * ry * ry * rz;
+        v[18] = (-o1 - o5) + 2 * qyz * rz + qzz * ry + w * ry * rz * rz;
+        v[19] = (-o2 - o6) + 3 * qzz * rz + w * rz * rz * rz;
+        // siblings across x parity (lane ^ 1) and y parity (lane ^ 8)
+#pragma unroll
+        for (int k = 0; k < 20; ++k) {
+            v[k] += __shfl_xor(v[k], 1);
+            v[k] += __shfl_xor(v[k], 8);
+        }
+        const bool leader = ((x | y) & 1) == 0;
+        const int pc = (y >> 1) * 4 + (x >> 1);
+        if (leader && (z & 1)) {
+#pragma unroll
+            for (int k = 0; k < 20; ++k) red[z >> 1][pc][k] = v[k];
+        }
+        __syncthreads();
+        if (!leader || (z & 1)) return;
+#pragma unroll
+        for (int k = 0; k < 20; ++k) v[k] += red[z >> 1][pc][k];
     }
-    const bool leader = ((x | y) & 1) == 0;
-    const int pc = (y >> 1) * 4 + (x >> 1);
-    if (leader && (z & 1)) {
-#pragma unroll
-        for (int k = 0; k < 20; ++k) red[z >> 1][pc][k] = v[k];
-    }
-    __syncthreads();
-    if (!leader || (z & 1)) return;
-#pragma unroll
-    for (int k = 0; k < 20; ++k) v[k] += red[z >> 1][pc][k];
     const double m = v[0];
     double ox = 0, oy = 0, oz = 0;
     if (m > 0) {
@@ -715,7 +753,8 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
 }
 
 // Leaf-target item (class 4): the 512 leaf cells of sub-grid sid against the
-// refined cells of its refined neighbours.  A leaf target takes every partner
+// refined cells of its refined neighbours in slots [o0, o1), written to Lf3
+// slot `slot`.  A leaf target takes every partner
 // whose parent cell lies within |D|^2 <= 8 of its own parent, so the 8
 // children of one target parent share one partner set: the 8 children of
 // each partner parent.  A wave works on one target parent at a time with
@@ -727,7 +766,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
 // lanes in a fixed order, and accumulate them into the item's LDS totals
 // (one wave per target parent and neighbour, so the order is fixed).
 template <int PR>
-__device__ __forceinline__ void c4_item(const Ctx& cx, int sid, unsigned char* smem) {
+__device__ __forceinline__ void c4_item(const Ctx& cx, int sid, int o0, int o1, int slot, unsigned char* smem) {
     using P = typename std::conditional<PR == PR_F32, float, double>::type;
     using PA = typename std::conditional<PR == PR_F64, double, float>::type;
     constexpr int V = 16 / int(sizeof(P));
@@ -744,7 +783,7 @@ __device__ __forceinline__ void c4_item(const Ctx& cx, int sid, unsigned char* s
     const double sfac = cx.corr ? -1.0 : 0.0;  // S holds the correction / 6
     for (int i = t; i < NLEAF * NCELL; i += 256) tot[i] = 0.0;
     const P oa[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // leaf targets carry no octupole
-    for (int o = 0; o < 27; ++o) {
+    for (int o = o0; o < o1; ++o) {
         const int code = T.nbr[o];
         if (o == 13 || code < 0 || !(code & 1)) continue;
         const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
@@ -826,7 +865,7 @@ __device__ __forceinline__ void c4_item(const Ctx& cx, int sid, unsigned char* s
     __syncthreads();
     // own terms from refined sources: phi = -G L0;  g = G (L1 - S)
     const double G = cx.G;
-    double* out = cx.Lf3 + size_t(T.slot3) * NLEAF * NCELL;
+    double* out = cx.Lf3 + size_t(slot) * NLEAF * NCELL;
     for (int i = t; i < NLEAF * NCELL; i += 256) out[i] = (i < NCELL ? -G : G) * tot[i];
 }
 
@@ -1139,7 +1178,7 @@ __device__ __forceinline__ void run_item(const Ctx& cx, const Item& it, unsigned
             if (it.b >> 3) mp_item<PR, 1>(cx, it.sub, it.a, it.b & 7, smem);
             else mp_item<PR, 0>(cx, it.sub, it.a, it.b & 7, smem);
             break;
-        case IT_MP_LEAF: c4_item<PR>(cx, it.sub, smem); break;
+        case IT_MP_LEAF: c4_item<PR>(cx, it.sub, it.a & 255, it.a >> 8, it.b, smem); break;
         case IT_MONO: mono_item<PR, SmemPR<PR>::NBR_OFF>(cx, it.sub, smem); break;
         default: top_item<PR>(cx, cx.top_items[it.sub], smem); break;
     }
@@ -1156,7 +1195,7 @@ __global__ __launch_bounds__(256) void k_class(Ctx cx, const Item* __restrict__ 
         if (it.b >> 3) mp_item<PR, 1>(cx, it.sub, it.a, it.b & 7, smem);
         else mp_item<PR, 0>(cx, it.sub, it.a, it.b & 7, smem);
     }
-    else if (KIND == IT_MP_LEAF) c4_item<PR>(cx, it.sub, smem);
+    else if (KIND == IT_MP_LEAF) c4_item<PR>(cx, it.sub, it.a & 255, it.a >> 8, it.b, smem);
     else if (KIND == IT_MONO) mono_item<PR, L::NBR_OFF>(cx, it.sub, smem);
     else top_item<PR>(cx, cx.top_items[it.sub], smem);
 }
@@ -1317,8 +1356,8 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
     } else {
         const double* F = cx.Lf + size_t(Cs.idx) * NLEAF * NCELL + q;
         double f0 = F[0], f1 = F[1 * NCELL], f2 = F[2 * NCELL], f3 = F[3 * NCELL];
-        if (Cs.slot3 >= 0) {
-            const double* F3 = cx.Lf3 + size_t(Cs.slot3) * NLEAF * NCELL + q;
+        for (int j = 0; j < Cs.n3; ++j) {  // class-4 slots, in order
+            const double* F3 = cx.Lf3 + size_t(Cs.slot3 + j) * NLEAF * NCELL + q;
             f0 += F3[0];
             f1 += F3[1 * NCELL];
             f2 += F3[2 * NCELL];
@@ -1358,7 +1397,7 @@ __global__ __launch_bounds__(512) void k_leaf_out(Ctx cx, const int32_t* __restr
         const double* F = cx.Lf + size_t(S.idx) * NLEAF * NCELL + q;
         for (int k = 0; k < 4; ++k) {
             double v = F[k * NCELL];
-            if (S.slot3 >= 0) v += cx.Lf3[size_t(S.slot3) * NLEAF * NCELL + k * NCELL + q];
+            for (int j = 0; j < S.n3; ++j) v += cx.Lf3[size_t(S.slot3 + j) * NLEAF * NCELL + k * NCELL + q];
             obuf[k][io] = v;
         }
     }

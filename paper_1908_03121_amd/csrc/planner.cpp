@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <unordered_map>
 
 namespace fmmg {
@@ -316,8 +317,38 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
             }
         }
     }
-    for (size_t k = 0; k < P.mp_leaf.size(); ++k) P.subs[size_t(P.mp_leaf[k])].slot3 = int32_t(k);
-    P.n_slot3 = int32_t(P.mp_leaf.size());
+    // class-4 items: each leaf's refined neighbours in slot order, cut after
+    // C4_ITEM_STEPS steps; one Lf3 slot per item, a leaf's slots consecutive
+    {
+        static const std::array<int, 27> steps = [] {
+            std::array<int, 27> k{};
+            StencilTables t;
+            build_stencil_tables(&t);
+            for (int o = 0; o < 27; ++o)
+                for (int g = t.c4_grp_begin[o]; g < t.c4_grp_begin[o + 1]; ++g) k[size_t(o)] += t.c4_grp[g] >> 18;
+            return k;
+        }();
+        P.c4_chunks.clear();
+        int32_t slot = 0;
+        for (int32_t s : P.mp_leaf) {
+            SubDev& S = P.subs[size_t(s)];
+            S.slot3 = slot;
+            int o0 = -1, acc = 0;
+            for (int o = 0; o < 27; ++o) {
+                if (o == 13 || S.nbr[o] < 0 || !(S.nbr[o] & 1)) continue;
+                if (o0 < 0) o0 = o;
+                acc += steps[size_t(o)];
+                if (acc >= C4_ITEM_STEPS) {
+                    P.c4_chunks.push_back({s, o0, o + 1, slot++, acc});
+                    o0 = -1;
+                    acc = 0;
+                }
+            }
+            if (o0 >= 0) P.c4_chunks.push_back({s, o0, 27, slot++, acc});
+            S.n3 = slot - S.slot3;
+        }
+        P.n_slot3 = slot;
+    }
     P.level_ref_begin.assign(size_t(P.max_level) + 2, 0);
     for (int l = 0; l <= P.max_level; ++l) {
         P.level_ref_begin[size_t(l)] = int32_t(P.ref_by_level.size());
@@ -452,20 +483,13 @@ void build_items(HostPlan* Pp, int ngroups, bool split) {
                 all.push_back({Item{IT_MP_REF, s, zt, g | (sw << 3)}, 64.0 * n + 2000.0, S.level});
             }
     }
-    // one class-4 item per leaf with refined neighbours: its cost is its
-    // (target parent, source parent) steps of 64 pairs each, plus the staging
-    // of every refined neighbour's slab
-    int c4_steps[27];
-    for (int o = 0; o < 27; ++o) {
-        c4_steps[o] = 0;
-        for (int g = tab.c4_grp_begin[o]; g < tab.c4_grp_begin[o + 1]; ++g) c4_steps[o] += tab.c4_grp[g] >> 18;
-    }
-    for (int32_t s : P.mp_leaf) {
-        const SubDev& S = P.subs[size_t(s)];
-        double cost = 2000.0;
-        for (int o = 0; o < 27; ++o)
-            if (o != 13 && S.nbr[o] >= 0 && (S.nbr[o] & 1)) cost += 64.0 * 0.65 * c4_steps[o] + 1500.0;
-        all.push_back({Item{IT_MP_LEAF, s, 0, 0}, cost, S.level});
+    // class-4 items: cost of their (target parent, source parent) steps of
+    // 64 pairs each, plus the staging of every refined neighbour's slab
+    for (const HostPlan::C4Chunk& c : P.c4_chunks) {
+        int nn = 0;
+        for (int o = c.o_begin; o < c.o_end; ++o) nn += o != 13 && P.subs[size_t(c.sub)].nbr[o] >= 0 && (P.subs[size_t(c.sub)].nbr[o] & 1);
+        all.push_back({Item{IT_MP_LEAF, c.sub, c.o_begin | (c.o_end << 8), c.slot},
+                       64.0 * 0.65 * c.steps + 1500.0 * nn + 2000.0, P.subs[size_t(c.sub)].level});
     }
     for (int32_t s : P.mono_leaf)
         all.push_back({Item{IT_MONO, s, 0, 0}, 512.0 * 743.0 * 0.025 + 4000.0, P.subs[size_t(s)].level});

@@ -50,7 +50,9 @@ struct HostPlan {
     // l2l_begin[2l+1]), its leaf children [l2l_begin[2l+1], l2l_begin[2l+2])
     std::vector<int32_t> l2l_tasks;
     std::vector<int32_t> l2l_begin;
-    int32_t n_slot3 = 0;               // leaves with refined neighbours (Lf3 slots)
+    int32_t n_slot3 = 0;               // Lf3 slots: one per class-4 item
+    struct C4Chunk { int32_t sub, o_begin, o_end, slot, steps; };
+    std::vector<C4Chunk> c4_chunks;    // class-4 items: a leaf's neighbour slots [o_begin, o_end)
 
     // same-level work items for a given number of plane groups, in two
     // branches: 0 = levels >= split (fine), 1 = levels < split (coarse)
