@@ -914,26 +914,41 @@ __device__ __forceinline__ void mono_class(const P* __restrict__ box, int cbeg, 
         // odd targets' mirrored dz folded into the kernel value); the x and y
         // parts share one column sum, scaled by dx and dy once per column.
         // FP32: all three are column partial sums, flushed to FP64
+        // The kernel values depend on dz^2 only, so canonical offsets +d and
+        // -d (both in the column's range for d <= NP) share them: their masses
+        // enter phi and the column sum as m(+d) + m(-d) and gz as
+        // d (m(+d) - m(-d)), 5 operations for 2 pairs instead of 6.
         constexpr bool F64 = sizeof(P) == 8;
+        constexpr int NP = -LO < LO + N - 1 ? -LO : LO + N - 1;
         P s0[8], s1[8], s2[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) s0[k] = s1[k] = s2[k] = 0;
+        // mp: mass at canonical offset +d (mirrored for odd targets), mq at -d
+        auto add = [&](int k, P a, P b, P cz, P mp, P mq, bool with_z) {
+            s1[k] += mp * b;
+            if (F64) {
+                phi[k] = fmaP(double(mp), double(a), phi[k]);
+                if (with_z) gz[k] = fmaP(double(mq), double((k & 1) ? -cz : cz), gz[k]);
+            } else {
+                s0[k] += mp * a;
+                if (with_z) s2[k] += mq * cz;
+            }
+        };
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             const int dzc = LO + i;  // canonical dz
+            if (dzc < 0 && -dzc <= NP) continue;  // taken with +|dzc|
             P a, b;
             mono_r<P>(rxy + dzc * dzc, a, b);
             const P cz = P(dzc) * b;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const P mm = m[k + ((k & 1) ? -dzc : dzc) - LO];
-                s1[k] += mm * b;
-                if (F64) {
-                    phi[k] = fmaP(double(mm), double(a), phi[k]);
-                    if (dzc != 0) gz[k] = fmaP(double(mm), double((k & 1) ? -cz : cz), gz[k]);
+                const P m1 = m[k + ((k & 1) ? -dzc : dzc) - LO];
+                if (dzc > 0 && dzc <= NP) {
+                    const P m2 = m[k + ((k & 1) ? dzc : -dzc) - LO];
+                    add(k, a, b, cz, m1 + m2, m1 - m2, true);
                 } else {
-                    s0[k] += mm * a;
-                    if (dzc != 0) s2[k] += mm * cz;
+                    add(k, a, b, cz, m1, m1, dzc != 0);
                 }
             }
         }
@@ -1251,6 +1266,7 @@ __device__ __forceinline__ double top_total(const Ctx& cx, const SubDev& T, int 
 // as parents, so this step does not wait for them).
 // Leaf children: phi = own + o0,  g = own - o1 + dg.
 // grid: one block of 512 per task (parent sub-grid * 8 + child slot).
+template <int NG>
 __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__ tasks, int parent_mode,
                                              double* __restrict__ phi, double* __restrict__ gout) {
     __shared__ double obuf[4][NCELL];
@@ -1264,11 +1280,10 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
     const int x = q & 7, y = (q >> 3) & 7, z = q >> 6;
     const int ex = 4 * (e >> 2), ey = 4 * ((e >> 1) & 1), ez = 4 * (e & 1);
     // cooperative fetch of the parent octant: value i = comp * 64 + cell (the
-    // component is uniform over a wave); every load of the three rounds is
-    // issued before the first is used (group partials beyond the plan's
-    // count re-read the last one and are not added)
-    const int ng = cx.ngroups;
-    double v[3], t[3][MAX_GROUPS];
+    // component is uniform over a wave); every load of the three rounds (the
+    // NG plane-group partials of each value included) is issued before the
+    // first is used
+    double v[3], t[3][NG];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         const int i = q + r * NCELL;
@@ -1284,8 +1299,7 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
             const size_t base = (size_t(Ps.idx) * NLOC + k) * NCELL + pq;
             if (parent_mode == PARENT_TOTAL) v[r] = cx.Lr[base];
 #pragma unroll
-            for (int gg = 0; gg < MAX_GROUPS; ++gg)
-                t[r][gg] = cx.Lp[size_t(gg < ng ? gg : ng - 1) * size_t(cx.part_stride) + base];
+            for (int gg = 0; gg < NG; ++gg) t[r][gg] = cx.Lp[size_t(gg) * size_t(cx.part_stride) + base];
         }
     }
 #pragma unroll
@@ -1295,8 +1309,7 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
         const int k = i >> 6;
         if (k < NLOC && parent_mode != PARENT_TOP_PARTS) {
 #pragma unroll
-            for (int gg = 0; gg < MAX_GROUPS; ++gg)
-                if (gg < ng) v[r] += t[r][gg];
+            for (int gg = 0; gg < NG; ++gg) v[r] += t[r][gg];
         }
         par[k][i & 63] = v[r];
     }
@@ -1474,7 +1487,14 @@ int persist_blocks_per_cu(int prec) {
 }
 
 void launch_l2l(const Ctx& a, const int32_t* tasks, int n, int parent_mode, double* phi, double* g) {
-    if (n > 0) hipLaunchKernelGGL(k_l2l, dim3(n), dim3(512), 0, a.st, a, tasks, parent_mode, phi, g);
+    if (n <= 0) return;
+    switch (a.ngroups) {
+        case 1: hipLaunchKernelGGL(k_l2l<1>, dim3(n), dim3(512), 0, a.st, a, tasks, parent_mode, phi, g); break;
+        case 2: hipLaunchKernelGGL(k_l2l<2>, dim3(n), dim3(512), 0, a.st, a, tasks, parent_mode, phi, g); break;
+        case 3: hipLaunchKernelGGL(k_l2l<3>, dim3(n), dim3(512), 0, a.st, a, tasks, parent_mode, phi, g); break;
+        case 4: hipLaunchKernelGGL(k_l2l<4>, dim3(n), dim3(512), 0, a.st, a, tasks, parent_mode, phi, g); break;
+        default: hipLaunchKernelGGL(k_l2l<5>, dim3(n), dim3(512), 0, a.st, a, tasks, parent_mode, phi, g); break;
+    }
 }
 
 void launch_leaf_out(const Ctx& a, const int32_t* list, int n, double* phi, double* g) {
