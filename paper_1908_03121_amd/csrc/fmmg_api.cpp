@@ -462,12 +462,13 @@ int64_t enqueue_solve(fmmg_plan* p, const fmmg_ws& w, const double* rho, double*
 std::string signature(const fmmg_plan* p) {
     std::ostringstream o;
     const HostPlan& hp = p->hp;
-    o << "fmmg1 trees=" << hp.n_trees << " sub=" << hp.subs.size() << " ref=" << hp.ref_sub.size()
+    o << "fmmg2 trees=" << hp.n_trees << " sub=" << hp.subs.size() << " ref=" << hp.ref_sub.size()
       << " leaf=" << hp.leaf_sub.size() << " lev=" << hp.max_level << " k3=" << hp.n_slot3
       << " top=" << (p->opt.top_mode == FMMG_TOP_FULL ? "full" : "stencil")
       << " prec=" << (p->opt.precision == FMMG_MIXED ? "mixed" : p->opt.precision == FMMG_MIXED_F32 ? "mixed_f32" : "fp64")
       << " cu=" << p->n_cu
-      << " split=" << hp.split_natural << " ovl=" << (p->opt.overlap ? 1 : 0);
+      << " split=" << hp.split_natural << " ovl=" << p->opt.overlap
+      << " graph=" << (p->opt.use_graph ? 1 : 0);
     return o.str();
 }
 

@@ -44,6 +44,30 @@ int main(int argc, char** argv) {
             }
             for (int g = 1; g <= MAX_GROUPS; ++g)
                 for (int split = 0; split < 2; ++split) build_items(&hp, g, split != 0);
+            // class-4 items: each leaf's refined neighbours covered exactly
+            // once, in slot order, by its own consecutive Lf3 slots
+            std::vector<int> covered(hp.subs.size() * 27, 0);
+            int32_t next_slot = 0;
+            for (const HostPlan::C4Chunk& c : hp.c4_chunks) {
+                const SubDev& S = hp.subs[size_t(c.sub)];
+                if (c.slot != next_slot++ || c.slot < S.slot3 || c.slot >= S.slot3 + S.n3 || c.o_begin < 0 ||
+                    c.o_end > 27 || c.o_begin >= c.o_end) {
+                    printf("%s class-4 chunk slots wrong\n", name);
+                    return 1;
+                }
+                for (int o = c.o_begin; o < c.o_end; ++o)  // the item visits only refined neighbours
+                    if (o != 13 && S.nbr[o] >= 0 && (S.nbr[o] & 1)) covered[size_t(c.sub) * 27 + size_t(o)]++;
+            }
+            if (next_slot != hp.n_slot3) { printf("%s class-4 slot count wrong\n", name); return 1; }
+            for (size_t s = 0; s < hp.subs.size(); ++s)
+                for (int o = 0; o < 27; ++o) {
+                    const SubDev& S = hp.subs[s];
+                    const bool want = S.kind == 0 && S.n3 > 0 && o != 13 && S.nbr[o] >= 0 && (S.nbr[o] & 1);
+                    if (covered[s * 27 + size_t(o)] != (want ? 1 : 0)) {
+                        printf("%s class-4 neighbour coverage wrong\n", name);
+                        return 1;
+                    }
+                }
             printf("%s %d %zu %zu %lld %lld %lld %lld %lld\n", name, top_full, hp.leaf_sub.size(),
                    hp.ref_sub.size(), (long long)hp.counts.cls[0], (long long)hp.counts.cls[1],
                    (long long)hp.counts.cls[2], (long long)hp.counts.cls[3], (long long)hp.counts.top);

@@ -645,7 +645,7 @@ def test_autotune_picks_a_shape_and_caches_it(tmp_path):
     with open(cache) as f:
         tab = json.load(f)
     assert len(tab) == 1
-    with fm.Plan([t], autotune=True, tuning_cache=cache) as p2:
+    with fm.Plan([t], autotune=True, tuning_cache=cache, use_graph=True) as p2:
         phi2, g2 = p2.solve(r)
         torch.cuda.synchronize()
         sh2 = p2.launch_shape()
@@ -653,6 +653,16 @@ def test_autotune_picks_a_shape_and_caches_it(tmp_path):
     for k in ("persistent", "plane_groups", "blocks_per_cu", "overlap", "split_level"):
         assert sh2[k] == sh[k]
     assert max(field_errors(phi2.cpu().numpy(), g2.cpu().numpy(), pr, gr)) < TOL64
+    # shapes timed as graph replays, or with a larger overlap allowance, are
+    # not reused by an eager plan or one that allows less overlap
+    for kw in (dict(use_graph=False), dict(use_graph=True, overlap=0)):
+        with fm.Plan([t], autotune=True, tuning_cache=cache, **kw) as p3:
+            p3.solve(r)
+            torch.cuda.synchronize()
+            sh3 = p3.launch_shape()
+        assert sh3["from_cache"] == 0 and sh3["overlap"] <= kw.get("overlap", 1)
+    with open(cache) as f:
+        assert len(json.load(f)) == 3
 
 
 def test_stage_timing_counts_launches():
