@@ -140,7 +140,7 @@ struct StencilTables {
     int32_t c4_slab[27];
     int32_t c4_grp_begin[28];
     int32_t c4_grp[C4_MAX_GROUPS];
-    int16_t c4_task[C4_MAX_TASKS];
+    int32_t c4_task[C4_MAX_TASKS];  // 32-bit: the wave-uniform index is a scalar load
 };
 
 // Top-level (all pairs) tile: 64 target cells (plane zt of sub-grid target)

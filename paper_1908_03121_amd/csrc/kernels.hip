@@ -825,13 +825,19 @@ __device__ __forceinline__ void c4_item(const Ctx& cx, int sid, int o0, int o1, 
             const int tx = 2 * (pt >> 4) + (tc >> 2), ty = 2 * ((pt >> 2) & 3) + ((tc >> 1) & 1);
             const int tz = 2 * (pt & 3) + (tc & 1);
             const P X0 = P(h * tx), Y0 = P(h * ty), Z0 = P(h * tz);
-            Acc<double> acc;
+            // two steps per iteration, each into its own sums: two
+            // independent dependency chains per wave
+            Acc<double> acc, acc2;
             acc.zero();
-            Acc<PA> part_store;
+            acc2.zero();
+            Acc<PA> part_store, part2_store;
             Acc<PA>& part = PR != PR_F64 ? part_store : *reinterpret_cast<Acc<PA>*>(&acc);
-            if (PR != PR_F64) part.zero();
-            for (int k = first; k < first + cnt; ++k) {
-                const int sp = c_tab.c4_task[k];
+            Acc<PA>& part2 = PR != PR_F64 ? part2_store : *reinterpret_cast<Acc<PA>*>(&acc2);
+            if (PR != PR_F64) {
+                part.zero();
+                part2.zero();
+            }
+            auto step = [&](int sp, Acc<double>& ac, Acc<PA>& pa) {
                 const unsigned char* cs = smem + (sp * 8 + c) * 16;
                 P src[NREC];
 #pragma unroll
@@ -841,9 +847,21 @@ __device__ __forceinline__ void c4_item(const Ctx& cx, int sid, int o0, int o1, 
 #pragma unroll
                     for (int i = 0; i < V; ++i) src[j * V + i] = pp[i];
                 }
-                pair_any<false, PR>(X0 - src[R_DX], Y0 - src[R_DY], Z0 - src[R_DZ], src, oa, acc, part);
+                pair_any<false, PR>(X0 - src[R_DX], Y0 - src[R_DY], Z0 - src[R_DZ], src, oa, ac, pa);
+            };
+            const int kend = first + cnt;
+            int k = first;
+            for (; k + 1 < kend; k += 2) {
+                const int sp0 = c_tab.c4_task[k], sp1 = c_tab.c4_task[k + 1];
+                step(sp0, acc, part);
+                step(sp1, acc2, part2);
             }
-            if (PR != PR_F64) acc.add(part, false, PR == PR_F32);
+            if (k < kend) step(c_tab.c4_task[k], acc, part);
+            if (PR != PR_F64) {
+                acc.add(part, false, PR == PR_F32);
+                acc.add(part2, false, PR == PR_F32);
+            }
+            acc.add(acc2, false);
             // the 8 source-child sums of each target, added across lanes
             double v[7] = {acc.l0, acc.l1[0], acc.l1[1], acc.l1[2], acc.s[0], acc.s[1], acc.s[2]};
 #pragma unroll

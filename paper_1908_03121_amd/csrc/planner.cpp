@@ -138,7 +138,7 @@ static void build_c4_tables(StencilTables* t) {
         std::stable_sort(grp.begin(), grp.end(), [](const Grp& a, const Grp& b) { return a.src.size() > b.src.size(); });
         for (const Grp& g : grp) {
             t->c4_grp[ng++] = g.pt | (nt << 6) | (int(g.src.size()) << 18);
-            for (int sp : g.src) t->c4_task[nt++] = int16_t(sp);
+            for (int sp : g.src) t->c4_task[nt++] = sp;
         }
     }
     t->c4_grp_begin[27] = ng;
