@@ -315,9 +315,12 @@ int64_t enqueue_solve(fmmg_plan* p, const fmmg_ws& w, const double* rho, double*
     };
     auto cnt = [&](int n) { if (n > 0) per[stage] += 1; };
     auto m2m = [&](const Ctx& x, int l) {
-        int b = hp.level_ref_begin[size_t(l)], e = hp.level_ref_begin[size_t(l) + 1];
-        launch_m2m(x, p->d_ref_by_level + b, e - b);
-        cnt(e - b);
+        const int b = hp.level_ref_begin[size_t(l)], m = hp.level_leafpar_end[size_t(l)],
+                  e = hp.level_ref_begin[size_t(l) + 1];
+        launch_m2m_leafpar(x, p->d_ref_by_level + b, m - b);
+        cnt(m - b);
+        launch_m2m(x, p->d_ref_by_level + m, e - m);
+        cnt(e - m);
     };
     const int kinds[IT_KINDS] = {IT_TOP, IT_MONO, IT_MP_REF, IT_MP_LEAF};
     auto one_class = [&](const Ctx& x, int br, int k) {

@@ -303,6 +303,101 @@ __global__ __launch_bounds__(512) void k_p2m_top(Ctx cx, const int32_t* __restri
     cx.mass[size_t(S.idx) * NCELL + q] = v * (h * h * h);
 }
 
+// The summed contributions v (m, S1, S2 in xx yy zz xy xz yz, S3 in xxx xxy
+// xxz xyy xyz xzz yyy yyz yzz zzz, all about the parent cell centre) moved to
+// the COM offset d = S1/m and stored trace-free as the record at out (stride
+// NCELL per component).
+__device__ __forceinline__ void m2m_store(double (&v)[20], double* out) {
+    const double m = v[0];
+    double ox = 0, oy = 0, oz = 0;
+    if (m > 0) {
+        const double im = 1.0 / m;
+        ox = v[1] * im;
+        oy = v[2] * im;
+        oz = v[3] * im;
+    }
+    double* p2 = v + 4;    // xx yy zz xy xz yz
+    double* p3 = v + 10;   // xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz
+    // shift to the COM: M3 = S3 - sym(S2 d) + 2 m d d d (S2 before its shift)
+    const double m2 = 2 * m;
+    p3[0] += -3 * p2[0] * ox + m2 * ox * ox * ox;
+    p3[1] += -(p2[0] * oy + 2 * p2[3] * ox) + m2 * ox * ox * oy;
+    p3[2] += -(p2[0] * oz + 2 * p2[4] * ox) + m2 * ox * ox * oz;
+    p3[3] += -(2 * p2[3] * oy + p2[1] * ox) + m2 * ox * oy * oy;
+    p3[4] += -(p2[3] * oz + p2[4] * oy + p2[5] * ox) + m2 * ox * oy * oz;
+    p3[5] += -(2 * p2[4] * oz + p2[2] * ox) + m2 * ox * oz * oz;
+    p3[6] += -3 * p2[1] * oy + m2 * oy * oy * oy;
+    p3[7] += -(p2[1] * oz + 2 * p2[5] * oy) + m2 * oy * oy * oz;
+    p3[8] += -(2 * p2[5] * oz + p2[2] * oy) + m2 * oy * oz * oz;
+    p3[9] += -3 * p2[2] * oz + m2 * oz * oz * oz;
+    p2[0] -= m * ox * ox;
+    p2[1] -= m * oy * oy;
+    p2[2] -= m * oz * oz;
+    p2[3] -= m * ox * oy;
+    p2[4] -= m * ox * oz;
+    p2[5] -= m * oy * oz;
+    const double tr = (p2[0] + p2[1] + p2[2]) * (1.0 / 3.0);
+    const double tx = p3[0] + p3[3] + p3[5];
+    const double ty = p3[1] + p3[6] + p3[8];
+    const double tz = p3[2] + p3[7] + p3[9];
+    out[R_M * NCELL] = m;
+    out[R_DX * NCELL] = ox;
+    out[R_DY * NCELL] = oy;
+    out[R_DZ * NCELL] = oz;
+    out[(R_Q + 0) * NCELL] = p2[0] - tr;
+    out[(R_Q + 1) * NCELL] = p2[1] - tr;
+    out[(R_Q + 2) * NCELL] = p2[3];
+    out[(R_Q + 3) * NCELL] = p2[4];
+    out[(R_Q + 4) * NCELL] = p2[5];
+    out[(R_O + 0) * NCELL] = p3[0] - 0.6 * tx;
+    out[(R_O + 1) * NCELL] = p3[1] - 0.2 * ty;
+    out[(R_O + 2) * NCELL] = p3[2] - 0.2 * tz;
+    out[(R_O + 3) * NCELL] = p3[3] - 0.2 * tx;
+    out[(R_O + 4) * NCELL] = p3[4];
+    out[(R_O + 5) * NCELL] = p3[6] - 0.6 * ty;
+    out[(R_O + 6) * NCELL] = p3[7] - 0.2 * tz;
+}
+
+// Sums of the 8 point masses mc[i][j][k] at offsets s a (s in {-1, 1}^3,
+// component s_x = 2i - 1 etc., a = h/2) from their parent cell centre, as
+// the contributions v of the upward step: with M, S_i = sum s_i m,
+// S_ij = sum s_i s_j m (i != j), S_xyz, the first moments are a S_i, the
+// second a^2 M (diagonal) and a^2 S_ij, the third a^3 S_i (xxx, xyy, xzz ...)
+// and a^3 S_xyz (xyz).
+__device__ __forceinline__ void leaf_octet(const double (&mc)[2][2][2], double hc, double (&v)[20]) {
+    double p[2][2], d[2][2];  // along z: sum and difference
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            p[i][j] = mc[i][j][1] + mc[i][j][0];
+            d[i][j] = mc[i][j][1] - mc[i][j][0];
+        }
+    double pp[2], pd[2], dp[2], dd[2];  // then along y
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        pp[i] = p[i][1] + p[i][0];
+        pd[i] = p[i][1] - p[i][0];
+        dp[i] = d[i][1] + d[i][0];
+        dd[i] = d[i][1] - d[i][0];
+    }
+    const double M = pp[1] + pp[0], Sx = pp[1] - pp[0], Sy = pd[1] + pd[0], Sxy = pd[1] - pd[0];
+    const double Sz = dp[1] + dp[0], Sxz = dp[1] - dp[0], Syz = dd[1] + dd[0], Sxyz = dd[1] - dd[0];
+    const double a1 = 0.5 * hc, a2 = a1 * a1, a3 = a2 * a1;
+    v[0] = M;
+    v[1] = a1 * Sx;
+    v[2] = a1 * Sy;
+    v[3] = a1 * Sz;
+    v[4] = v[5] = v[6] = a2 * M;
+    v[7] = a2 * Sxy;
+    v[8] = a2 * Sxz;
+    v[9] = a2 * Syz;
+    v[10] = v[13] = v[15] = a3 * Sx;  // xxx, xyy, xzz
+    v[11] = v[16] = v[18] = a3 * Sy;  // xxy, yyy, yzz
+    v[12] = v[17] = v[19] = a3 * Sz;  // xxz, yyz, zzz
+    v[14] = a3 * Sxyz;
+}
+
 // One octant of a refined sub-grid's cells from the 512 cells of one child
 // sub-grid (leaf: point masses m = rho h^3 at the cell centres, also stored
 // for the same-level step; refined: their records).  The contribution of a
@@ -353,37 +448,7 @@ __global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__
                     const int io = ((x + i) * NS + (y + j)) * NS + (z + k);
                     mc[i][j][k] = rin[io + (io >> 3)] * h3;
                 }
-        double p[2][2], d[2][2];  // along z: sum and difference
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                p[i][j] = mc[i][j][1] + mc[i][j][0];
-                d[i][j] = mc[i][j][1] - mc[i][j][0];
-            }
-        double pp[2], pd[2], dp[2], dd[2];  // then along y
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            pp[i] = p[i][1] + p[i][0];
-            pd[i] = p[i][1] - p[i][0];
-            dp[i] = d[i][1] + d[i][0];
-            dd[i] = d[i][1] - d[i][0];
-        }
-        const double M = pp[1] + pp[0], Sx = pp[1] - pp[0], Sy = pd[1] + pd[0], Sxy = pd[1] - pd[0];
-        const double Sz = dp[1] + dp[0], Sxz = dp[1] - dp[0], Syz = dd[1] + dd[0], Sxyz = dd[1] - dd[0];
-        const double a1 = 0.5 * hc, a2 = a1 * a1, a3 = a2 * a1;
-        v[0] = M;
-        v[1] = a1 * Sx;
-        v[2] = a1 * Sy;
-        v[3] = a1 * Sz;
-        v[4] = v[5] = v[6] = a2 * M;
-        v[7] = a2 * Sxy;
-        v[8] = a2 * Sxz;
-        v[9] = a2 * Syz;
-        v[10] = v[13] = v[15] = a3 * Sx;  // xxx, xyy, xzz
-        v[11] = v[16] = v[18] = a3 * Sy;  // xxy, yyy, yzz
-        v[12] = v[17] = v[19] = a3 * Sz;  // xxz, yyz, zzz
-        v[14] = a3 * Sxyz;
+        leaf_octet(mc, hc, v);
     } else {
         const double* r = cx.rec + size_t(Cs.idx) * NREC * NCELL + q;
         const double w = r[R_M * NCELL];
@@ -432,57 +497,56 @@ __global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__
 #pragma unroll
         for (int k = 0; k < 20; ++k) v[k] += red[z >> 1][pc][k];
     }
-    const double m = v[0];
-    double ox = 0, oy = 0, oz = 0;
-    if (m > 0) {
-        const double im = 1.0 / m;
-        ox = v[1] * im;
-        oy = v[2] * im;
-        oz = v[3] * im;
-    }
-    double* p2 = v + 4;    // xx yy zz xy xz yz
-    double* p3 = v + 10;   // xxx xxy xxz xyy xyz xzz yyy yyz yzz zzz
-    // shift to the COM: M3 = S3 - sym(S2 d) + 2 m d d d (S2 before its shift)
-    const double m2 = 2 * m;
-    p3[0] += -3 * p2[0] * ox + m2 * ox * ox * ox;
-    p3[1] += -(p2[0] * oy + 2 * p2[3] * ox) + m2 * ox * ox * oy;
-    p3[2] += -(p2[0] * oz + 2 * p2[4] * ox) + m2 * ox * ox * oz;
-    p3[3] += -(2 * p2[3] * oy + p2[1] * ox) + m2 * ox * oy * oy;
-    p3[4] += -(p2[3] * oz + p2[4] * oy + p2[5] * ox) + m2 * ox * oy * oz;
-    p3[5] += -(2 * p2[4] * oz + p2[2] * ox) + m2 * ox * oz * oz;
-    p3[6] += -3 * p2[1] * oy + m2 * oy * oy * oy;
-    p3[7] += -(p2[1] * oz + 2 * p2[5] * oy) + m2 * oy * oy * oz;
-    p3[8] += -(2 * p2[5] * oz + p2[2] * oy) + m2 * oy * oz * oz;
-    p3[9] += -3 * p2[2] * oz + m2 * oz * oz * oz;
-    p2[0] -= m * ox * ox;
-    p2[1] -= m * oy * oy;
-    p2[2] -= m * oz * oz;
-    p2[3] -= m * ox * oy;
-    p2[4] -= m * ox * oz;
-    p2[5] -= m * oy * oz;
-    const double tr = (p2[0] + p2[1] + p2[2]) * (1.0 / 3.0);
-    const double tx = p3[0] + p3[3] + p3[5];
-    const double ty = p3[1] + p3[6] + p3[8];
-    const double tz = p3[2] + p3[7] + p3[9];
     const int ex = e >> 2, ey = (e >> 1) & 1, ez = e & 1;
     const int pq = ((4 * ez + (z >> 1)) * NS + (4 * ey + (y >> 1))) * NS + (4 * ex + (x >> 1));
-    double* out = cx.rec + size_t(Ps.idx) * NREC * NCELL + pq;
-    out[R_M * NCELL] = m;
-    out[R_DX * NCELL] = ox;
-    out[R_DY * NCELL] = oy;
-    out[R_DZ * NCELL] = oz;
-    out[(R_Q + 0) * NCELL] = p2[0] - tr;
-    out[(R_Q + 1) * NCELL] = p2[1] - tr;
-    out[(R_Q + 2) * NCELL] = p2[3];
-    out[(R_Q + 3) * NCELL] = p2[4];
-    out[(R_Q + 4) * NCELL] = p2[5];
-    out[(R_O + 0) * NCELL] = p3[0] - 0.6 * tx;
-    out[(R_O + 1) * NCELL] = p3[1] - 0.2 * ty;
-    out[(R_O + 2) * NCELL] = p3[2] - 0.2 * tz;
-    out[(R_O + 3) * NCELL] = p3[3] - 0.2 * tx;
-    out[(R_O + 4) * NCELL] = p3[4];
-    out[(R_O + 5) * NCELL] = p3[6] - 0.6 * ty;
-    out[(R_O + 6) * NCELL] = p3[7] - 0.2 * tz;
+    m2m_store(v, cx.rec + size_t(Ps.idx) * NREC * NCELL + pq);
+}
+
+// A refined sub-grid whose 8 children are all leaves: one block per parent.
+// The 8 children's densities are staged in LDS with coalesced loads (each
+// thread issues its 8 loads at once), their masses written in the internal
+// order, and each thread forms one parent cell from its 8 point masses, so
+// that the record is written whole (coalesced per component).
+// grid: (such parents of the level), 512 threads.
+__global__ __launch_bounds__(512) void k_m2m_leafpar(Ctx cx, const int32_t* __restrict__ list) {
+    __shared__ double rin[8][NCELL + NCELL / 8];  // per child, I/O order, one pad per z-row
+    const SubDev& Ps = cx.subs[list[blockIdx.x]];
+    const int q = threadIdx.x;
+    double rv[8];
+    size_t cb[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        cb[e] = size_t(cx.subs[Ps.child[e]].idx) * NCELL;
+        rv[e] = cx.rho[cb[e] + q];  // coalesced
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        check_rho(cx, rv[e], cb[e] + q, true);
+        rin[e][q + (q >> 3)] = rv[e];
+    }
+    __syncthreads();
+    const double hc = 0.5 * Ps.h, h3 = hc * hc * hc;
+    const int io = io_index(q);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) cx.mass[cb[e] + q] = rin[e][io + (io >> 3)] * h3;
+    // parent cell q = (z*8 + y)*8 + x: child sub-grid e = (x/4, y/4, z/4),
+    // children at (2 (x%4) + i, 2 (y%4) + j, 2 (z%4) + k) in it
+    const int x = q & 7, y = (q >> 3) & 7, z = q >> 6;
+    const int e = (x >> 2) * 4 + (y >> 2) * 2 + (z >> 2);
+    const int cx0 = 2 * (x & 3), cy0 = 2 * (y & 3), cz0 = 2 * (z & 3);
+    double mc[2][2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int ic = ((cx0 + i) * NS + (cy0 + j)) * NS + (cz0 + k);
+                mc[i][j][k] = rin[e][ic + (ic >> 3)] * h3;
+            }
+    double v[20];
+    leaf_octet(mc, hc, v);
+    m2m_store(v, cx.rec + size_t(Ps.idx) * NREC * NCELL + q);
 }
 
 // ---------------------------------------------------------------------------
@@ -1467,6 +1531,10 @@ void launch_p2m_top(const Ctx& a, const int32_t* list, int n) {
 
 void launch_m2m(const Ctx& a, const int32_t* list, int n) {
     if (n > 0) hipLaunchKernelGGL(k_m2m, dim3(n * 8), dim3(512), 0, a.st, a, list);
+}
+
+void launch_m2m_leafpar(const Ctx& a, const int32_t* list, int n) {
+    if (n > 0) hipLaunchKernelGGL(k_m2m_leafpar, dim3(n), dim3(512), 0, a.st, a, list);
 }
 
 template <int K>

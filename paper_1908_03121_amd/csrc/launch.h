@@ -45,6 +45,8 @@ enum { PARENT_TOTAL = 0, PARENT_TOP_PARTS = 1, PARENT_OWN_PARTS = 2 };
 hipError_t upload_tables(const StencilTables* t, hipStream_t st);
 void launch_p2m_top(const Ctx& a, const int32_t* list, int n);
 void launch_m2m(const Ctx& a, const int32_t* list, int n);
+// parents whose 8 children are all leaves: one block per parent
+void launch_m2m_leafpar(const Ctx& a, const int32_t* list, int n);
 void launch_class(const Ctx& a, int kind, const Item* items, int n);
 // ctr: two ints, zero before the first launch and re-armed by each launch
 void launch_persist(const Ctx& a, const Item* items, int n, int grid, int* ctr);

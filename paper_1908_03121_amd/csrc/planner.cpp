@@ -349,11 +349,22 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
         }
         P.n_slot3 = slot;
     }
+    // refined sub-grids level by level; within a level, those whose 8
+    // children are all leaves first (their upward step has its own kernel)
     P.level_ref_begin.assign(size_t(P.max_level) + 2, 0);
+    P.level_leafpar_end.assign(size_t(P.max_level) + 1, 0);
     for (int l = 0; l <= P.max_level; ++l) {
         P.level_ref_begin[size_t(l)] = int32_t(P.ref_by_level.size());
-        for (int32_t s : P.ref_sub)
-            if (P.subs[size_t(s)].level == l) P.ref_by_level.push_back(s);
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int32_t s : P.ref_sub) {
+                const SubDev& S = P.subs[size_t(s)];
+                if (S.level != l) continue;
+                bool leaves = true;
+                for (int e = 0; e < 8; ++e) leaves &= P.subs[size_t(S.child[e])].kind == 0;
+                if (leaves == (pass == 0)) P.ref_by_level.push_back(s);
+            }
+            if (pass == 0) P.level_leafpar_end[size_t(l)] = int32_t(P.ref_by_level.size());
+        }
     }
     P.level_ref_begin[size_t(P.max_level) + 1] = int32_t(P.ref_by_level.size());
     P.level_leaves.assign(size_t(P.max_level) + 1, 0);

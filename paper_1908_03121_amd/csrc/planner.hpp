@@ -43,6 +43,8 @@ struct HostPlan {
     std::vector<int32_t> mp_leaf;      // leaf targets with a refined neighbour
     std::vector<int32_t> level_ref_begin;  // refined sub ids sorted by level: [l, l+1)
     std::vector<int32_t> ref_by_level;
+    std::vector<int32_t> level_leafpar_end;  // level l's parents with 8 leaf children:
+                                             // [level_ref_begin[l], level_leafpar_end[l])
     std::vector<int32_t> top_leaf;     // top-level leaves (output straight from own terms)
     std::vector<int32_t> level_leaves; // number of leaf sub-grids per level
     // downward tasks, parent sub id * 8 + child slot, grouped by parent level
