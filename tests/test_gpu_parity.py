@@ -332,6 +332,27 @@ def test_c4_batch_every_tree_every_cell(k):
         check_form("c4", prec, errs, f, tq)
 
 
+def test_four_copies_of_the_batch_reproduce_it_bitwise():
+    """64 trees in one plan (4 copies of the 16-tree batch, 122,928 leaf
+    sub-grids, 4x the benchmark's size) in the persistent shape: every
+    copy's potential and acceleration are bitwise those of the 16-tree plan
+    (no item's arithmetic depends on another tree or on its position in the
+    work list)."""
+    W = c4_workload()
+    kw = dict(persistent=True, plane_groups=1, blocks_per_cu=3, overlap=0)
+    phi1, g1, st1 = run(W.trees, W.rho, **kw)
+    rho4 = np.concatenate([W.rho] * 4)
+    phi4, g4, st4 = run(W.trees * 4, rho4, **kw)
+    n = W.n_leaves
+    print(f"  {st4['n_trees']} trees, {st4['n_leaves']} leaves, {sum(st4['pairs']) + st4['pairs_top']} pairs",
+          flush=True)
+    assert st4["n_trees"] == 64 and st4["n_leaves"] == 4 * n
+    assert sum(st4["pairs"]) == 4 * sum(st1["pairs"])
+    for c in range(4):
+        assert np.array_equal(phi4[c * n:(c + 1) * n], phi1), c
+        assert np.array_equal(g4[c * n:(c + 1) * n], g1), c
+
+
 def test_zero_density_regions():
     """Cells without mass: their centre is their centre of mass and they act
     on nothing; an all-zero field gives exactly zero."""
