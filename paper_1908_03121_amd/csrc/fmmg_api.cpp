@@ -92,7 +92,8 @@ constexpr int MAX_LAUNCH_STREAMS = 128;  // stream pool of the per-sub-grid laun
 // Per-solve device workspaces of a plan.
 struct fmmg_ws {
     double* mass = nullptr;   // [n_leaf][512]
-    double* rec = nullptr;    // [n_ref][16][512]
+    double* rec = nullptr;    // [n_ref][512][16]
+    double* com = nullptr;    // [n_ref][3][512]
     double* Lp = nullptr;     // [groups][n_ref][19][512]
     double* Lr = nullptr;     // [n_ref][19][512]
     double* Lf = nullptr;     // [n_leaf][4][512]
@@ -168,7 +169,7 @@ void release(fmmg_plan* p) {
     drop_graph(p);
     void* bufs[] = {p->d_subs, p->d_leaf_sub, p->d_ref_by_level, p->d_top_leaf, p->d_l2l_tasks,
                     p->d_top_src, p->d_top_items, p->d_top_reduce, p->d_items_class, p->d_items_lpt,
-                    p->ws.counter, p->ws.mass, p->ws.rec, p->ws.Lp, p->ws.Lr, p->ws.Lf, p->ws.Lf3,
+                    p->ws.counter, p->ws.mass, p->ws.rec, p->ws.com, p->ws.Lp, p->ws.Lr, p->ws.Lf, p->ws.Lf3,
                     p->ws.part, p->d_bad, p->d_rho_bad};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -196,6 +197,8 @@ Ctx make_ctx(const fmmg_plan* p, const fmmg_ws& w, hipStream_t st) {
     a.leaf_sub = p->d_leaf_sub;
     a.mass = w.mass;
     a.rec = w.rec;
+    a.com = w.com;
+    a.rec_zero = int64_t(p->hp.ref_sub.size()) * NCELL;
     a.Lp = w.Lp;
     a.Lr = w.Lr;
     a.Lf = w.Lf;
@@ -771,7 +774,8 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         size_t nl = hp.leaf_sub.size(), nr = hp.ref_sub.size();
 #define AL(dst, n, what) if ((s = dev_alloc(&(dst), (n), what)) != FMMG_OK) { release(p); return s; }
         AL(p->ws.mass, nl * NCELL, "leaf masses");
-        AL(p->ws.rec, nr * NREC * NCELL, "multipole records");
+        AL(p->ws.rec, (nr * NCELL + 1) * NREC, "multipole records");  // + one zero record
+        AL(p->ws.com, nr * 3 * NCELL, "centre-of-mass offsets");
         AL(p->ws.Lp, size_t(p->max_groups) * nr * NLOC * NCELL, "refined own terms");
         AL(p->ws.Lr, nr * NLOC * NCELL, "refined expansions");
         AL(p->ws.Lf, nl * NLEAF * NCELL, "leaf terms");
@@ -782,6 +786,10 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         if (e != hipSuccess) { release(p); return fail(FMMG_ENOMEM, "hipMalloc counter"); }
         e = hipMemsetAsync(p->ws.counter, 0, 4 * sizeof(int), st);
         if (e != hipSuccess) { release(p); return hip_fail(e, "counter clear"); }
+        // the zero record after the last refined cell (read for leaf and
+        // absent source cells when a plane window is staged)
+        e = hipMemsetAsync(p->ws.rec + nr * NCELL * NREC, 0, NREC * sizeof(double), st);
+        if (e != hipSuccess) { release(p); return hip_fail(e, "zero record clear"); }
         // the solves' density flag and the pinned host word it is handed to
         e = hipMalloc(reinterpret_cast<void**>(&p->d_rho_bad), sizeof(unsigned long long));
         if (e != hipSuccess) { release(p); return fail(FMMG_ENOMEM, "hipMalloc density flag"); }

@@ -5,10 +5,15 @@
 // q = (z*8 + y)*8 + x inside a sub-grid, x fastest, so that a z-plane of a
 // sub-grid is 64 contiguous values):
 //   mass [n_leaf][512]            leaf cell masses m = rho h^3
-//   rec  [n_ref][16][512]         refined cells: m, COM offset from the cell
+//   rec  [n_ref][512][16]         refined cells, 16 contiguous values per
+//                                 cell (read and written as 8 16-byte
+//                                 groups): m, COM offset from the cell
 //                                 centre (3), trace-free quadrupole (5:
 //                                 xx yy xy xz yz), trace-free octupole
 //                                 (7: xxx xxy xxz xyy xyz yyy yyz)
+//                                 followed by one all-zero record
+//   com  [n_ref][3][512]          the COM offsets again, component-major,
+//                                 for the downward pass
 //   Lp   [groups][n_ref][19][512] refined cells' own (same-level) Taylor
 //                                 coefficients, one partial per group of
 //                                 source planes: L0, L1 (3), trace-free L2 (5),

@@ -73,6 +73,18 @@ __device__ __forceinline__ int io_index(int q) {
     return (x * 8 + y) * 8 + z;
 }
 
+// The 16 record values of refined cell `cell` (refined index * 512 + cell
+// index): 8 16-byte loads from one address.
+__device__ __forceinline__ void load_rec(const double* __restrict__ rec, size_t cell, double (&v)[NREC]) {
+    const double2* p = reinterpret_cast<const double2*>(rec + cell * NREC);
+#pragma unroll
+    for (int j = 0; j < NREC / 2; ++j) {
+        const double2 t = p[j];
+        v[2 * j] = t.x;
+        v[2 * j + 1] = t.y;
+    }
+}
+
 // Accumulators of one target cell.  Refined targets carry all 19 components
 // (L2 as its trace-free parts xx yy xy xz yz plus the running trace term
 // mb*d1 that both diagonal parts share); leaf targets only L0, L1 and the
@@ -305,9 +317,9 @@ __global__ __launch_bounds__(512) void k_p2m_top(Ctx cx, const int32_t* __restri
 
 // The summed contributions v (m, S1, S2 in xx yy zz xy xz yz, S3 in xxx xxy
 // xxz xyy xyz xzz yyy yyz yzz zzz, all about the parent cell centre) moved to
-// the COM offset d = S1/m and stored trace-free as the record at out (stride
-// NCELL per component).
-__device__ __forceinline__ void m2m_store(double (&v)[20], double* out) {
+// the COM offset d = S1/m and stored trace-free as the record at out (16
+// contiguous values), the COM offset also at com (stride NCELL per axis).
+__device__ __forceinline__ void m2m_store(double (&v)[20], double* out, double* com) {
     const double m = v[0];
     double ox = 0, oy = 0, oz = 0;
     if (m > 0) {
@@ -340,22 +352,29 @@ __device__ __forceinline__ void m2m_store(double (&v)[20], double* out) {
     const double tx = p3[0] + p3[3] + p3[5];
     const double ty = p3[1] + p3[6] + p3[8];
     const double tz = p3[2] + p3[7] + p3[9];
-    out[R_M * NCELL] = m;
-    out[R_DX * NCELL] = ox;
-    out[R_DY * NCELL] = oy;
-    out[R_DZ * NCELL] = oz;
-    out[(R_Q + 0) * NCELL] = p2[0] - tr;
-    out[(R_Q + 1) * NCELL] = p2[1] - tr;
-    out[(R_Q + 2) * NCELL] = p2[3];
-    out[(R_Q + 3) * NCELL] = p2[4];
-    out[(R_Q + 4) * NCELL] = p2[5];
-    out[(R_O + 0) * NCELL] = p3[0] - 0.6 * tx;
-    out[(R_O + 1) * NCELL] = p3[1] - 0.2 * ty;
-    out[(R_O + 2) * NCELL] = p3[2] - 0.2 * tz;
-    out[(R_O + 3) * NCELL] = p3[3] - 0.2 * tx;
-    out[(R_O + 4) * NCELL] = p3[4];
-    out[(R_O + 5) * NCELL] = p3[6] - 0.6 * ty;
-    out[(R_O + 6) * NCELL] = p3[7] - 0.2 * tz;
+    double w[NREC];
+    w[R_M] = m;
+    w[R_DX] = ox;
+    w[R_DY] = oy;
+    w[R_DZ] = oz;
+    w[R_Q + 0] = p2[0] - tr;
+    w[R_Q + 1] = p2[1] - tr;
+    w[R_Q + 2] = p2[3];
+    w[R_Q + 3] = p2[4];
+    w[R_Q + 4] = p2[5];
+    w[R_O + 0] = p3[0] - 0.6 * tx;
+    w[R_O + 1] = p3[1] - 0.2 * ty;
+    w[R_O + 2] = p3[2] - 0.2 * tz;
+    w[R_O + 3] = p3[3] - 0.2 * tx;
+    w[R_O + 4] = p3[4];
+    w[R_O + 5] = p3[6] - 0.6 * ty;
+    w[R_O + 6] = p3[7] - 0.2 * tz;
+    double2* o2 = reinterpret_cast<double2*>(out);
+#pragma unroll
+    for (int j = 0; j < NREC / 2; ++j) o2[j] = make_double2(w[2 * j], w[2 * j + 1]);
+    com[0] = ox;
+    com[NCELL] = oy;
+    com[2 * NCELL] = oz;
 }
 
 // Sums of the 8 point masses mc[i][j][k] at offsets s a (s in {-1, 1}^3,
@@ -450,14 +469,15 @@ __global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__
                 }
         leaf_octet(mc, hc, v);
     } else {
-        const double* r = cx.rec + size_t(Cs.idx) * NREC * NCELL + q;
-        const double w = r[R_M * NCELL];
-        const double dx = r[R_DX * NCELL], dy = r[R_DY * NCELL], dz = r[R_DZ * NCELL];
-        const double qxx = r[(R_Q + 0) * NCELL], qyy = r[(R_Q + 1) * NCELL], qxy = r[(R_Q + 2) * NCELL];
-        const double qxz = r[(R_Q + 3) * NCELL], qyz = r[(R_Q + 4) * NCELL];
-        const double o0 = r[(R_O + 0) * NCELL], o1 = r[(R_O + 1) * NCELL], o2 = r[(R_O + 2) * NCELL];
-        const double o3 = r[(R_O + 3) * NCELL], o4 = r[(R_O + 4) * NCELL], o5 = r[(R_O + 5) * NCELL];
-        const double o6 = r[(R_O + 6) * NCELL];
+        double r[NREC];
+        load_rec(cx.rec, size_t(Cs.idx) * NCELL + q, r);
+        const double w = r[R_M];
+        const double dx = r[R_DX], dy = r[R_DY], dz = r[R_DZ];
+        const double qxx = r[R_Q + 0], qyy = r[R_Q + 1], qxy = r[R_Q + 2];
+        const double qxz = r[R_Q + 3], qyz = r[R_Q + 4];
+        const double o0 = r[R_O + 0], o1 = r[R_O + 1], o2 = r[R_O + 2];
+        const double o3 = r[R_O + 3], o4 = r[R_O + 4], o5 = r[R_O + 5];
+        const double o6 = r[R_O + 6];
         const double rx = ((x & 1) - 0.5) * hc + dx, ry = ((y & 1) - 0.5) * hc + dy, rz = ((z & 1) - 0.5) * hc + dz;
         const double qzz = -qxx - qyy;
         v[0] = w;
@@ -499,7 +519,7 @@ __global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__
     }
     const int ex = e >> 2, ey = (e >> 1) & 1, ez = e & 1;
     const int pq = ((4 * ez + (z >> 1)) * NS + (4 * ey + (y >> 1))) * NS + (4 * ex + (x >> 1));
-    m2m_store(v, cx.rec + size_t(Ps.idx) * NREC * NCELL + pq);
+    m2m_store(v, cx.rec + (size_t(Ps.idx) * NCELL + pq) * NREC, cx.com + size_t(Ps.idx) * 3 * NCELL + pq);
 }
 
 // A refined sub-grid whose 8 children are all leaves: one block per parent.
@@ -546,7 +566,7 @@ __global__ __launch_bounds__(512) void k_m2m_leafpar(Ctx cx, const int32_t* __re
             }
     double v[20];
     leaf_octet(mc, hc, v);
-    m2m_store(v, cx.rec + size_t(Ps.idx) * NREC * NCELL + q);
+    m2m_store(v, cx.rec + (size_t(Ps.idx) * NCELL + q) * NREC, cx.com + size_t(Ps.idx) * 3 * NCELL + q);
 }
 
 // ---------------------------------------------------------------------------
@@ -646,13 +666,14 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
 
     // target data
     P oa[9];
-    const double* rt = cx.rec + size_t(tidx) * NREC * NCELL;
-    const double mA = rt[R_M * NCELL + q];
-    double dAx = rt[R_DX * NCELL + q], dAy = rt[R_DY * NCELL + q], dAz = rt[R_DZ * NCELL + q];
+    double rt[NREC];
+    load_rec(cx.rec, size_t(tidx) * NCELL + q, rt);
+    const double mA = rt[R_M];
+    double dAx = rt[R_DX], dAy = rt[R_DY], dAz = rt[R_DZ];
     {
         const double os = mA > 0 ? 1.0 / (6.0 * mA) : 0.0;
 #pragma unroll
-        for (int k = 0; k < 7; ++k) oa[k] = P(rt[(R_O + k) * NCELL + q] * os);
+        for (int k = 0; k < 7; ++k) oa[k] = P(rt[R_O + k] * os);
         if (SWEEP) {
             swap_yz(dAy, dAz);
             swap_yz_o(oa);
@@ -705,12 +726,13 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
                     const int code = nb[(ox + 1) * 9 + (oy + 1) * VN + (oz + 1) * WN];
                     const int cq = lz * WS + (ly - NS * oy) * VS + (lx - NS * ox);
                     const int kind = code < 0 ? -1 : (code & 1), nidx = code >> 1;
-                    const double* r = cx.rec + (kind == 1 ? size_t(nidx) * NREC * NCELL + cq : size_t(0));
+                    // leaf and absent cells read the zero record; a leaf
+                    // cell's mass then replaces its zero mass
                     const double* mp = cx.mass + (kind == 0 ? size_t(nidx) * NCELL + cq : size_t(0));
                     double v[NREC];
-#pragma unroll
-                    for (int k = 0; k < NREC; ++k) v[k] = r[k * NCELL];
+                    load_rec(cx.rec, kind == 1 ? size_t(nidx) * NCELL + cq : size_t(cx.rec_zero), v);
                     const double mm = *mp;
+                    if (kind == 0) v[R_M] = mm;
                     if (SWEEP) {
                         swap_yz(v[R_DY], v[R_DZ]);
                         swap_yz_q(v + R_Q);
@@ -722,7 +744,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
                     P w[NREC];
 #pragma unroll
                     for (int k = 0; k < NREC; ++k) {
-                        double val = kind == 1 ? v[k] : (k == 0 && kind == 0 ? mm : 0.0);
+                        double val = v[k];
                         if (k >= R_DX && k <= R_DZ) val = fma(h, pos[k - R_DX], val);
                         if (k >= R_O) val *= 1.0 / 6.0;
                         w[k] = P(val);
@@ -863,10 +885,8 @@ __device__ __forceinline__ void c4_item(const Ctx& cx, int sid, int o0, int o1, 
             const int ix = sp / (ny * nz), iy = (sp / nz) % ny, iz = sp % nz;
             const int lx = 2 * (px0 + ix) + (ch >> 2), ly = 2 * (py0 + iy) + ((ch >> 1) & 1);
             const int lz = 2 * (pz0 + iz) + (ch & 1);
-            const double* r = cx.rec + size_t(code >> 1) * NREC * NCELL + (lz * NS + ly) * NS + lx;
             double v[NREC];
-#pragma unroll
-            for (int k = 0; k < NREC; ++k) v[k] = r[k * NCELL];
+            load_rec(cx.rec, size_t(code >> 1) * NCELL + (lz * NS + ly) * NS + lx, v);
             v[R_DX] = fma(h, double(NS * ox + lx), v[R_DX]);
             v[R_DY] = fma(h, double(NS * oy + ly), v[R_DY]);
             v[R_DZ] = fma(h, double(NS * oz + lz), v[R_DZ]);
@@ -1185,13 +1205,14 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
     double mA, dAx = 0, dAy = 0, dAz = 0;
     P oa[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (tref) {
-        const double* r = cx.rec + size_t(T.idx) * NREC * NCELL;
-        mA = r[R_M * NCELL + q];
-        dAx = r[R_DX * NCELL + q];
-        dAy = r[R_DY * NCELL + q];
-        dAz = r[R_DZ * NCELL + q];
+        double r[NREC];
+        load_rec(cx.rec, size_t(T.idx) * NCELL + q, r);
+        mA = r[R_M];
+        dAx = r[R_DX];
+        dAy = r[R_DY];
+        dAz = r[R_DZ];
         const double os = mA > 0 ? 1.0 / (6.0 * mA) : 0.0;
-        for (int k = 0; k < 7; ++k) oa[k] = P(r[(R_O + k) * NCELL + q] * os);
+        for (int k = 0; k < 7; ++k) oa[k] = P(r[R_O + k] * os);
         oa[7] = -oa[0] - oa[3];
         oa[8] = -oa[1] - oa[5];
     } else {
@@ -1215,9 +1236,10 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
             sc[2 * 256 + t] = NS * S.coord[2] + (cq >> 6);
             sc[3 * 256 + t] = S.kind;
             if (S.kind == 1) {
-                const double* r = cx.rec + size_t(S.idx) * NREC * NCELL + cq;
+                double r[NREC];
+                load_rec(cx.rec, size_t(S.idx) * NCELL + cq, r);
 #pragma unroll
-                for (int k = 0; k < NREC; ++k) sv[k * 256 + t] = P(r[k * NCELL] * (k >= R_O ? 1.0 / 6.0 : 1.0));
+                for (int k = 0; k < NREC; ++k) sv[k * 256 + t] = P(r[k] * (k >= R_O ? 1.0 / 6.0 : 1.0));
             } else {
                 sv[t] = P(cx.mass[size_t(S.idx) * NCELL + cq]);
 #pragma unroll
@@ -1374,7 +1396,7 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
         v[r] = 0.0;
         if (i >= (NLOC + 3) * 64) continue;
         if (k >= NLOC) {
-            v[r] = cx.rec[(size_t(Ps.idx) * NREC + R_DX + (k - NLOC)) * NCELL + pq];
+            v[r] = cx.com[(size_t(Ps.idx) * 3 + (k - NLOC)) * NCELL + pq];
         } else if (parent_mode == PARENT_TOP_PARTS) {
             v[r] = top_total(cx, Ps, k, pq);
         } else {
@@ -1409,10 +1431,10 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
     double cdx = 0, cdy = 0, cdz = 0;
     const bool cref = Cs.kind == 1;
     if (cref) {
-        const double* cr = cx.rec + size_t(Cs.idx) * NREC * NCELL + q;
-        cdx = cr[R_DX * NCELL];
-        cdy = cr[R_DY * NCELL];
-        cdz = cr[R_DZ * NCELL];
+        const double* cr = cx.com + size_t(Cs.idx) * 3 * NCELL + q;
+        cdx = cr[0];
+        cdy = cr[NCELL];
+        cdz = cr[2 * NCELL];
     }
     const double rx = ((x & 1) - 0.5) * hc + cdx - par[NLOC][pc];
     const double ry = ((y & 1) - 0.5) * hc + cdy - par[NLOC + 1][pc];

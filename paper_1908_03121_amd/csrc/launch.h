@@ -15,7 +15,9 @@ struct Ctx {
     const SubDev* subs;
     const int32_t* leaf_sub;
     double* mass;
-    double* rec;
+    double* rec;            // [n_ref][512][16] records, cell-major
+    double* com;            // [n_ref][3][512] their centre-of-mass offsets (downward pass)
+    int64_t rec_zero;       // cell index of the all-zero record after the last refined cell
     double* Lp;             // [MAX_GROUPS][n_ref][19][512] own terms per plane group
     double* Lr;             // [n_ref][19][512] totals
     double* Lf;             // [n_leaf][4][512]
