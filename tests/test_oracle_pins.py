@@ -468,6 +468,46 @@ def test_c2_fmm_vs_direct_sum_at_sampled_cells():
     assert e_g > 1e-4
 
 
+def test_c2_truncation_error_interior_and_coarse_fine_boundary_cells():
+    """The same field's truncation error reported separately for interior
+    leaves (all 26 same-level neighbours are leaves) and coarse-fine boundary
+    leaves (a same-level neighbour inside the domain is absent, i.e. coarser,
+    or refined): 300 sampled cells each against Newton's sum.  Boundary
+    cells, whose near partners across the level change are taken as
+    multipoles, carry the larger error."""
+    import itertools
+    W = wl.c2()
+    t = W.trees[0]
+    ref = t.refined_mask()
+    key = {(int(l), *map(int, c)): i for i, (l, c) in enumerate(zip(t.level, t.coord))}
+    bnd = []
+    for s in t.leaf_indices():
+        lv, c, n = int(t.level[s]), t.coord[s], 1 << int(t.level[s])
+        b = False
+        for o in itertools.product((-1, 0, 1), repeat=3):
+            p = c + np.array(o)
+            if o == (0, 0, 0) or (p < 0).any() or (p >= n).any():
+                continue
+            j = key.get((lv, *map(int, p)))
+            b |= j is None or bool(ref[j])
+        bnd.append(b)
+    bnd = np.array(bnd)
+    assert 0 < bnd.sum() < len(bnd)
+    rng = np.random.default_rng(11)
+    errs = {}
+    for name, pool in (("interior", np.nonzero(~bnd)[0]), ("boundary", np.nonzero(bnd)[0])):
+        li = rng.choice(pool, 300).astype(np.int32)
+        ci = rng.integers(0, 512, 300).astype(np.int32)
+        pf, gf = oracle.solve_sampled(t, W.rho, li, ci)
+        pd, gd = oracle.direct_sum_sampled(t, W.rho, li, ci)
+        errs[name] = (np.linalg.norm(pf - pd) / np.linalg.norm(pd), np.linalg.norm(gf - gd) / np.linalg.norm(gd))
+    print(f"  {bnd.sum()} of {len(bnd)} leaves on a coarse-fine boundary; errors {errs}", flush=True)
+    # measured: interior phi 6.3e-5, g 1.4e-3; boundary phi 5.6e-4, g 1.0e-2
+    assert errs["interior"][0] < 2e-4 and errs["interior"][1] < 4e-3
+    assert errs["boundary"][0] < 1.5e-3 and errs["boundary"][1] < 3e-2
+    assert errs["boundary"][0] > errs["interior"][0] and errs["boundary"][1] > errs["interior"][1]
+
+
 def test_oracle_rejects_malformed_input():
     t = wl.uniform_tree(1)
     rho = np.ones((8, 8, 8, 8))
