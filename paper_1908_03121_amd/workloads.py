@@ -361,3 +361,23 @@ def small_amr(seed: int, max_level: int = 2, p_refine: float = 0.4) -> Workload:
 
 
 CONFIGS = {"c0": c0, "c1": c1, "c2": c2, "c4": c4}
+
+
+def isolated_masses(tree: TreeDesc, seed: int, fill: float = 0.6) -> np.ndarray:
+    """Densities that are zero except in single leaf cells, at most one per
+    cell of the level-0 sub-grid (so every non-leaf cell holds at most one
+    massive leaf cell below it): a random ``fill`` fraction of the level-0
+    cells gets one, at a random leaf cell inside it, with a lognormal
+    density.  Needs a refined root."""
+    if tree.level.shape[0] < 2:
+        raise ValueError("isolated_masses needs a refined root sub-grid")
+    rng = np.random.default_rng(seed)
+    x = tree.leaf_cell_centres().reshape(-1, 3)
+    root = np.floor((x - np.asarray(tree.origin)) / (tree.L0 / N_SUB)).astype(np.int64)
+    key = (root[:, 0] * N_SUB + root[:, 1]) * N_SUB + root[:, 2]
+    rho = np.zeros(x.shape[0])
+    for k in np.unique(key):
+        if rng.uniform() < fill:
+            cells = np.nonzero(key == k)[0]
+            rho[cells[rng.integers(cells.shape[0])]] = rng.lognormal(0.0, 1.0)
+    return rho.reshape(-1, N_SUB, N_SUB, N_SUB)

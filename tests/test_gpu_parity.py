@@ -369,6 +369,25 @@ def test_zero_density_regions():
     assert not phi0.any() and not g0.any()
 
 
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g1"])
+def test_isolated_point_masses_give_newton_on_the_gpu(shape):
+    """At most one massive leaf cell per level-0 cell on the binary-star tree
+    (five levels, all four classes, class-4 chunks, both sweep frames): at the
+    massive cells the product's field is Newton's sum to round-off, checked
+    against the direct sum without going through the FMM oracle."""
+    t = c2_workload().trees[0]
+    rho = wl.isolated_masses(t, 11)
+    li, ci = np.nonzero(rho.reshape(rho.shape[0], 512) > 0)
+    print(f"  {li.shape[0]} isolated masses", flush=True)
+    assert li.shape[0] > 250
+    phi, g, _ = run([t], rho, use_graph=True, **SHAPES[shape])
+    pd, gd = oracle.direct_sum_sampled(t, rho, li, ci)
+    ep = np.abs(phi[li, ci] - pd).max() / np.abs(pd).max()
+    eg = np.abs(g[li, :, ci] - gd).max() / np.abs(gd).max()
+    print(f"  errors against Newton: phi {ep:.3e} g {eg:.3e}", flush=True)
+    assert ep < TOL64 and eg < TOL64
+
+
 @pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
 def test_graph_replays_match_eager(shape):
     W = wl.small_amr(5)

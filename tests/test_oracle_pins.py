@@ -508,6 +508,30 @@ def test_c2_truncation_error_interior_and_coarse_fine_boundary_cells():
     assert errs["boundary"][0] > errs["interior"][0] and errs["boundary"][1] > errs["interior"][1]
 
 
+@pytest.mark.parametrize("seed,max_level", [(1, 2), (3, 3)])
+def test_isolated_point_masses_are_exact_newton(seed, max_level):
+    """If every non-leaf cell holds at most one massive leaf cell, each massive
+    cell's multipoles about its centre of mass are a bare monopole and every
+    downward shift towards a massive cell is by zero: the method then gives
+    Newton's field at the massive cells to round-off, through every class and
+    level, with or without the correction (whose terms all carry a quadrupole
+    or octupole).  A pair counted twice or missed, a wrong sign or G fails
+    this at O(1)."""
+    t = wl.small_amr(seed, max_level=max_level).trees[0]
+    rho = wl.isolated_masses(t, seed)
+    sel = rho.reshape(rho.shape[0], 512) > 0
+    assert sel.sum() > 250
+    phi, g = oracle.solve(t, rho)
+    pd, gd = oracle.direct_sum(t, rho)
+    gs, gds = g.transpose(0, 2, 1)[sel], gd.transpose(0, 2, 1)[sel]
+    assert np.abs(phi[sel] - pd[sel]).max() < 1e-13 * np.abs(pd[sel]).max()
+    assert np.abs(gs - gds).max() < 1e-13 * np.abs(gds).max()
+    phi0, g0 = oracle.solve(t, rho, correction=False)
+    assert np.array_equal(phi0, phi) and np.array_equal(g0, g)
+    # the massless cells still carry the truncation error
+    assert np.abs(phi[~sel] - pd[~sel]).max() > 1e-4 * np.abs(pd[~sel]).max()
+
+
 def test_oracle_rejects_malformed_input():
     t = wl.uniform_tree(1)
     rho = np.ones((8, 8, 8, 8))
