@@ -314,7 +314,7 @@ def main():
         rho = torch.tensor(work.rho, dtype=torch.float64, device=dev)
         pers, groups = args.shape.split("_g")
         with fm.Plan(work.trees, persistent=pers == "persistent", plane_groups=int(groups), overlap=0,
-                     blocks_per_cu=args.bpc) as plan:
+                     blocks_per_cu=args.bpc, use_graph=False) as plan:
             phi, g = plan.solve(rho)
             for _ in range(2):
                 plan.solve(rho, phi, g)

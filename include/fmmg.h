@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define FMMG_VERSION 2
+#define FMMG_VERSION 3
 
 typedef struct fmmg_plan fmmg_plan; /* opaque; owns device tables and workspaces */
 
@@ -101,7 +101,8 @@ typedef struct {
     int32_t use_graph;          /* 1 = capture the launch sequence in a hipGraph on the
                                    first solve and replay it on the solve's stream
                                    (re-captured when the rho/phi/g pointers change);
-                                   0 = eager                                            */
+                                   0 = eager; -1 (default) = 1 for a batched plan
+                                   (n_trees > 1) without timing, else 0                 */
     int32_t persistent;         /* 1 = same-level step as one persistent launch over a
                                    work list of all classes and trees; 0 = one launch
                                    per class                                            */
@@ -179,6 +180,7 @@ typedef struct {
                                    also the fine monopole class runs on a third one      */
     int32_t split_level;        /* levels below this one form the coarse branch        */
     int32_t launch_streams;     /* streams of the per-sub-grid launch model, or 0      */
+    int32_t use_graph;          /* 1 if solves are captured and replayed as a hipGraph */
 } fmmg_launch_shape;
 
 typedef struct {

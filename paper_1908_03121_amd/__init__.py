@@ -61,13 +61,13 @@ class fmmg_timings(C.Structure):
 class fmmg_launch_shape(C.Structure):
     _fields_ = [("persistent", C.c_int32), ("plane_groups", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("from_cache", C.c_int32), ("tuned_ms", C.c_double), ("overlap", C.c_int32),
-                ("split_level", C.c_int32), ("launch_streams", C.c_int32)]
+                ("split_level", C.c_int32), ("launch_streams", C.c_int32), ("use_graph", C.c_int32)]
 
     def as_dict(self):
         return {"persistent": int(self.persistent), "plane_groups": int(self.plane_groups),
                 "blocks_per_cu": int(self.blocks_per_cu), "overlap": int(self.overlap),
                 "split_level": int(self.split_level), "launch_streams": int(self.launch_streams),
-                "from_cache": int(self.from_cache),
+                "from_cache": int(self.from_cache), "use_graph": int(self.use_graph),
                 "tuned_ms": float(self.tuned_ms)}
 
 
@@ -275,7 +275,7 @@ class Plan:
     """Owns one fmmg plan.  ``solve`` returns (phi [L,512], g [L,3,512])."""
 
     def __init__(self, trees: Sequence, precision: str = "fp64", top_mode: str = "full",
-                 G: float = 1.0, angular_correction: bool = True, use_graph: bool = False,
+                 G: float = 1.0, angular_correction: bool = True, use_graph: bool | None = None,
                  persistent: bool = False, timing: bool = False, plane_groups: int = 0,
                  blocks_per_cu: int = 0, autotune: bool = False, tuning_cache: str | None = None,
                  overlap: int = 1, launch_streams: int = 0, stream=None):
@@ -284,7 +284,8 @@ class Plan:
         opt.top_mode = {"full": FMMG_TOP_FULL, "stencil": FMMG_TOP_STENCIL_ONLY}[top_mode]
         opt.G = float(G)
         opt.angular_correction = int(bool(angular_correction))
-        opt.use_graph = int(bool(use_graph))
+        # None: the library's default (capture batched plans without timing)
+        opt.use_graph = -1 if use_graph is None else int(bool(use_graph))
         opt.persistent = int(bool(persistent))
         opt.timing = int(bool(timing))
         opt.plane_groups = int(plane_groups)

@@ -282,6 +282,7 @@ fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int o
     p->shape.overlap = overlap;
     p->shape.split_level = p->hp.split;
     p->shape.launch_streams = int32_t(p->pool.size());
+    p->shape.use_graph = p->opt.use_graph ? 1 : 0;
     return FMMG_OK;
 }
 
@@ -673,7 +674,7 @@ void fmmg_default_options(fmmg_options* opt) {
     opt->top_mode = FMMG_TOP_FULL;
     opt->G = 1.0;
     opt->angular_correction = 1;
-    opt->use_graph = 0;
+    opt->use_graph = -1;
     opt->persistent = 0;
     opt->timing = 0;
     opt->plane_groups = 0;
@@ -721,6 +722,8 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         p = new fmmg_plan();
         if (opt) p->opt = *opt;
         else fmmg_default_options(&p->opt);
+        // use_graph < 0: capture batched plans, unless their stages are timed
+        if (p->opt.use_graph < 0) p->opt.use_graph = (n_trees > 1 && !p->opt.timing) ? 1 : 0;
         const fmmg_options& o = p->opt;
         std::string bad;
         if (o.precision != FMMG_FP64 && o.precision != FMMG_MIXED && o.precision != FMMG_MIXED_F32)

@@ -435,6 +435,29 @@ def test_graph_recaptures_for_new_buffers_on_a_side_stream():
         assert max(field_errors(phi.cpu().numpy(), g.cpu().numpy(), pr, gr)) < TOL64
 
 
+def test_batched_plans_replay_a_graph_by_default():
+    """Default options: a batched plan captures its launch sequence on the first
+    solve and replays it (the same result as eager launches, bit for bit); a
+    one-tree plan and a timed batched plan launch eagerly."""
+    a, b = wl.small_amr(2), wl.small_amr(3)
+    trees = [a.trees[0], b.trees[0]]
+    r = torch.tensor(np.concatenate([a.rho, b.rho]), dtype=torch.float64, device=DEV)
+    with fm.Plan(trees, use_graph=False) as pe:
+        ref = [x.clone() for x in pe.solve(r)]
+        torch.cuda.synchronize()
+        assert pe.launch_shape()["use_graph"] == 0
+    with fm.Plan(trees) as p:
+        assert p.launch_shape()["use_graph"] == 1
+        for rep in range(3):
+            phi, g = p.solve(r)
+            torch.cuda.synchronize()
+            assert torch.equal(phi, ref[0]) and torch.equal(g, ref[1]), rep
+    with fm.Plan([a.trees[0]]) as p1:
+        assert p1.launch_shape()["use_graph"] == 0
+    with fm.Plan(trees, timing=True) as pt:
+        assert pt.launch_shape()["use_graph"] == 0
+
+
 @pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
 def test_repeat_solves_are_bitwise_deterministic(shape):
     """Every output is written by one work item in a fixed order, so even the

@@ -26,14 +26,14 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(fm.EXPORTED)
     for n in names:
         assert hasattr(L, n), n
-    assert fm.fmmg_version() == 2
+    assert fm.fmmg_version() == 3
 
 
 def test_default_options():
     o = fm.fmmg_default_options()
     assert o.precision == fm.FMMG_FP64 and o.top_mode == fm.FMMG_TOP_FULL
     assert o.G == 1.0 and o.angular_correction == 1
-    assert o.overlap == 1 and o.launch_streams == 0 and o.use_graph == 0 and o.persistent == 0
+    assert o.overlap == 1 and o.launch_streams == 0 and o.use_graph == -1 and o.persistent == 0
 
 
 @pytest.mark.parametrize("bad", [
