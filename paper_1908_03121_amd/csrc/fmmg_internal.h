@@ -118,9 +118,10 @@ constexpr int C4_ITEM_STEPS = 400;
 // Canonical stencil tables (parity (0,0,0); other parities are mirror images:
 // a cell of parity p uses offset (sx*dx, sy*dy, sz*dz) with s = 1 - 2p).
 struct StencilTables {
-    // refined-target multipole kernel: entries (dx + 8) | (dy + 8) << 8,
-    // grouped by canonical dz (DZ0..DZ0+NDZ-1), far entries first, then near
-    // ones
+    // refined-target multipole kernel: entries 16 dx (low signed 16 bits)
+    // and 16 MP_PRS dy (high signed 16 bits), the byte offsets of the source
+    // cell in the plane window, grouped by canonical dz (DZ0..DZ0+NDZ-1), far
+    // entries first, then near ones
     int32_t mp_entry[743];
     int32_t mp_far_begin[NDZ], mp_far_count[NDZ];
     int32_t mp_near_begin[NDZ], mp_near_count[NDZ];

@@ -19,6 +19,9 @@
 
 namespace fmmg {
 
+// two signed 16-bit lanes of a 32-bit register (packed dot products)
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
 __constant__ StencilTables c_tab;
 
 // ---------------------------------------------------------------------------
@@ -697,6 +700,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     // component group of the plane window:
     // lbase + sx * 16 dx + sy * (16 MP_PRS) dy  (mirror signs per lane)
     const int lbase = ((y + REACH) * MP_PRS + (x + REACH)) * 16;
+    const short2_t sxy = {short(sx), short(sy)};
 
     for (int gi = i0; gi < i1; ++gi) {
         const int dz = sz * (DZ0 + gi);
@@ -768,10 +772,12 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         Acc<PA>& part = PR != PR_F64 ? part_store : *reinterpret_cast<Acc<PA>*>(&acc);
         if (PR != PR_F64) part.zero();
         const int32_t* tab = c_tab.mp_entry;
+        // byte offset of an entry's source cell for this lane: the entry's
+        // canonical offsets (dx, dy) scaled to bytes, in two signed 16-bit
+        // halves, dotted with the lane's mirror signs (one instruction)
+        auto addr = [&](int e) { return __builtin_amdgcn_sdot2(sxy, __builtin_bit_cast(short2_t, tab[e]), lbase, false); };
         auto one = [&](int e) {
-            const int ent = tab[e];
-            const int dx16 = ((ent & 255) - 8) * 16, dy16 = (((ent >> 8) & 255) - 8) * (16 * MP_PRS);
-            const unsigned char* cs = smem + lbase + __mul24(sx, dx16) + __mul24(sy, dy16);
+            const unsigned char* cs = smem + addr(e);
             P src[NREC];
 #pragma unroll
             for (int j = 0; j < NREC / V; ++j) {
@@ -796,9 +802,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         if (do_near) {
             const int nbg = c_tab.mp_near_begin[gi], ne = nbg + c_tab.mp_near_count[gi];
             for (int e = nbg + w; e < ne; e += 4) {
-                const int ent = tab[e];
-                const int dx16 = ((ent & 255) - 8) * 16, dy16 = (((ent >> 8) & 255) - 8) * (16 * MP_PRS);
-                if (!leafflag[(lbase + __mul24(sx, dx16) + __mul24(sy, dy16)) >> 4]) continue;
+                if (!leafflag[addr(e) >> 4]) continue;
                 one(e);
             }
         }

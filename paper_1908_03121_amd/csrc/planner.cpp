@@ -154,9 +154,11 @@ void build_stencil_tables(StencilTables* t) {
             int begin = pos;
             for (size_t e = 0; e < c.dx.size(); ++e) {
                 if (c.dz[e] != dz || c.far[e] != (pass == 0)) continue;
-                // footprint: the in-plane neighbour columns (o_u, o_v) that the
-                // 64 lanes of a plane reach, bit (o_u + 1) * 3 + (o_v + 1)
-                t->mp_entry[pos++] = (c.dx[e] + 8) | ((c.dy[e] + 8) << 8);
+                // byte offsets of the source cell in a component group of
+                // the plane window (16 bytes per cell, MP_PRS cells per row)
+                const uint32_t ox = uint16_t(int16_t(16 * c.dx[e]));
+                const uint32_t oy = uint16_t(int16_t(16 * MP_PRS * c.dy[e]));
+                t->mp_entry[pos++] = int32_t(ox | (oy << 16));
             }
             if (pass == 0) { t->mp_far_begin[g] = begin; t->mp_far_count[g] = pos - begin; }
             else { t->mp_near_begin[g] = begin; t->mp_near_count[g] = pos - begin; }
