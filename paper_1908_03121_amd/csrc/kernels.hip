@@ -146,13 +146,14 @@ __device__ __forceinline__ void oct_rr(const P o[7], P oxzz, P oyzz, P XmZ, P Ym
 // factor -G (applied once per target):
 //   L0 += mb D0 + 1/2 q:D2 - 1/6 o:D3,  L1 += mb D1 + 1/2 q:D3,
 //   L2 += mb D2,  L3 += mb D3,
-//   S  += D4:(o_B - (mb/mA) o_A) / 6   (angular-momentum correction, times -G)
+//   S  += D4:(o_B - (mb/mA) o_A) / 18  (angular-momentum correction, times -3G)
 // With trace-free tensors and D^(n) = sum of R^k delta^j terms these reduce to
 //   q:D2 = d2 RqR,  (q:D3)_i = d3 R_i RqR + 2 d2 (qR)_i,  o:D3 = d3 o:RRR,
 //   (D4:Q)_i = d4 R_i Q:RRR + 3 d3 (Q:RR)_i,
 // where d0 = 1/r, d1 = -1/r^3, d2 = 3/r^5, d3 = -15/r^7, d4 = 105/r^9.
 // The source octupole arrives divided by 6 (o holds o_B/6), which folds the
-// 1/6 of L0 into the staged data and leaves S scaled by 1/6; the target's
+// 1/6 of L0 into the staged data and scales S by 1/6; S is further taken
+// over 3 (d4/3 R_i Q:RRR + d3 (Q:RR)_i), which saves the factor 3; the target's
 // arrives divided by 6 mA (oa holds o_A/(6 mA), zero for mA = 0), so that
 // its weight in the correction is -mb.
 // FULL: refined target (L2, L3 and its own octupole oa enter; oa[7], oa[8]
@@ -203,7 +204,7 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
     // correction terms: always accumulated (no branch in the pair body); the
     // output scale of S is zero when the correction is off
     {
-        const P d4 = P(-7) * ir2 * d3;
+        const P d4t = P(-7.0 / 3.0) * ir2 * d3;  // d4 / 3
         P Qx = wb[0], Qy = wb[1], Qz = wb[2];
         if (FULL) {
             P wa[3];
@@ -213,10 +214,10 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
             Qz = fmaP(-mb, wa[2], Qz);
         }
         const P QRRR = fmaP(X, Qx, fmaP(Y, Qy, Z * Qz));
-        const P t4 = d4 * QRRR, t3 = P(3) * d3;
-        a.s[0] = fmaP(t4, X, fmaP(t3, Qx, a.s[0]));
-        a.s[1] = fmaP(t4, Y, fmaP(t3, Qy, a.s[1]));
-        a.s[2] = fmaP(t4, Z, fmaP(t3, Qz, a.s[2]));
+        const P t4 = d4t * QRRR;
+        a.s[0] = fmaP(t4, X, fmaP(d3, Qx, a.s[0]));
+        a.s[1] = fmaP(t4, Y, fmaP(d3, Qy, a.s[1]));
+        a.s[2] = fmaP(t4, Z, fmaP(d3, Qz, a.s[2]));
     }
 }
 
@@ -236,7 +237,7 @@ __device__ __forceinline__ void pair_terms_mix(double X, double Y, double Z, dou
     const double d1 = -d0 * ir2;
     const double d2 = -3.0 * ir2 * d1;
     const double d3 = -5.0 * ir2 * d2;
-    const double d4 = -7.0 * ir2 * d3;
+    const double d4t = (-7.0 / 3.0) * ir2 * d3;  // d4 / 3, as in pair_terms
     const double XY = X * Y, XZ = X * Z, YZ = Y * Z;
     const double XmZ = XX - ZZ, YmZ = YY - ZZ, XY2 = XY + XY, XZ2 = XZ + XZ, YZ2 = YZ + YZ;
     double wb[3];
@@ -252,10 +253,10 @@ __device__ __forceinline__ void pair_terms_mix(double X, double Y, double Z, dou
             Qz = fmaP(-mb, wa[2], Qz);
         }
         const double QRRR = fmaP(X, Qx, fmaP(Y, Qy, Z * Qz));
-        const double t4 = d4 * QRRR, t3 = 3.0 * d3;
-        s[0] = fmaP(t4, X, fmaP(t3, Qx, s[0]));
-        s[1] = fmaP(t4, Y, fmaP(t3, Qy, s[1]));
-        s[2] = fmaP(t4, Z, fmaP(t3, Qz, s[2]));
+        const double t4 = d4t * QRRR;
+        s[0] = fmaP(t4, X, fmaP(d3, Qx, s[0]));
+        s[1] = fmaP(t4, Y, fmaP(d3, Qy, s[1]));
+        s[2] = fmaP(t4, Z, fmaP(d3, Qz, s[2]));
     }
     const float x = float(X), y = float(Y), z = float(Z), m = float(mb);
     const float f0 = float(d0), f1 = float(d1), f2 = float(d2), f3 = float(d3);
@@ -829,7 +830,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     }
     __syncthreads();
     const double G = cx.G;
-    const double gs = use_corr ? -G : 0.0;  // S holds the correction / 6
+    const double gs = use_corr ? -3.0 * G : 0.0;  // S holds the correction / 18
     auto sum4 = [&](int k, int l) {
         return red[(0 * NLOC + k) * 64 + l] + red[(1 * NLOC + k) * 64 + l] +
                red[(2 * NLOC + k) * 64 + l] + red[(3 * NLOC + k) * 64 + l];
@@ -870,7 +871,7 @@ __device__ __forceinline__ void c4_item(const Ctx& cx, int sid, int o0, int o1, 
     const int c = lane & 7, tc = lane >> 3;
     const SubDev& T = cx.subs[sid];
     const double h = T.h;
-    const double sfac = cx.corr ? -1.0 : 0.0;  // S holds the correction / 6
+    const double sfac = cx.corr ? -3.0 : 0.0;  // S holds the correction / 18
     for (int i = t; i < NLEAF * NCELL; i += 256) tot[i] = 0.0;
     const P oa[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // leaf targets carry no octupole
     for (int o = o0; o < o1; ++o) {
@@ -1350,7 +1351,8 @@ __global__ __launch_bounds__(256, 3) void k_persist(Ctx cx, const Item* __restri
 // step 3: downward pass
 // ---------------------------------------------------------------------------
 // Total expansion of a top-level target under the all-pairs rule: the sum of
-// its partial slots in a fixed order, scaled by -G (S holds the correction / 6).
+// its partial slots in a fixed order, scaled by -G (S, which holds the
+// correction / 18, by -3G).
 __device__ __forceinline__ double top_total(const Ctx& cx, const SubDev& T, int k, int q) {
     const TopReduce R = cx.top_reds[T.red];
     const double* base = cx.part + (size_t(R.part_begin) * NLOC + k) * NCELL + q;
@@ -1360,7 +1362,7 @@ __device__ __forceinline__ double top_total(const Ctx& cx, const SubDev& T, int 
         const double t = base[size_t(p < R.n_part ? p : R.n_part - 1) * (NLOC * NCELL)];
         v += p < R.n_part ? t : 0.0;
     }
-    return (k >= T_S && !cx.corr ? 0.0 : -cx.G) * v;
+    return (k >= T_S ? (cx.corr ? -3.0 * cx.G : 0.0) : -cx.G) * v;
 }
 
 // Parent expansion (L0, L1, trace-free L2, L3, correction dg) re-expanded at
