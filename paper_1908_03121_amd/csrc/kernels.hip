@@ -88,6 +88,12 @@ __device__ __forceinline__ void load_rec(const double* __restrict__ rec, size_t 
     }
 }
 
+// Scale of record component k as the pair terms take a staged source:
+// quadrupole times -3, octupole divided by 2, mass and position unchanged.
+__device__ __forceinline__ constexpr double stage_scale(int k) {
+    return k >= R_O ? 0.5 : (k >= R_Q ? -3.0 : 1.0);
+}
+
 // Accumulators of one target cell.  Refined targets carry all 19 components
 // (L2 as its trace-free parts xx yy xy xz yz plus the running trace term
 // mb*d1 that both diagonal parts share); leaf targets only L0, L1 and the
@@ -114,14 +120,15 @@ struct Acc {
             for (int i = 0; i < 7; ++i) l3[i] += P(o.l3[i]);
         }
     }
-    // the 19 output components (L2 diagonal with its trace term)
+    // the 19 output components (L2 diagonal with its trace term); the pair
+    // terms accumulate L2 (without the trace term) and L3 divided by -3
     __device__ __forceinline__ void out(double v[NLOC]) const {
         v[T_L0] = double(l0);
         for (int i = 0; i < 3; ++i) v[T_L1 + i] = double(l1[i]);
-        v[T_L2 + 0] = double(l2[0]) + double(l2t);
-        v[T_L2 + 1] = double(l2[1]) + double(l2t);
-        for (int i = 2; i < 5; ++i) v[T_L2 + i] = double(l2[i]);
-        for (int i = 0; i < 7; ++i) v[T_L3 + i] = double(l3[i]);
+        v[T_L2 + 0] = fma(-3.0, double(l2[0]), double(l2t));
+        v[T_L2 + 1] = fma(-3.0, double(l2[1]), double(l2t));
+        for (int i = 2; i < 5; ++i) v[T_L2 + i] = -3.0 * double(l2[i]);
+        for (int i = 0; i < 7; ++i) v[T_L3 + i] = -3.0 * double(l3[i]);
         for (int i = 0; i < 3; ++i) v[T_S + i] = double(s[i]);
     }
 };
@@ -146,16 +153,20 @@ __device__ __forceinline__ void oct_rr(const P o[7], P oxzz, P oyzz, P XmZ, P Ym
 // factor -G (applied once per target):
 //   L0 += mb D0 + 1/2 q:D2 - 1/6 o:D3,  L1 += mb D1 + 1/2 q:D3,
 //   L2 += mb D2,  L3 += mb D3,
-//   S  += D4:(o_B - (mb/mA) o_A) / 18  (angular-momentum correction, times -3G)
+//   dg += -G/6 D4:(o_B - (mb/mA) o_A)   (angular-momentum correction)
 // With trace-free tensors and D^(n) = sum of R^k delta^j terms these reduce to
 //   q:D2 = d2 RqR,  (q:D3)_i = d3 R_i RqR + 2 d2 (qR)_i,  o:D3 = d3 o:RRR,
 //   (D4:Q)_i = d4 R_i Q:RRR + 3 d3 (Q:RR)_i,
 // where d0 = 1/r, d1 = -1/r^3, d2 = 3/r^5, d3 = -15/r^7, d4 = 105/r^9.
-// The source octupole arrives divided by 6 (o holds o_B/6), which folds the
-// 1/6 of L0 into the staged data and scales S by 1/6; S is further taken
-// over 3 (d4/3 R_i Q:RRR + d3 (Q:RR)_i), which saves the factor 3; the target's
-// arrives divided by 6 mA (oa holds o_A/(6 mA), zero for mA = 0), so that
-// its weight in the correction is -mb.
+// The constants are folded into the staged data and the output scales: the
+// kernel forms e2 = d2/-3 = -1/r^5, e3 = d3/-3 and g4 = -7/3 e3/r^2 = -d4/9,
+// the source quadrupole arrives times -3 (q holds -3 q_B) and its octupole
+// divided by 2 (o holds o_B/2), the target's octupole divided by 2 mA (oa
+// holds o_A/(2 mA), zero for mA = 0, so that its weight in the correction is
+// -mb).  Then the L0, L1 sums are the plain ones, the L2 (without its trace
+// term mb d1) and L3 sums carry the factor -1/3 (Acc::out), and S sums
+//   e3 (Q:RR)_i + g4 R_i Q:RRR = -(D4:Q)_i / 18,  Q = o_B/2 - mb o_A/(2 mA),
+// so that dg = 3G S.
 // FULL: refined target (L2, L3 and its own octupole oa enter; oa[7], oa[8]
 // hold its dependent components xzz, yzz).
 template <bool FULL, typename P>
@@ -166,8 +177,8 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
     const P d0 = rsqrt_full(r2);
     const P ir2 = d0 * d0;
     const P d1 = -d0 * ir2;
-    const P d2 = P(-3) * ir2 * d1;
-    const P d3 = P(-5) * ir2 * d2;
+    const P e2 = ir2 * d1;            // d2 / -3
+    const P e3 = P(-5) * ir2 * e2;    // d3 / -3
     const P XY = X * Y, XZ = X * Z, YZ = Y * Z;
     const P XmZ = XX - ZZ, YmZ = YY - ZZ, XY2 = XY + XY, XZ2 = XZ + XZ, YZ2 = YZ + YZ;
     const P qzz = -q[0] - q[1];
@@ -177,14 +188,14 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
     const P hRqR = P(0.5) * fmaP(X, ux, fmaP(Y, uy, Z * uz));
     P wb[3];
     oct_rr(o, -o[0] - o[3], -o[1] - o[5], XmZ, YmZ, XY2, XZ2, YZ2, wb);
-    const P BRRR = fmaP(X, wb[0], fmaP(Y, wb[1], Z * wb[2]));  // o:RRR / 6
-    a.l0 = fmaP(mb, d0, fmaP(d2, hRqR, fmaP(-d3, BRRR, a.l0)));
-    const P c1 = fmaP(mb, d1, d3 * hRqR);
-    a.l1[0] = fmaP(c1, X, fmaP(d2, ux, a.l1[0]));
-    a.l1[1] = fmaP(c1, Y, fmaP(d2, uy, a.l1[1]));
-    a.l1[2] = fmaP(c1, Z, fmaP(d2, uz, a.l1[2]));
+    const P BRRR = fmaP(X, wb[0], fmaP(Y, wb[1], Z * wb[2]));  // o_B:RRR / 2
+    a.l0 = fmaP(mb, d0, fmaP(e2, hRqR, fmaP(e3, BRRR, a.l0)));
+    const P c1 = fmaP(mb, d1, e3 * hRqR);
+    a.l1[0] = fmaP(c1, X, fmaP(e2, ux, a.l1[0]));
+    a.l1[1] = fmaP(c1, Y, fmaP(e2, uy, a.l1[1]));
+    a.l1[2] = fmaP(c1, Z, fmaP(e2, uz, a.l1[2]));
     if (FULL) {
-        const P md2 = mb * d2, md3 = mb * d3;
+        const P md2 = mb * e2, md3 = mb * e3;
         a.l2t = fmaP(mb, d1, a.l2t);
         a.l2[0] = fmaP(md2, XX, a.l2[0]);
         a.l2[1] = fmaP(md2, YY, a.l2[1]);
@@ -204,7 +215,7 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
     // correction terms: always accumulated (no branch in the pair body); the
     // output scale of S is zero when the correction is off
     {
-        const P d4t = P(-7.0 / 3.0) * ir2 * d3;  // d4 / 3
+        const P g4 = P(-7.0 / 3.0) * ir2 * e3;  // d4 / 9
         P Qx = wb[0], Qy = wb[1], Qz = wb[2];
         if (FULL) {
             P wa[3];
@@ -214,10 +225,10 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
             Qz = fmaP(-mb, wa[2], Qz);
         }
         const P QRRR = fmaP(X, Qx, fmaP(Y, Qy, Z * Qz));
-        const P t4 = d4t * QRRR;
-        a.s[0] = fmaP(t4, X, fmaP(d3, Qx, a.s[0]));
-        a.s[1] = fmaP(t4, Y, fmaP(d3, Qy, a.s[1]));
-        a.s[2] = fmaP(t4, Z, fmaP(d3, Qz, a.s[2]));
+        const P t4 = g4 * QRRR;
+        a.s[0] = fmaP(t4, X, fmaP(e3, Qx, a.s[0]));
+        a.s[1] = fmaP(t4, Y, fmaP(e3, Qy, a.s[1]));
+        a.s[2] = fmaP(t4, Z, fmaP(e3, Qz, a.s[2]));
     }
 }
 
@@ -235,14 +246,14 @@ __device__ __forceinline__ void pair_terms_mix(double X, double Y, double Z, dou
     const double d0 = rsqrt_full(r2);
     const double ir2 = d0 * d0;
     const double d1 = -d0 * ir2;
-    const double d2 = -3.0 * ir2 * d1;
-    const double d3 = -5.0 * ir2 * d2;
-    const double d4t = (-7.0 / 3.0) * ir2 * d3;  // d4 / 3, as in pair_terms
+    const double e2 = ir2 * d1;                  // as in pair_terms
+    const double e3 = -5.0 * ir2 * e2;
+    const double g4 = (-7.0 / 3.0) * ir2 * e3;
     const double XY = X * Y, XZ = X * Z, YZ = Y * Z;
     const double XmZ = XX - ZZ, YmZ = YY - ZZ, XY2 = XY + XY, XZ2 = XZ + XZ, YZ2 = YZ + YZ;
     double wb[3];
     oct_rr(o, -o[0] - o[3], -o[1] - o[5], XmZ, YmZ, XY2, XZ2, YZ2, wb);
-    const double BRRR = fmaP(X, wb[0], fmaP(Y, wb[1], Z * wb[2]));  // o:RRR / 6
+    const double BRRR = fmaP(X, wb[0], fmaP(Y, wb[1], Z * wb[2]));  // o_B:RRR / 2
     {
         double Qx = wb[0], Qy = wb[1], Qz = wb[2];
         if (FULL) {
@@ -253,20 +264,20 @@ __device__ __forceinline__ void pair_terms_mix(double X, double Y, double Z, dou
             Qz = fmaP(-mb, wa[2], Qz);
         }
         const double QRRR = fmaP(X, Qx, fmaP(Y, Qy, Z * Qz));
-        const double t4 = d4t * QRRR;
-        s[0] = fmaP(t4, X, fmaP(d3, Qx, s[0]));
-        s[1] = fmaP(t4, Y, fmaP(d3, Qy, s[1]));
-        s[2] = fmaP(t4, Z, fmaP(d3, Qz, s[2]));
+        const double t4 = g4 * QRRR;
+        s[0] = fmaP(t4, X, fmaP(e3, Qx, s[0]));
+        s[1] = fmaP(t4, Y, fmaP(e3, Qy, s[1]));
+        s[2] = fmaP(t4, Z, fmaP(e3, Qz, s[2]));
     }
     const float x = float(X), y = float(Y), z = float(Z), m = float(mb);
-    const float f0 = float(d0), f1 = float(d1), f2 = float(d2), f3 = float(d3);
+    const float f0 = float(d0), f1 = float(d1), f2 = float(e2), f3 = float(e3);
     const float q0 = float(q[0]), q1 = float(q[1]), q2 = float(q[2]), q3 = float(q[3]), q4 = float(q[4]);
     const float qzz = -q0 - q1;
     const float ux = fmaP(q0, x, fmaP(q2, y, q3 * z));
     const float uy = fmaP(q2, x, fmaP(q1, y, q4 * z));
     const float uz = fmaP(q3, x, fmaP(q4, y, qzz * z));
     const float hRqR = 0.5f * fmaP(x, ux, fmaP(y, uy, z * uz));
-    a.l0 = fmaP(m, f0, fmaP(f2, hRqR, fmaP(-f3, float(BRRR), a.l0)));
+    a.l0 = fmaP(m, f0, fmaP(f2, hRqR, fmaP(f3, float(BRRR), a.l0)));
     const float c1 = fmaP(m, f1, f3 * hRqR);
     a.l1[0] = fmaP(c1, x, fmaP(f2, ux, a.l1[0]));
     a.l1[1] = fmaP(c1, y, fmaP(f2, uy, a.l1[1]));
@@ -675,7 +686,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     const double mA = rt[R_M];
     double dAx = rt[R_DX], dAy = rt[R_DY], dAz = rt[R_DZ];
     {
-        const double os = mA > 0 ? 1.0 / (6.0 * mA) : 0.0;
+        const double os = mA > 0 ? 1.0 / (2.0 * mA) : 0.0;
 #pragma unroll
         for (int k = 0; k < 7; ++k) oa[k] = P(rt[R_O + k] * os);
         if (SWEEP) {
@@ -744,14 +755,14 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
                         swap_yz_o(v + R_O);
                     }
                     // the COM offset becomes a position (frame coordinates of the
-                    // cell centre plus the offset) and the octupole is divided by 6
+                    // cell centre plus the offset); moments scaled by stage_scale
                     const double pos[3] = {double(lx), double(ly), double(zs)};
                     P w[NREC];
 #pragma unroll
                     for (int k = 0; k < NREC; ++k) {
                         double val = v[k];
                         if (k >= R_DX && k <= R_DZ) val = fma(h, pos[k - R_DX], val);
-                        if (k >= R_O) val *= 1.0 / 6.0;
+                        val *= stage_scale(k);
                         w[k] = P(val);
                     }
 #pragma unroll
@@ -830,7 +841,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     }
     __syncthreads();
     const double G = cx.G;
-    const double gs = use_corr ? -3.0 * G : 0.0;  // S holds the correction / 18
+    const double gs = use_corr ? 3.0 * G : 0.0;  // dg = 3G S
     auto sum4 = [&](int k, int l) {
         return red[(0 * NLOC + k) * 64 + l] + red[(1 * NLOC + k) * 64 + l] +
                red[(2 * NLOC + k) * 64 + l] + red[(3 * NLOC + k) * 64 + l];
@@ -871,7 +882,7 @@ __device__ __forceinline__ void c4_item(const Ctx& cx, int sid, int o0, int o1, 
     const int c = lane & 7, tc = lane >> 3;
     const SubDev& T = cx.subs[sid];
     const double h = T.h;
-    const double sfac = cx.corr ? -3.0 : 0.0;  // S holds the correction / 18
+    const double sfac = cx.corr ? 3.0 : 0.0;  // dg = 3G S
     for (int i = t; i < NLEAF * NCELL; i += 256) tot[i] = 0.0;
     const P oa[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // leaf targets carry no octupole
     for (int o = o0; o < o1; ++o) {
@@ -884,7 +895,7 @@ __device__ __forceinline__ void c4_item(const Ctx& cx, int sid, int o0, int o1, 
         __syncthreads();  // the previous neighbour's slab is no longer read
         // stage: thread t holds child t & 7 of slab parent t >> 3; its position
         // in the frame of the target sub-grid (centre of its cell (0,0,0)),
-        // octupole divided by 6
+        // moments scaled by stage_scale
         if (t < nslab) {
             const int sp = t >> 3, ch = t & 7;
             const int ix = sp / (ny * nz), iy = (sp / nz) % ny, iz = sp % nz;
@@ -896,7 +907,7 @@ __device__ __forceinline__ void c4_item(const Ctx& cx, int sid, int o0, int o1, 
             v[R_DY] = fma(h, double(NS * oy + ly), v[R_DY]);
             v[R_DZ] = fma(h, double(NS * oz + lz), v[R_DZ]);
 #pragma unroll
-            for (int k = R_O; k < NREC; ++k) v[k] *= 1.0 / 6.0;
+            for (int k = R_Q; k < NREC; ++k) v[k] *= stage_scale(k);
 #pragma unroll
             for (int j = 0; j < NREC / V; ++j) {
                 PV pv;
@@ -1216,7 +1227,7 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
         dAx = r[R_DX];
         dAy = r[R_DY];
         dAz = r[R_DZ];
-        const double os = mA > 0 ? 1.0 / (6.0 * mA) : 0.0;
+        const double os = mA > 0 ? 1.0 / (2.0 * mA) : 0.0;
         for (int k = 0; k < 7; ++k) oa[k] = P(r[R_O + k] * os);
         oa[7] = -oa[0] - oa[3];
         oa[8] = -oa[1] - oa[5];
@@ -1225,8 +1236,8 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
     }
     Acc<double> acc;
     acc.zero();
-    // sources staged through LDS, 256 per tile: 16 record values (octupole
-    // divided by 6, as the pair terms take it) and the
+    // sources staged through LDS, 256 per tile: 16 record values (moments
+    // scaled by stage_scale, as the pair terms take them) and the
     // global integer cell coordinates (w = 1 for a refined sub-grid's cell)
     P* sv = reinterpret_cast<P*>(smem);
     int* sc = reinterpret_cast<int*>(smem + NREC * 256 * sizeof(P));
@@ -1244,7 +1255,7 @@ __device__ __forceinline__ void top_item(const Ctx& cx, const TopItem& it, unsig
                 double r[NREC];
                 load_rec(cx.rec, size_t(S.idx) * NCELL + cq, r);
 #pragma unroll
-                for (int k = 0; k < NREC; ++k) sv[k * 256 + t] = P(r[k] * (k >= R_O ? 1.0 / 6.0 : 1.0));
+                for (int k = 0; k < NREC; ++k) sv[k * 256 + t] = P(r[k] * stage_scale(k));
             } else {
                 sv[t] = P(cx.mass[size_t(S.idx) * NCELL + cq]);
 #pragma unroll
@@ -1351,8 +1362,8 @@ __global__ __launch_bounds__(256, 3) void k_persist(Ctx cx, const Item* __restri
 // step 3: downward pass
 // ---------------------------------------------------------------------------
 // Total expansion of a top-level target under the all-pairs rule: the sum of
-// its partial slots in a fixed order, scaled by -G (S, which holds the
-// correction / 18, by -3G).
+// its partial slots in a fixed order, scaled by -G (the correction sums S
+// by 3G).
 __device__ __forceinline__ double top_total(const Ctx& cx, const SubDev& T, int k, int q) {
     const TopReduce R = cx.top_reds[T.red];
     const double* base = cx.part + (size_t(R.part_begin) * NLOC + k) * NCELL + q;
@@ -1362,7 +1373,7 @@ __device__ __forceinline__ double top_total(const Ctx& cx, const SubDev& T, int 
         const double t = base[size_t(p < R.n_part ? p : R.n_part - 1) * (NLOC * NCELL)];
         v += p < R.n_part ? t : 0.0;
     }
-    return (k >= T_S ? (cx.corr ? -3.0 * cx.G : 0.0) : -cx.G) * v;
+    return (k >= T_S ? (cx.corr ? 3.0 * cx.G : 0.0) : -cx.G) * v;
 }
 
 // Parent expansion (L0, L1, trace-free L2, L3, correction dg) re-expanded at
