@@ -121,14 +121,15 @@ struct Acc {
         }
     }
     // the 19 output components (L2 diagonal with its trace term); the pair
-    // terms accumulate L2 (without the trace term) and L3 divided by -3
+    // terms accumulate L2 (without the trace term) and L3 divided by -3, and
+    // the mixed components L2 xy xz yz and L3 xyz once more doubled
     __device__ __forceinline__ void out(double v[NLOC]) const {
         v[T_L0] = double(l0);
         for (int i = 0; i < 3; ++i) v[T_L1 + i] = double(l1[i]);
         v[T_L2 + 0] = fma(-3.0, double(l2[0]), double(l2t));
         v[T_L2 + 1] = fma(-3.0, double(l2[1]), double(l2t));
-        for (int i = 2; i < 5; ++i) v[T_L2 + i] = -3.0 * double(l2[i]);
-        for (int i = 0; i < 7; ++i) v[T_L3 + i] = -3.0 * double(l3[i]);
+        for (int i = 2; i < 5; ++i) v[T_L2 + i] = -1.5 * double(l2[i]);
+        for (int i = 0; i < 7; ++i) v[T_L3 + i] = (i == 4 ? -1.5 : -3.0) * double(l3[i]);
         for (int i = 0; i < 3; ++i) v[T_S + i] = double(s[i]);
     }
 };
@@ -164,7 +165,8 @@ __device__ __forceinline__ void oct_rr(const P o[7], P oxzz, P oyzz, P XmZ, P Ym
 // divided by 2 (o holds o_B/2), the target's octupole divided by 2 mA (oa
 // holds o_A/(2 mA), zero for mA = 0, so that its weight in the correction is
 // -mb).  Then the L0, L1 sums are the plain ones, the L2 (without its trace
-// term mb d1) and L3 sums carry the factor -1/3 (Acc::out), and S sums
+// term mb d1) and L3 sums carry the factor -1/3, the mixed ones (L2 xy xz
+// yz, L3 xyz, formed from the doubled products) -2/3 (Acc::out), and S sums
 //   e3 (Q:RR)_i + g4 R_i Q:RRR = -(D4:Q)_i / 18,  Q = o_B/2 - mb o_A/(2 mA),
 // so that dg = 3G S.
 // FULL: refined target (L2, L3 and its own octupole oa enter; oa[7], oa[8]
@@ -179,8 +181,9 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
     const P d1 = -d0 * ir2;
     const P e2 = ir2 * d1;            // d2 / -3
     const P e3 = P(-5) * ir2 * e2;    // d3 / -3
-    const P XY = X * Y, XZ = X * Z, YZ = Y * Z;
-    const P XmZ = XX - ZZ, YmZ = YY - ZZ, XY2 = XY + XY, XZ2 = XZ + XZ, YZ2 = YZ + YZ;
+    const P X2 = X + X, Y2 = Y + Y;
+    const P XY2 = X2 * Y, XZ2 = X2 * Z, YZ2 = Y2 * Z;  // doubled mixed products
+    const P XmZ = XX - ZZ, YmZ = YY - ZZ;
     const P qzz = -q[0] - q[1];
     const P ux = fmaP(q[0], X, fmaP(q[2], Y, q[3] * Z));
     const P uy = fmaP(q[2], X, fmaP(q[1], Y, q[4] * Z));
@@ -199,16 +202,16 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
         a.l2t = fmaP(mb, d1, a.l2t);
         a.l2[0] = fmaP(md2, XX, a.l2[0]);
         a.l2[1] = fmaP(md2, YY, a.l2[1]);
-        a.l2[2] = fmaP(md2, XY, a.l2[2]);
-        a.l2[3] = fmaP(md2, XZ, a.l2[3]);
-        a.l2[4] = fmaP(md2, YZ, a.l2[4]);
+        a.l2[2] = fmaP(md2, XY2, a.l2[2]);
+        a.l2[3] = fmaP(md2, XZ2, a.l2[3]);
+        a.l2[4] = fmaP(md2, YZ2, a.l2[4]);
         const P m3 = P(3) * md2;
         const P bx = fmaP(md3, XX, md2), cy = fmaP(md3, YY, md2);
         a.l3[0] = fmaP(X, fmaP(md3, XX, m3), a.l3[0]);
         a.l3[1] = fmaP(Y, bx, a.l3[1]);
         a.l3[2] = fmaP(Z, bx, a.l3[2]);
         a.l3[3] = fmaP(X, cy, a.l3[3]);
-        a.l3[4] = fmaP(md3 * XY, Z, a.l3[4]);
+        a.l3[4] = fmaP(md3 * XY2, Z, a.l3[4]);
         a.l3[5] = fmaP(Y, fmaP(md3, YY, m3), a.l3[5]);
         a.l3[6] = fmaP(Z, cy, a.l3[6]);
     }
@@ -249,8 +252,9 @@ __device__ __forceinline__ void pair_terms_mix(double X, double Y, double Z, dou
     const double e2 = ir2 * d1;                  // as in pair_terms
     const double e3 = -5.0 * ir2 * e2;
     const double g4 = (-7.0 / 3.0) * ir2 * e3;
-    const double XY = X * Y, XZ = X * Z, YZ = Y * Z;
-    const double XmZ = XX - ZZ, YmZ = YY - ZZ, XY2 = XY + XY, XZ2 = XZ + XZ, YZ2 = YZ + YZ;
+    const double X2 = X + X, Y2 = Y + Y;
+    const double XY2 = X2 * Y, XZ2 = X2 * Z, YZ2 = Y2 * Z;
+    const double XmZ = XX - ZZ, YmZ = YY - ZZ;
     double wb[3];
     oct_rr(o, -o[0] - o[3], -o[1] - o[5], XmZ, YmZ, XY2, XZ2, YZ2, wb);
     const double BRRR = fmaP(X, wb[0], fmaP(Y, wb[1], Z * wb[2]));  // o_B:RRR / 2
@@ -288,16 +292,17 @@ __device__ __forceinline__ void pair_terms_mix(double X, double Y, double Z, dou
         a.l2t = fmaP(m, f1, a.l2t);
         a.l2[0] = fmaP(md2, xx, a.l2[0]);
         a.l2[1] = fmaP(md2, yy, a.l2[1]);
-        a.l2[2] = fmaP(md2, x * y, a.l2[2]);
-        a.l2[3] = fmaP(md2, x * z, a.l2[3]);
-        a.l2[4] = fmaP(md2, y * z, a.l2[4]);
+        const float x2 = x + x;
+        a.l2[2] = fmaP(md2, x2 * y, a.l2[2]);
+        a.l2[3] = fmaP(md2, x2 * z, a.l2[3]);
+        a.l2[4] = fmaP(md2, (y + y) * z, a.l2[4]);
         const float m3 = 3.0f * md2;
         const float bx = fmaP(md3, xx, md2), cy = fmaP(md3, yy, md2);
         a.l3[0] = fmaP(x, fmaP(md3, xx, m3), a.l3[0]);
         a.l3[1] = fmaP(y, bx, a.l3[1]);
         a.l3[2] = fmaP(z, bx, a.l3[2]);
         a.l3[3] = fmaP(x, cy, a.l3[3]);
-        a.l3[4] = fmaP(md3 * x * y, z, a.l3[4]);
+        a.l3[4] = fmaP(md3 * x2 * y, z, a.l3[4]);
         a.l3[5] = fmaP(y, fmaP(md3, yy, m3), a.l3[5]);
         a.l3[6] = fmaP(z, cy, a.l3[6]);
     }
