@@ -94,16 +94,17 @@ __device__ __forceinline__ constexpr double stage_scale(int k) {
     return k >= R_O ? 0.5 : (k >= R_Q ? -3.0 : 1.0);
 }
 
-// Accumulators of one target cell.  Refined targets carry all 19 components
-// (L2 as its trace-free parts xx yy xy xz yz plus the running trace term
-// mb*d1 that both diagonal parts share); leaf targets only L0, L1 and the
-// correction sum S.
+// Accumulators of one target cell.  Refined targets carry all 19 components,
+// leaf targets only L0, L1 and the correction sum S.  L2 and L3 are summed
+// in the forms the pair terms produce most cheaply (see pair_terms): l2 sums
+// mb e2 times (XX - ZZ, YY - ZZ, 2XY, 2XZ, 2YZ), l3 the components xzz,
+// xxy, xxz, xyy, 2xyz, yzz, yyz of mb D3 divided by -3.  Since D2 and D3
+// are trace-free, out() recovers L2 xx, yy and L3 xxx, yyy from them.
 template <typename P>
 struct Acc {
-    P l0, l1[3], l2[5], l2t, l3[7], s[3];
+    P l0, l1[3], l2[5], l3[7], s[3];
     __device__ __forceinline__ void zero() {
         l0 = 0;
-        l2t = 0;
         for (int i = 0; i < 3; ++i) l1[i] = 0, s[i] = 0;
         for (int i = 0; i < 5; ++i) l2[i] = 0;
         for (int i = 0; i < 7; ++i) l3[i] = 0;
@@ -116,20 +117,24 @@ struct Acc {
             for (int i = 0; i < 3; ++i) s[i] += P(o.s[i]);
         if (full) {
             for (int i = 0; i < 5; ++i) l2[i] += P(o.l2[i]);
-            l2t += P(o.l2t);
             for (int i = 0; i < 7; ++i) l3[i] += P(o.l3[i]);
         }
     }
-    // the 19 output components (L2 diagonal with its trace term); the pair
-    // terms accumulate L2 (without the trace term) and L3 divided by -3, and
-    // the mixed components L2 xy xz yz and L3 xyz once more doubled
+    // the 19 output components: with P = l2[0], Q = l2[1] (mb e2 summed
+    // over XX - ZZ and YY - ZZ) and mb d1 = mb e2 r^2, L2 xx = mb e2 (r^2 -
+    // 3 XX) = Q - 2P and L2 yy = P - 2Q; L3 xxx = -(xyy + xzz) and
+    // yyy = -(xxy + yzz); the rest undo the factors -1/3 and 2
     __device__ __forceinline__ void out(double v[NLOC]) const {
         v[T_L0] = double(l0);
         for (int i = 0; i < 3; ++i) v[T_L1 + i] = double(l1[i]);
-        v[T_L2 + 0] = fma(-3.0, double(l2[0]), double(l2t));
-        v[T_L2 + 1] = fma(-3.0, double(l2[1]), double(l2t));
+        const double P2 = double(l2[0]), Q2 = double(l2[1]);
+        v[T_L2 + 0] = fma(-2.0, P2, Q2);
+        v[T_L2 + 1] = fma(-2.0, Q2, P2);
         for (int i = 2; i < 5; ++i) v[T_L2 + i] = -1.5 * double(l2[i]);
-        for (int i = 0; i < 7; ++i) v[T_L3 + i] = (i == 4 ? -1.5 : -3.0) * double(l3[i]);
+        v[T_L3 + 0] = 3.0 * (double(l3[3]) + double(l3[0]));
+        v[T_L3 + 5] = 3.0 * (double(l3[1]) + double(l3[5]));
+        for (int i : {1, 2, 3, 6}) v[T_L3 + i] = -3.0 * double(l3[i]);
+        v[T_L3 + 4] = -1.5 * double(l3[4]);
         for (int i = 0; i < 3; ++i) v[T_S + i] = double(s[i]);
     }
 };
@@ -198,27 +203,26 @@ __device__ __forceinline__ void pair_terms(P X, P Y, P Z, P mb, const P q[5], co
     a.l1[1] = fmaP(c1, Y, fmaP(e2, uy, a.l1[1]));
     a.l1[2] = fmaP(c1, Z, fmaP(e2, uz, a.l1[2]));
     if (FULL) {
+        // -1/3 of mb D2 and mb D3 in the forms of Acc
         const P md2 = mb * e2, md3 = mb * e3;
-        a.l2t = fmaP(mb, d1, a.l2t);
-        a.l2[0] = fmaP(md2, XX, a.l2[0]);
-        a.l2[1] = fmaP(md2, YY, a.l2[1]);
+        a.l2[0] = fmaP(md2, XmZ, a.l2[0]);
+        a.l2[1] = fmaP(md2, YmZ, a.l2[1]);
         a.l2[2] = fmaP(md2, XY2, a.l2[2]);
         a.l2[3] = fmaP(md2, XZ2, a.l2[3]);
         a.l2[4] = fmaP(md2, YZ2, a.l2[4]);
-        const P m3 = P(3) * md2;
-        const P bx = fmaP(md3, XX, md2), cy = fmaP(md3, YY, md2);
-        a.l3[0] = fmaP(X, fmaP(md3, XX, m3), a.l3[0]);
+        const P bx = fmaP(md3, XX, md2), cy = fmaP(md3, YY, md2), cz = fmaP(md3, ZZ, md2);
+        a.l3[0] = fmaP(X, cz, a.l3[0]);
         a.l3[1] = fmaP(Y, bx, a.l3[1]);
         a.l3[2] = fmaP(Z, bx, a.l3[2]);
         a.l3[3] = fmaP(X, cy, a.l3[3]);
         a.l3[4] = fmaP(md3 * XY2, Z, a.l3[4]);
-        a.l3[5] = fmaP(Y, fmaP(md3, YY, m3), a.l3[5]);
+        a.l3[5] = fmaP(Y, cz, a.l3[5]);
         a.l3[6] = fmaP(Z, cy, a.l3[6]);
     }
     // correction terms: always accumulated (no branch in the pair body); the
     // output scale of S is zero when the correction is off
     {
-        const P g4 = P(-7.0 / 3.0) * ir2 * e3;  // d4 / 9
+        const P g4 = P(-7.0 / 3.0) * ir2 * e3;  // -d4 / 9
         P Qx = wb[0], Qy = wb[1], Qz = wb[2];
         if (FULL) {
             P wa[3];
@@ -288,22 +292,20 @@ __device__ __forceinline__ void pair_terms_mix(double X, double Y, double Z, dou
     a.l1[2] = fmaP(c1, z, fmaP(f2, uz, a.l1[2]));
     if (FULL) {
         const float md2 = m * f2, md3 = m * f3;
-        const float xx = x * x, yy = y * y;
-        a.l2t = fmaP(m, f1, a.l2t);
-        a.l2[0] = fmaP(md2, xx, a.l2[0]);
-        a.l2[1] = fmaP(md2, yy, a.l2[1]);
+        const float xx = x * x, yy = y * y, zz = z * z;
+        a.l2[0] = fmaP(md2, xx - zz, a.l2[0]);
+        a.l2[1] = fmaP(md2, yy - zz, a.l2[1]);
         const float x2 = x + x;
         a.l2[2] = fmaP(md2, x2 * y, a.l2[2]);
         a.l2[3] = fmaP(md2, x2 * z, a.l2[3]);
         a.l2[4] = fmaP(md2, (y + y) * z, a.l2[4]);
-        const float m3 = 3.0f * md2;
-        const float bx = fmaP(md3, xx, md2), cy = fmaP(md3, yy, md2);
-        a.l3[0] = fmaP(x, fmaP(md3, xx, m3), a.l3[0]);
+        const float bx = fmaP(md3, xx, md2), cy = fmaP(md3, yy, md2), cz = fmaP(md3, zz, md2);
+        a.l3[0] = fmaP(x, cz, a.l3[0]);
         a.l3[1] = fmaP(y, bx, a.l3[1]);
         a.l3[2] = fmaP(z, bx, a.l3[2]);
         a.l3[3] = fmaP(x, cy, a.l3[3]);
         a.l3[4] = fmaP(md3 * x2 * y, z, a.l3[4]);
-        a.l3[5] = fmaP(y, fmaP(md3, yy, m3), a.l3[5]);
+        a.l3[5] = fmaP(y, cz, a.l3[5]);
         a.l3[6] = fmaP(z, cy, a.l3[6]);
     }
 }
