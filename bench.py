@@ -30,10 +30,15 @@ PEAK_FP64 = 78.6e12      # MI355X FP64 vector, FLOP/s
 PEAK_FP32_PACKED = 157.3e12  # MI355X FP32 vector with packed FP32 (not used by these kernels)
 PEAK_HBM = 8.0e12        # bytes/s
 
-# Arithmetic of one ordered pair in the kernels' formulation (FMA = 2 flop):
-FLOP_PAIR_REFINED = 203  # refined target: L0..L3 (order 3) + correction (79 FMA, 35 MUL, 9 ADD, 1 RSQ)
-FLOP_PAIR_LEAF_MP = 127  # leaf target, multipole source: L0, L1 + correction (45 FMA, 27 MUL, 9 ADD, 1 RSQ)
-FLOP_PAIR_MONO = 6       # leaf <- leaf monopole, lattice kernel tables: 3 FMA
+# Arithmetic of one ordered pair in the kernels' formulation (FMA = 2 flop),
+# counted in the compiled pair loops:
+FLOP_PAIR_REFINED = 196  # refined target: L0..L3 (order 3) + correction (77 FMA, 33 MUL, 8 ADD, 1 RSQ)
+FLOP_PAIR_LEAF_MP = 124  # leaf target, multipole source: L0, L1 + correction (45 FMA, 25 MUL, 8 ADD, 1 RSQ)
+# leaf <- leaf monopole with lattice kernel tables: per lane and sub-grid
+# 8 targets x 744 offsets; phi, the column sum and g_z cost 3 FMA per offset,
+# 2 ADD + 3 FMA per +-dz pair of offsets, 2 FMA at dz = 0, plus 2 FMA per
+# target and column for g_x, g_y: (8 x 3176 + 100 x 32) / 5952 = 4.8 flop
+FLOP_PAIR_MONO = 4.8
 
 
 def log(msg):
