@@ -120,6 +120,27 @@ def test_random_amr_fp64(seed, shape):
     assert f < 1e-13 and tq < 1e-13
 
 
+@pytest.mark.parametrize("shape", ["per_class_g1", "persistent_g1"])
+def test_batch_of_random_amr_trees_fp64(shape):
+    """Eight random AMR trees of two and three levels below the root in one
+    plan (captured and replayed by default): every cell of every tree
+    against the oracle, and every tree's force and torque at round-off."""
+    ws = [wl.small_amr(20 + i, max_level=2 + i % 2, p_refine=0.2 + 0.05 * i) for i in range(8)]
+    trees = [w.trees[0] for w in ws]
+    rho = np.concatenate([w.rho for w in ws])
+    phi, g, st = run(trees, rho, **SHAPES[shape])
+    off = 0
+    for w in ws:
+        n = w.n_leaves
+        pr, gr = oracle.solve(w.trees[0], w.rho)
+        errs = field_errors(phi[off:off + n], g[off:off + n], pr, gr)
+        f, tq = residuals(w.trees[0], w.rho, g[off:off + n])
+        print(f"  {w.name}: {n} leaves, errors {errs} force {f:.2e} torque {tq:.2e}", flush=True)
+        assert max(errs) < TOL64 and f < 1e-13 and tq < 1e-13
+        off += n
+    assert off == rho.shape[0] and st["n_trees"] == 8
+
+
 @pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
 def test_random_amr_deeper_fp64(shape):
     W = wl.small_amr(11, max_level=3, p_refine=0.3)
