@@ -86,6 +86,8 @@ int prec_form(fmmg_precision pr) {
     return pr == FMMG_MIXED ? PR_MIX : pr == FMMG_MIXED_F32 ? PR_F32 : PR_F64;
 }
 constexpr int MAX_LAUNCH_STREAMS = 128;  // stream pool of the per-sub-grid launch model
+constexpr int COUNTER_STRIDE = 16;  // ints per branch of the persistent-launch counters (>= NQUEUE + 1)
+static_assert(COUNTER_STRIDE >= NQUEUE + 1, "persistent-launch counters");
 
 }  // namespace
 
@@ -99,7 +101,7 @@ struct fmmg_ws {
     double* Lf = nullptr;     // [n_leaf][4][512]
     double* Lf3 = nullptr;    // [n_slot3][4][512]
     double* part = nullptr;   // [top partial slots][19][512]
-    int* counter = nullptr;   // two persistent-launch counter pairs (4 ints)
+    int* counter = nullptr;   // persistent-launch counters: NQUEUE + 1 per branch, COUNTER_STRIDE apart
 };
 
 struct fmmg_plan {
@@ -335,7 +337,9 @@ int64_t enqueue_solve(fmmg_plan* p, const fmmg_ws& w, const double* rho, double*
     auto fused = [&](const Ctx& x, int br) {
         const int n = hp.lpt_begin[br + 1] - hp.lpt_begin[br];
         const int grid = br == 0 ? p->shape.blocks_per_cu * p->n_cu : p->n_cu;
-        launch_persist(x, p->d_items_lpt + hp.lpt_begin[br], n, grid, w.counter + 2 * br);
+        Queues qs;
+        for (int q = 0; q <= NQUEUE; ++q) qs.begin[q] = hp.queue_begin[br][q] - hp.lpt_begin[br];
+        launch_persist(x, p->d_items_lpt + hp.lpt_begin[br], qs, grid, w.counter + COUNTER_STRIDE * br);
         cnt(n);
     };
     auto items = [&](const Ctx& x, int br) {
@@ -785,9 +789,9 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         AL(p->ws.Lf3, size_t(hp.n_slot3) * NLEAF * NCELL, "leaf terms from refined sources");
         AL(p->ws.part, size_t(hp.n_top_parts) * NLOC * NCELL, "top partial sums");
 #undef AL
-        e = hipMalloc(reinterpret_cast<void**>(&p->ws.counter), 4 * sizeof(int));
+        e = hipMalloc(reinterpret_cast<void**>(&p->ws.counter), 2 * COUNTER_STRIDE * sizeof(int));
         if (e != hipSuccess) { release(p); return fail(FMMG_ENOMEM, "hipMalloc counter"); }
-        e = hipMemsetAsync(p->ws.counter, 0, 4 * sizeof(int), st);
+        e = hipMemsetAsync(p->ws.counter, 0, 2 * COUNTER_STRIDE * sizeof(int), st);
         if (e != hipSuccess) { release(p); return hip_fail(e, "counter clear"); }
         // the zero record after the last refined cell (read for leaf and
         // absent source cells when a plane window is staged)

@@ -90,6 +90,7 @@ struct SubDev {
 // Same-level work items.  A block of 256 threads (4 waves) runs one item.
 enum { IT_MP_REF = 0, IT_MP_LEAF = 1, IT_MONO = 2, IT_TOP = 3, IT_KINDS = 4 };
 constexpr int MAX_GROUPS = 5;   // source-plane groups of a refined-target item (of the 10 canonical dz)
+constexpr int NQUEUE = 8;       // persistent-launch queues: one per XCD of the MI355X
 struct Item {
     int32_t kind;
     int32_t sub;   // target sub-grid (IT_TOP: index into the top items)

@@ -1342,26 +1342,34 @@ __global__ __launch_bounds__(256) void k_class(Ctx cx, const Item* __restrict__ 
     else top_item<PR>(cx, cx.top_items[it.sub], smem);
 }
 
-// Persistent launch over a list of items: each block takes the next item of
-// the (largest-first) list from ctr[0] until the list is exhausted, so every
-// block exits once all items are taken.  The last block to exit re-arms
-// ctr[0] and ctr[1] (both zero before the first launch) for the next launch.
+// Persistent launch over NQUEUE item queues, one per XCD: the blocks of a
+// launch are dealt to the XCDs in turn, so block b starts on queue b % NQUEUE
+// (a compact region of the octree whose source records its XCD's L2 keeps),
+// taking the next item from ctr[q] until the queue is exhausted, then helps
+// with the other queues in turn.  Every block passes each queue once, so it
+// exits once all items are taken; the last block to exit (counted in
+// ctr[NQUEUE]) re-arms all NQUEUE + 1 counters (zero before the first launch)
+// for the next launch.
 template <int PR>
-__global__ __launch_bounds__(256, 3) void k_persist(Ctx cx, const Item* __restrict__ items, int n,
+__global__ __launch_bounds__(256, 3) void k_persist(Ctx cx, const Item* __restrict__ items, Queues qs,
                                                     int* __restrict__ ctr) {
     __shared__ __attribute__((aligned(16))) unsigned char smem[SmemPR<PR>::BYTES];
     __shared__ int s_it;
-    for (;;) {
-        if (threadIdx.x == 0) s_it = atomicAdd(&ctr[0], 1);
-        __syncthreads();
-        const int it = s_it;
-        __syncthreads();
-        if (it >= n) break;
-        run_item<PR>(cx, items[it], smem);
+    const int home = int(blockIdx.x % NQUEUE);
+    for (int r = 0; r < NQUEUE; ++r) {
+        const int q = (home + r) % NQUEUE;
+        const int b = qs.begin[q], e = qs.begin[q + 1];
+        for (;;) {
+            if (threadIdx.x == 0) s_it = b < e ? b + atomicAdd(&ctr[q], 1) : e;
+            __syncthreads();
+            const int it = s_it;
+            __syncthreads();
+            if (it >= e) break;
+            run_item<PR>(cx, items[it], smem);
+        }
     }
-    if (threadIdx.x == 0 && atomicAdd(&ctr[1], 1) == int(gridDim.x) - 1) {
-        atomicExch(&ctr[0], 0);
-        atomicExch(&ctr[1], 0);
+    if (threadIdx.x == 0 && atomicAdd(&ctr[NQUEUE], 1) == int(gridDim.x) - 1) {
+        for (int q = 0; q <= NQUEUE; ++q) atomicExch(&ctr[q], 0);
     }
 }
 
@@ -1600,14 +1608,15 @@ void launch_class(const Ctx& a, int kind, const Item* items, int n) {
     }
 }
 
-void launch_persist(const Ctx& a, const Item* items, int n, int grid, int* ctr) {
+void launch_persist(const Ctx& a, const Item* items, const Queues& qs, int grid, int* ctr) {
+    const int n = qs.begin[NQUEUE];
     if (n <= 0 || grid <= 0) return;
     if (grid > n) grid = n;
     if (a.prec == PR_MIX)
-        hipLaunchKernelGGL((k_persist<PR_MIX>), dim3(grid), dim3(256), 0, a.st, a, items, n, ctr);
+        hipLaunchKernelGGL((k_persist<PR_MIX>), dim3(grid), dim3(256), 0, a.st, a, items, qs, ctr);
     else if (a.prec == PR_F32)
-        hipLaunchKernelGGL((k_persist<PR_F32>), dim3(grid), dim3(256), 0, a.st, a, items, n, ctr);
-    else hipLaunchKernelGGL((k_persist<PR_F64>), dim3(grid), dim3(256), 0, a.st, a, items, n, ctr);
+        hipLaunchKernelGGL((k_persist<PR_F32>), dim3(grid), dim3(256), 0, a.st, a, items, qs, ctr);
+    else hipLaunchKernelGGL((k_persist<PR_F64>), dim3(grid), dim3(256), 0, a.st, a, items, qs, ctr);
 }
 
 int persist_blocks_per_cu(int prec) {

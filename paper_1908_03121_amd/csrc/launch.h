@@ -50,8 +50,13 @@ void launch_m2m(const Ctx& a, const int32_t* list, int n);
 // parents whose 8 children are all leaves: one block per parent
 void launch_m2m_leafpar(const Ctx& a, const int32_t* list, int n);
 void launch_class(const Ctx& a, int kind, const Item* items, int n);
-// ctr: two ints, zero before the first launch and re-armed by each launch
-void launch_persist(const Ctx& a, const Item* items, int n, int grid, int* ctr);
+// The item queues of a persistent launch: queue q is items [begin[q],
+// begin[q + 1]) (offsets into the launch's list; begin[0] = 0).
+struct Queues {
+    int32_t begin[NQUEUE + 1];
+};
+// ctr: NQUEUE + 1 ints, zero before the first launch and re-armed by each launch
+void launch_persist(const Ctx& a, const Item* items, const Queues& qs, int grid, int* ctr);
 int persist_blocks_per_cu(int prec);
 void launch_l2l(const Ctx& a, const int32_t* tasks, int n, int parent_mode, double* phi, double* g);
 void launch_leaf_out(const Ctx& a, const int32_t* list, int n, double* phi, double* g);

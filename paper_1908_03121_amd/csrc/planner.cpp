@@ -538,12 +538,64 @@ void build_items(HostPlan* Pp, int ngroups, bool split) {
         }
         P.class_begin[b][IT_KINDS] = int32_t(P.items_class.size());
     }
-    std::stable_sort(all.begin(), all.end(), [](const Costed& a, const Costed& b) { return a.cost > b.cost; });
+    // persistent lists: per branch, NQUEUE queues, one per XCD (the blocks of
+    // a persistent launch are dealt to the XCDs in turn, and each XCD has its
+    // own L2).  Items in the order of their target sub-grid along a Z-order
+    // curve (tree by tree, positions scaled to the finest level), so that a
+    // queue holds a compact region whose source records stay in its XCD's
+    // L2, cut into NQUEUE runs of equal estimated cost; top-level items lead
+    // their run, the small monopole items trail it (a short tail).
+    // (19 bits per axis below the tree index: the coarsest bits are kept for
+    // deep trees; the key orders only, so a lost bit costs locality, not
+    // correctness)
+    int lmax = 0, c0max = 1;
+    for (const SubDev& S : P.subs) {
+        lmax = std::max(lmax, int(S.level));
+        if (S.level == 0)
+            for (int a = 0; a < 3; ++a) c0max = std::max(c0max, int(S.coord[a]) + 1);
+    }
+    int top_bits = 0;  // bits of a level-0 coordinate
+    while ((1 << top_bits) < c0max) ++top_bits;
+    const int nbits = lmax + top_bits, drop = nbits > 19 ? nbits - 19 : 0;
+    auto zkey = [&](const Costed& c) -> uint64_t {
+        if (c.it.kind == IT_TOP) return 0;
+        const SubDev& S = P.subs[size_t(c.it.sub)];
+        uint64_t x[3];
+        for (int a = 0; a < 3; ++a) x[a] = (uint64_t(uint32_t(S.coord[a])) << (lmax - S.level)) >> drop;
+        uint64_t k = 0;
+        for (int bit = nbits - drop - 1; bit >= 0; --bit)
+            for (int a = 0; a < 3; ++a) k = (k << 1) | ((x[a] >> bit) & 1);
+        return (uint64_t(uint32_t(S.tree) & 63) << 57) | k;
+    };
+    std::vector<std::pair<uint64_t, size_t>> order;
+    order.reserve(all.size());
+    for (size_t i = 0; i < all.size(); ++i) order.push_back({zkey(all[i]), i});
+    std::stable_sort(order.begin(), order.end());
     P.items_lpt.clear();
     for (int b = 0; b < 2; ++b) {
         P.lpt_begin[b] = int32_t(P.items_lpt.size());
-        for (const Costed& c : all)
-            if (branch(c) == b) P.items_lpt.push_back(c.it);
+        double total = 0;
+        for (const auto& o : order)
+            if (branch(all[o.second]) == b) total += all[o.second].cost;
+        std::vector<size_t> run[NQUEUE];
+        double acc = 0;
+        for (const auto& o : order) {
+            const Costed& c = all[o.second];
+            if (branch(c) != b) continue;
+            int q = total > 0 ? int(acc / total * NQUEUE) : 0;
+            if (q >= NQUEUE) q = NQUEUE - 1;
+            run[q].push_back(o.second);
+            acc += c.cost;
+        }
+        for (int q = 0; q < NQUEUE; ++q) {
+            P.queue_begin[b][q] = int32_t(P.items_lpt.size());
+            for (int pass = 0; pass < 3; ++pass)
+                for (size_t i : run[q]) {
+                    const int k = all[i].it.kind;
+                    if ((pass == 0) == (k == IT_TOP) && (pass == 2) == (k == IT_MONO)) P.items_lpt.push_back(all[i].it);
+                }
+        }
+        P.queue_begin[b][NQUEUE] = int32_t(P.items_lpt.size());
     }
     P.lpt_begin[2] = int32_t(P.items_lpt.size());
 }

@@ -5,6 +5,8 @@
 // Built with g++ and AddressSanitizer / UndefinedBehaviorSanitizer; no GPU.
 #include "planner.hpp"
 
+#include <algorithm>
+#include <array>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -43,7 +45,31 @@ int main(int argc, char** argv) {
                 return 1;
             }
             for (int g = 1; g <= MAX_GROUPS; ++g)
-                for (int split = 0; split < 2; ++split) build_items(&hp, g, split != 0);
+                for (int split = 0; split < 2; ++split) {
+                    build_items(&hp, g, split != 0);
+                    // the persistent queues of each branch partition it, and
+                    // hold the same items as the per-class lists
+                    for (int b = 0; b < 2; ++b) {
+                        bool ok = hp.queue_begin[b][0] == hp.lpt_begin[b] &&
+                                  hp.queue_begin[b][NQUEUE] == hp.lpt_begin[b + 1];
+                        for (int q = 0; q < NQUEUE; ++q) ok = ok && hp.queue_begin[b][q] <= hp.queue_begin[b][q + 1];
+                        std::vector<std::array<int32_t, 4>> a, c;
+                        for (int32_t i = hp.lpt_begin[b]; i < hp.lpt_begin[b + 1]; ++i) {
+                            const Item& it = hp.items_lpt[size_t(i)];
+                            a.push_back({it.kind, it.sub, it.a, it.b});
+                        }
+                        for (int32_t i = hp.class_begin[b][0]; i < hp.class_begin[b][IT_KINDS]; ++i) {
+                            const Item& it = hp.items_class[size_t(i)];
+                            c.push_back({it.kind, it.sub, it.a, it.b});
+                        }
+                        std::sort(a.begin(), a.end());
+                        std::sort(c.begin(), c.end());
+                        if (!ok || a != c) {
+                            printf("%s persistent queues wrong (groups %d split %d branch %d)\n", name, g, split, b);
+                            return 1;
+                        }
+                    }
+                }
             // class-4 items: each leaf's refined neighbours covered exactly
             // once, in slot order, by its own consecutive Lf3 slots
             std::vector<int> covered(hp.subs.size() * 27, 0);
