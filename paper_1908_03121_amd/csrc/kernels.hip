@@ -1332,7 +1332,11 @@ __global__ __launch_bounds__(256) void k_class(Ctx cx, const Item* __restrict__ 
     // the monopole class of the mixed form uses FP32 masses, as PR_F32 does
     using L = SmemPR<(KIND == IT_MONO && PR == PR_MIX) ? PR_F32 : PR>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[L::BYTES];
-    const Item it = items[blockIdx.x];
+    // blocks are dealt to the NQUEUE XCDs in turn: XCD x runs a contiguous
+    // run of the list (neighbouring sub-grids, shared sources in its L2)
+    const int nb = int(gridDim.x), b = int(blockIdx.x);
+    const int per = nb / NQUEUE, rem = nb % NQUEUE, x = b % NQUEUE;
+    const Item it = items[x * per + (x < rem ? x : rem) + b / NQUEUE];
     if (KIND == IT_MP_REF) {
         if (it.b >> 3) mp_item<PR, 1>(cx, it.sub, it.a, it.b & 7, smem);
         else mp_item<PR, 0>(cx, it.sub, it.a, it.b & 7, smem);
