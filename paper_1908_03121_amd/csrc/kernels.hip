@@ -733,11 +733,11 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         if (!any) continue;
         __syncthreads();
         // stage the 18x18 source window of plane zs: each thread takes up to
-        // two cells and issues all loads of a cell at once (record and mass
+        // two cells and issues the loads of both at once (record and mass
         // loads are unconditional, from a valid address, and then selected)
         {
             const int lz = zs - NS * oz;
-#pragma unroll 1
+#pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const int cr = t + u * 256;
                 if (cr < PCELLS) {
