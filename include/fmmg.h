@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define FMMG_VERSION 3
+#define FMMG_VERSION 4
 
 typedef struct fmmg_plan fmmg_plan; /* opaque; owns device tables and workspaces */
 
@@ -118,7 +118,7 @@ typedef struct {
                                    0 = the occupancy limit                              */
     int32_t autotune;           /* 1 = the first solve times the candidate launch shapes
                                    (per-class or persistent, plane groups, blocks per
-                                   CU, overlap) on the caller's data, each run as the
+                                   CU, overlap, item queues) on the caller's data, each run as the
                                    plan will run it (captured and replayed when
                                    use_graph is set), keeps the fastest, and records
                                    it in tuning_cache; that solve synchronises the
@@ -148,6 +148,13 @@ typedef struct {
                                    autotune are not allowed.  Results are bitwise equal
                                    to those of the default shapes with the same
                                    plane_groups.                                        */
+    int32_t xcd_queues;         /* persistent launch: 1 (default) = one item queue per
+                                   XCD, each a compact region of the octrees (items in
+                                   space-filling-curve order, cut into runs of equal
+                                   estimated cost), a block starting on its own XCD's
+                                   queue and helping the others once it is drained;
+                                   0 = one list, largest estimated cost first.  With
+                                   autotune both are tried.  Results are bitwise equal. */
 } fmmg_options;
 
 /* Stages of one solve, in launch order. */
@@ -181,6 +188,7 @@ typedef struct {
     int32_t split_level;        /* levels below this one form the coarse branch        */
     int32_t launch_streams;     /* streams of the per-sub-grid launch model, or 0      */
     int32_t use_graph;          /* 1 if solves are captured and replayed as a hipGraph */
+    int32_t xcd_queues;         /* persistent launch: 1 = one item queue per XCD        */
 } fmmg_launch_shape;
 
 typedef struct {

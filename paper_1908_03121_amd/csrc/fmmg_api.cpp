@@ -125,6 +125,7 @@ struct fmmg_plan {
     TopReduce* d_top_reduce = nullptr;
     Item* d_items_class = nullptr;
     Item* d_items_lpt = nullptr;
+    Item* d_items_xcd = nullptr;
     size_t items_capacity = 0;
     fmmg_ws ws;                            // plan-owned workspaces
     unsigned long long* d_bad = nullptr;   // fmmg_check_density's result
@@ -170,7 +171,7 @@ void release(fmmg_plan* p) {
     if (!p) return;
     drop_graph(p);
     void* bufs[] = {p->d_subs, p->d_leaf_sub, p->d_ref_by_level, p->d_top_leaf, p->d_l2l_tasks,
-                    p->d_top_src, p->d_top_items, p->d_top_reduce, p->d_items_class, p->d_items_lpt,
+                    p->d_top_src, p->d_top_items, p->d_top_reduce, p->d_items_class, p->d_items_lpt, p->d_items_xcd,
                     p->ws.counter, p->ws.mass, p->ws.rec, p->ws.com, p->ws.Lp, p->ws.Lr, p->ws.Lf, p->ws.Lf3,
                     p->ws.part, p->d_bad, p->d_rho_bad};
     for (void* b : bufs)
@@ -254,7 +255,9 @@ void build_runs(fmmg_plan* p) {
     for (const Keyed& k : v) p->runs.push_back(k.r);
 }
 
-fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int overlap, hipStream_t st) {
+fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int overlap, int queues,
+                        hipStream_t st) {
+    if (queues != 0 && queues != 1) return fail(FMMG_EINVAL, "xcd_queues must be 0 or 1");
     if (groups < 1 || groups > p->max_groups)
         return fail(FMMG_EINVAL, "plane_groups must be 1.." + std::to_string(p->max_groups) + " for this plan");
     if (bpc < 0) return fail(FMMG_EINVAL, "blocks_per_cu must be >= 0");
@@ -270,13 +273,15 @@ fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int o
                                    p->hp.items_class.size() * sizeof(Item), hipMemcpyHostToDevice, st), "item upload");
             HIP_TRY(hipMemcpyAsync(p->d_items_lpt, p->hp.items_lpt.data(),
                                    p->hp.items_lpt.size() * sizeof(Item), hipMemcpyHostToDevice, st), "item upload");
+            HIP_TRY(hipMemcpyAsync(p->d_items_xcd, p->hp.items_xcd.data(),
+                                   p->hp.items_xcd.size() * sizeof(Item), hipMemcpyHostToDevice, st), "item upload");
         }
         HIP_TRY(hipStreamSynchronize(st), "item upload");
         build_runs(p);
     }
     if (p->hp.split == 0) overlap = 0;
     if (p->shape.persistent != persistent || p->shape.plane_groups != groups || p->shape.blocks_per_cu != bpc ||
-        p->shape.overlap != overlap)
+        p->shape.overlap != overlap || p->shape.xcd_queues != queues)
         drop_graph(p);
     p->shape.persistent = persistent;
     p->shape.plane_groups = groups;
@@ -285,6 +290,7 @@ fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int o
     p->shape.split_level = p->hp.split;
     p->shape.launch_streams = int32_t(p->pool.size());
     p->shape.use_graph = p->opt.use_graph ? 1 : 0;
+    p->shape.xcd_queues = queues;
     return FMMG_OK;
 }
 
@@ -337,9 +343,13 @@ int64_t enqueue_solve(fmmg_plan* p, const fmmg_ws& w, const double* rho, double*
     auto fused = [&](const Ctx& x, int br) {
         const int n = hp.lpt_begin[br + 1] - hp.lpt_begin[br];
         const int grid = br == 0 ? p->shape.blocks_per_cu * p->n_cu : p->n_cu;
+        // one queue per XCD, or the largest-first list as queue 0 (blocks
+        // whose own queue is empty move on to it)
         Queues qs;
-        for (int q = 0; q <= NQUEUE; ++q) qs.begin[q] = hp.queue_begin[br][q] - hp.lpt_begin[br];
-        launch_persist(x, p->d_items_lpt + hp.lpt_begin[br], qs, grid, w.counter + COUNTER_STRIDE * br);
+        const bool xq = p->shape.xcd_queues != 0;
+        for (int q = 0; q <= NQUEUE; ++q) qs.begin[q] = xq ? hp.queue_begin[br][q] - hp.lpt_begin[br] : (q ? n : 0);
+        launch_persist(x, (xq ? p->d_items_xcd : p->d_items_lpt) + hp.lpt_begin[br], qs, grid,
+                       w.counter + COUNTER_STRIDE * br);
         cnt(n);
     };
     auto items = [&](const Ctx& x, int br) {
@@ -484,8 +494,10 @@ std::string signature(const fmmg_plan* p) {
 }
 
 // Cache file: a JSON object, one entry per line:
-//   "signature": {"persistent": P, "plane_groups": G, "blocks_per_cu": B, "overlap": O, "ms": T},
-bool cache_lookup(const char* path, const std::string& sig, int* pers, int* groups, int* bpc, int* ovl) {
+//   "signature": {"persistent": P, "plane_groups": G, "blocks_per_cu": B, "overlap": O,
+//                 "xcd_queues": Q, "ms": T},
+bool cache_lookup(const char* path, const std::string& sig, int* pers, int* groups, int* bpc, int* ovl,
+                  int* queues) {
     if (!path) return false;
     std::ifstream f(path);
     if (!f) return false;
@@ -493,23 +505,27 @@ bool cache_lookup(const char* path, const std::string& sig, int* pers, int* grou
     while (std::getline(f, line)) {
         size_t at = line.find(key);
         if (at == std::string::npos) continue;
-        int a = -1, b = -1, c = -1, d = -1;
+        int a = -1, b = -1, c = -1, d = -1, q = -1;
         const char* s = line.c_str() + at + key.size();
-        if (std::sscanf(s, " {\"persistent\": %d, \"plane_groups\": %d, \"blocks_per_cu\": %d, \"overlap\": %d",
-                        &a, &b, &c, &d) == 4 &&
-            (a == 0 || a == 1) && b >= 1 && b <= MAX_GROUPS && c >= 0 && d >= 0 && d <= 2) {
+        if (std::sscanf(s,
+                        " {\"persistent\": %d, \"plane_groups\": %d, \"blocks_per_cu\": %d, \"overlap\": %d, "
+                        "\"xcd_queues\": %d",
+                        &a, &b, &c, &d, &q) == 5 &&
+            (a == 0 || a == 1) && b >= 1 && b <= MAX_GROUPS && c >= 0 && d >= 0 && d <= 2 && (q == 0 || q == 1)) {
             // (a group count above the plan's buffers is rejected by apply_shape)
             *pers = a;
             *groups = b;
             *bpc = c;
             *ovl = d;
+            *queues = q;
             return true;
         }
     }
     return false;
 }
 
-void cache_store(const char* path, const std::string& sig, int pers, int groups, int bpc, int ovl, double ms) {
+void cache_store(const char* path, const std::string& sig, int pers, int groups, int bpc, int ovl, int queues,
+                 double ms) {
     if (!path) return;
     std::vector<std::string> keep;
     {
@@ -525,8 +541,8 @@ void cache_store(const char* path, const std::string& sig, int pers, int groups,
     char buf[512];
     std::snprintf(buf, sizeof(buf),
                   "  \"%s\": {\"persistent\": %d, \"plane_groups\": %d, \"blocks_per_cu\": %d, \"overlap\": %d, "
-                  "\"ms\": %.6f}",
-                  sig.c_str(), pers, groups, bpc, ovl, ms);
+                  "\"xcd_queues\": %d, \"ms\": %.6f}",
+                  sig.c_str(), pers, groups, bpc, ovl, queues, ms);
     keep.push_back(buf);
     std::string tmp = std::string(path) + ".tmp";
     {
@@ -540,24 +556,25 @@ void cache_store(const char* path, const std::string& sig, int pers, int groups,
 }
 
 fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStream_t st) {
-    int pers = 0, groups = 0, bpc = 0, ovl = 0;
+    int pers = 0, groups = 0, bpc = 0, ovl = 0, queues = 1;
     const std::string sig = signature(p);
-    if (cache_lookup(p->opt.tuning_cache, sig, &pers, &groups, &bpc, &ovl)) {
-        fmmg_status s = apply_shape(p, pers, groups, bpc, ovl, st);
+    if (cache_lookup(p->opt.tuning_cache, sig, &pers, &groups, &bpc, &ovl, &queues)) {
+        fmmg_status s = apply_shape(p, pers, groups, bpc, ovl, queues, st);
         if (s != FMMG_OK) return s;
         p->shape.from_cache = 1;
         p->tuned = true;
         return FMMG_OK;
     }
-    struct Cand { int pers, groups, bpc, ovl; };
+    struct Cand { int pers, groups, bpc, ovl, queues; };
     std::vector<Cand> cands;
     const int max_ov = p->hp.split_natural > 0 ? p->opt.overlap : 0;
     for (int ov = 0; ov <= max_ov; ++ov)
         for (int gr : {1, 2, 3, 5}) {
             if (gr > p->max_groups) continue;
-            cands.push_back({0, gr, 0, ov});
+            cands.push_back({0, gr, 0, ov, p->opt.xcd_queues});
             if (ov == 2) continue;  // the third stream applies to per-class launches only
-            for (int b = 1; b <= p->max_bpc; ++b) cands.push_back({1, gr, b, ov});
+            for (int b = 1; b <= p->max_bpc; ++b)
+                for (int q : {1, 0}) cands.push_back({1, gr, b, ov, q});
         }
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
@@ -581,7 +598,7 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
     // uses graphs, else eager launches; it is timed as the best of 3 runs of
     // enough solves to last about 1 ms
     for (const Cand& c : cands) {
-        status = apply_shape(p, c.pers, c.groups, c.bpc, c.ovl, st);
+        status = apply_shape(p, c.pers, c.groups, c.bpc, c.ovl, c.queues, st);
         if (status != FMMG_OK) break;
         hipGraph_t cg = nullptr;
         hipGraphExec_t ce = nullptr;
@@ -645,7 +662,7 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
         if (best_cg) (void)hipGraphDestroy(best_cg);
     };
     if (status != FMMG_OK) { drop_best(); return status; }
-    status = apply_shape(p, bc.pers, bc.groups, bc.bpc, bc.ovl, st);
+    status = apply_shape(p, bc.pers, bc.groups, bc.bpc, bc.ovl, bc.queues, st);
     if (status != FMMG_OK) { drop_best(); return status; }
     if (best_ce) {
         drop_graph(p);
@@ -659,7 +676,8 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
     p->shape.from_cache = 0;
     p->shape.tuned_ms = best;
     p->tuned = true;
-    cache_store(p->opt.tuning_cache, sig, bc.pers, bc.groups, p->shape.blocks_per_cu, p->shape.overlap, best);
+    cache_store(p->opt.tuning_cache, sig, bc.pers, bc.groups, p->shape.blocks_per_cu, p->shape.overlap, bc.queues,
+                best);
     return FMMG_OK;
 }
 
@@ -686,6 +704,7 @@ void fmmg_default_options(fmmg_options* opt) {
     opt->autotune = 0;
     opt->tuning_cache = nullptr;
     opt->overlap = 1;
+    opt->xcd_queues = 1;
 }
 
 fmmg_status fmmg_count_pairs(const fmmg_tree_desc* trees, int32_t n_trees, fmmg_top_mode top_mode,
@@ -741,6 +760,7 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         else if (o.launch_streams < 0 || o.launch_streams > MAX_LAUNCH_STREAMS) bad = "launch_streams must be 0..128";
         else if (o.launch_streams && o.timing) bad = "timing needs launch_streams = 0";
         else if (o.launch_streams && o.autotune) bad = "autotune needs launch_streams = 0";
+        else if (o.xcd_queues != 0 && o.xcd_queues != 1) bad = "xcd_queues must be 0 or 1";
         if (!bad.empty()) { release(p); return fail(FMMG_EINVAL, bad); }
         hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
         hipError_t e = hipGetDevice(&p->device);
@@ -777,6 +797,7 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         UP(p->d_top_reduce, hp.top_reduce, 0, "top reductions");
         UP(p->d_items_class, std::vector<Item>(), p->items_capacity, "work items");
         UP(p->d_items_lpt, std::vector<Item>(), p->items_capacity, "work items");
+        UP(p->d_items_xcd, std::vector<Item>(), p->items_capacity, "work items");
 #undef UP
         size_t nl = hp.leaf_sub.size(), nr = hp.ref_sub.size();
 #define AL(dst, n, what) if ((s = dev_alloc(&(dst), (n), what)) != FMMG_OK) { release(p); return s; }
@@ -843,7 +864,7 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         p->hp.ngroups = 0;  // force the first item upload
         memset(&p->shape, 0, sizeof(p->shape));
         s = apply_shape(p, o.persistent ? 1 : 0, o.plane_groups ? o.plane_groups : 2, o.blocks_per_cu,
-                        o.overlap, st);
+                        o.overlap, o.xcd_queues, st);
         if (s != FMMG_OK) { release(p); return s; }
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) { release(p); return hip_fail(e, "plan upload"); }

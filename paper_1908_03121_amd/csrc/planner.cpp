@@ -571,9 +571,8 @@ void build_items(HostPlan* Pp, int ngroups, bool split) {
     order.reserve(all.size());
     for (size_t i = 0; i < all.size(); ++i) order.push_back({zkey(all[i]), i});
     std::stable_sort(order.begin(), order.end());
-    P.items_lpt.clear();
+    P.items_xcd.clear();
     for (int b = 0; b < 2; ++b) {
-        P.lpt_begin[b] = int32_t(P.items_lpt.size());
         double total = 0;
         for (const auto& o : order)
             if (branch(all[o.second]) == b) total += all[o.second].cost;
@@ -588,14 +587,23 @@ void build_items(HostPlan* Pp, int ngroups, bool split) {
             acc += c.cost;
         }
         for (int q = 0; q < NQUEUE; ++q) {
-            P.queue_begin[b][q] = int32_t(P.items_lpt.size());
+            P.queue_begin[b][q] = int32_t(P.items_xcd.size());
             for (int pass = 0; pass < 3; ++pass)
                 for (size_t i : run[q]) {
                     const int k = all[i].it.kind;
-                    if ((pass == 0) == (k == IT_TOP) && (pass == 2) == (k == IT_MONO)) P.items_lpt.push_back(all[i].it);
+                    if ((pass == 0) == (k == IT_TOP) && (pass == 2) == (k == IT_MONO)) P.items_xcd.push_back(all[i].it);
                 }
         }
-        P.queue_begin[b][NQUEUE] = int32_t(P.items_lpt.size());
+        P.queue_begin[b][NQUEUE] = int32_t(P.items_xcd.size());
+    }
+    // the single list: largest estimated cost first
+    std::vector<Costed> lpt = all;
+    std::stable_sort(lpt.begin(), lpt.end(), [](const Costed& a, const Costed& b) { return a.cost > b.cost; });
+    P.items_lpt.clear();
+    for (int b = 0; b < 2; ++b) {
+        P.lpt_begin[b] = int32_t(P.items_lpt.size());
+        for (const Costed& c : lpt)
+            if (branch(c) == b) P.items_lpt.push_back(c.it);
     }
     P.lpt_begin[2] = int32_t(P.items_lpt.size());
 }

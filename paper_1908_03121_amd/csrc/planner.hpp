@@ -64,11 +64,13 @@ struct HostPlan {
     int32_t sweep_y_targets = 0;       // refined targets whose plane items run along y
     std::vector<Item> items_class;     // grouped by branch, then kind, in list order
     int32_t class_begin[2][IT_KINDS + 1] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
-    // persistent lists: branch 0 then branch 1, each cut into NQUEUE queues
-    // (one per XCD, see persist_queues) of about equal estimated cost
+    // persistent lists, branch 0 then branch 1 (the same items per branch in
+    // both): items_lpt largest estimated cost first; items_xcd cut into
+    // NQUEUE queues, one per XCD, of about equal estimated cost
     std::vector<Item> items_lpt;
-    int32_t lpt_begin[3] = {0, 0, 0};
-    int32_t queue_begin[2][NQUEUE + 1] = {};  // queue q of branch b: [queue_begin[b][q], [q + 1]) in items_lpt
+    std::vector<Item> items_xcd;
+    int32_t lpt_begin[3] = {0, 0, 0};  // branch b: [lpt_begin[b], lpt_begin[b + 1]) in both lists
+    int32_t queue_begin[2][NQUEUE + 1] = {};  // queue q of branch b: [queue_begin[b][q], [q + 1]) in items_xcd
 
     // top level under the all-pairs rule
     std::vector<int32_t> top_src;      // per tree, its level-0 sub ids (concatenated)

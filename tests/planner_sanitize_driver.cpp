@@ -53,18 +53,21 @@ int main(int argc, char** argv) {
                         bool ok = hp.queue_begin[b][0] == hp.lpt_begin[b] &&
                                   hp.queue_begin[b][NQUEUE] == hp.lpt_begin[b + 1];
                         for (int q = 0; q < NQUEUE; ++q) ok = ok && hp.queue_begin[b][q] <= hp.queue_begin[b][q + 1];
-                        std::vector<std::array<int32_t, 4>> a, c;
+                        std::vector<std::array<int32_t, 4>> a, x, c;
                         for (int32_t i = hp.lpt_begin[b]; i < hp.lpt_begin[b + 1]; ++i) {
                             const Item& it = hp.items_lpt[size_t(i)];
                             a.push_back({it.kind, it.sub, it.a, it.b});
+                            const Item& jt = hp.items_xcd[size_t(i)];
+                            x.push_back({jt.kind, jt.sub, jt.a, jt.b});
                         }
                         for (int32_t i = hp.class_begin[b][0]; i < hp.class_begin[b][IT_KINDS]; ++i) {
                             const Item& it = hp.items_class[size_t(i)];
                             c.push_back({it.kind, it.sub, it.a, it.b});
                         }
                         std::sort(a.begin(), a.end());
+                        std::sort(x.begin(), x.end());
                         std::sort(c.begin(), c.end());
-                        if (!ok || a != c) {
+                        if (!ok || a != c || x != c) {
                             printf("%s persistent queues wrong (groups %d split %d branch %d)\n", name, g, split, b);
                             return 1;
                         }

@@ -625,6 +625,29 @@ def test_density_check_and_argument_errors():
         assert max(field_errors(phi.cpu().numpy(), g.cpu().numpy(), pr, gr)) < TOL64
 
 
+@pytest.mark.parametrize("bpc", [3, 1])
+def test_xcd_queues_and_single_list_are_bitwise_equal(bpc):
+    """The persistent launch's two item orders (one queue per XCD, or one
+    largest-first list) run the same items, each output written by one item
+    in a fixed order: bitwise equal results, in a graph and eagerly, on the
+    batch of 16 binary-star trees and on one random AMR tree."""
+    for W in (c4_workload(), wl.small_amr(5)):
+        r = torch.tensor(W.rho, dtype=torch.float64, device=DEV)
+        outs = []
+        for q in (1, 0):
+            for graph in (True, False):
+                with fm.Plan(W.trees, persistent=True, plane_groups=1, blocks_per_cu=bpc, xcd_queues=q,
+                             use_graph=graph) as p:
+                    assert p.launch_shape()["xcd_queues"] == q
+                    for _ in range(2):
+                        phi, g = p.solve(r)
+                    torch.cuda.synchronize()
+                    outs.append((phi.clone(), g.clone()))
+        print(f"  {W.name}: {len(outs)} runs", flush=True)
+        for phi, g in outs[1:]:
+            assert torch.equal(phi, outs[0][0]) and torch.equal(g, outs[0][1])
+
+
 @pytest.mark.parametrize("groups", [1, 3])
 def test_persistent_and_class_launches_are_bitwise_equal(groups):
     """The persistent launch (items taken largest first from a counter, all
@@ -734,7 +757,7 @@ def test_autotune_picks_a_shape_and_caches_it(tmp_path):
         torch.cuda.synchronize()
         sh2 = p2.launch_shape()
     assert sh2["from_cache"] == 1
-    for k in ("persistent", "plane_groups", "blocks_per_cu", "overlap", "split_level"):
+    for k in ("persistent", "plane_groups", "blocks_per_cu", "overlap", "split_level", "xcd_queues"):
         assert sh2[k] == sh[k]
     assert max(field_errors(phi2.cpu().numpy(), g2.cpu().numpy(), pr, gr)) < TOL64
     # shapes timed as graph replays, or with a larger overlap allowance, are
