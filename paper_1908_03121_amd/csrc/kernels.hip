@@ -1350,10 +1350,10 @@ __global__ __launch_bounds__(256) void k_class(Ctx cx, const Item* __restrict__ 
 // launch are dealt to the XCDs in turn, so block b starts on queue b % NQUEUE
 // (a compact region of the octree whose source records its XCD's L2 keeps),
 // taking the next item from ctr[q] until the queue is exhausted, then helps
-// with the other queues in turn.  Every block passes each queue once, so it
-// exits once all items are taken; the last block to exit (counted in
-// ctr[NQUEUE]) re-arms all NQUEUE + 1 counters (zero before the first launch)
-// for the next launch.
+// with the other queues in turn (a single list is passed as queue 0 with the
+// others empty).  Every block passes each queue once, so it exits once all
+// items are taken; the last block to exit (counted in ctr[NQUEUE]) re-arms
+// all NQUEUE + 1 counters (zero before the first launch) for the next launch.
 template <int PR>
 __global__ __launch_bounds__(256, 3) void k_persist(Ctx cx, const Item* __restrict__ items, Queues qs,
                                                     int* __restrict__ ctr) {
