@@ -94,6 +94,26 @@ __device__ __forceinline__ constexpr double stage_scale(int k) {
     return k >= R_O ? 0.5 : (k >= R_Q ? -3.0 : 1.0);
 }
 
+// A double moved across lanes by a DPP control (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = unsigned(__builtin_amdgcn_update_dpp(0, int(unsigned(b)), CTRL, 0xF, 0xF, false));
+    const unsigned hi = unsigned(__builtin_amdgcn_update_dpp(0, int(unsigned(b >> 32)), CTRL, 0xF, 0xF, false));
+    return __builtin_bit_cast(double, (unsigned long long)lo | ((unsigned long long)hi << 32));
+}
+
+// Sum over the 8 lanes 8k .. 8k + 7 of a full wave, in every one of them:
+// lane ^ 1 and lane ^ 2 within a quad (quad_perm), then the lane mirrored
+// within the 8 (row_half_mirror), which lies in the other quad.  DPP moves,
+// no LDS; a fixed order, so the result is reproducible.
+__device__ __forceinline__ double sum8_lanes(double v) {
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    return v;
+}
+
 // Index into a launch's list for this block: the blocks of a launch are dealt
 // to the NQUEUE XCDs in turn, so XCD x (blocks b with b % NQUEUE = x) gets a
 // contiguous run of the list (neighbouring sub-grids: shared data in its L2).
@@ -978,14 +998,10 @@ __device__ __forceinline__ void c4_item(const Ctx& cx, int sid, int o0, int o1, 
                 acc.add(part2, false, PR == PR_F32);
             }
             acc.add(acc2, false);
-            // the 8 source-child sums of each target, added across lanes
+            // the 8 source-child sums of each target, added across its 8 lanes
             double v[7] = {acc.l0, acc.l1[0], acc.l1[1], acc.l1[2], acc.s[0], acc.s[1], acc.s[2]};
 #pragma unroll
-            for (int k = 0; k < 7; ++k) {
-                v[k] += __shfl_xor(v[k], 1);
-                v[k] += __shfl_xor(v[k], 2);
-                v[k] += __shfl_xor(v[k], 4);
-            }
+            for (int k = 0; k < 7; ++k) v[k] = sum8_lanes(v[k]);
             if (c == 0) {
                 const int q = (tz * NS + ty) * NS + tx;
                 // a target without mass gets no correction term
