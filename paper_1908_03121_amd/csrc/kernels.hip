@@ -551,11 +551,13 @@ __global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__
         v[17] = o6 + qyy * rz + 2 * qyz * ry + w * ry * ry * rz;
         v[18] = (-o1 - o5) + 2 * qyz * rz + qzz * ry + w * ry * rz * rz;
         v[19] = (-o2 - o6) + 3 * qzz * rz + w * rz * rz * rz;
-        // siblings across x parity (lane ^ 1) and y parity (lane ^ 8)
+        // siblings across x parity (lane ^ 1: quad_perm [1, 0, 3, 2]) and y
+        // parity (lane ^ 8: rotation by 8 within each row of 16 lanes), by
+        // DPP moves (every lane of the block takes this branch)
 #pragma unroll
         for (int k = 0; k < 20; ++k) {
-            v[k] += __shfl_xor(v[k], 1);
-            v[k] += __shfl_xor(v[k], 8);
+            v[k] += dpp_f64<0xB1>(v[k]);
+            v[k] += dpp_f64<0x128>(v[k]);
         }
         const bool leader = ((x | y) & 1) == 0;
         const int pc = (y >> 1) * 4 + (x >> 1);
