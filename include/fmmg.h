@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define FMMG_VERSION 4
+#define FMMG_VERSION 5
 
 typedef struct fmmg_plan fmmg_plan; /* opaque; owns device tables and workspaces */
 
@@ -155,6 +155,16 @@ typedef struct {
                                    queue and helping the others once it is drained;
                                    0 = one list, largest estimated cost first.  With
                                    autotune both are tried.  Results are bitwise equal. */
+    int32_t plane_pairs;        /* refined-target work items: 1 = an item takes the two
+                                   target planes of one plane of parent cells, which
+                                   reach the same source planes, so each staged source
+                                   plane serves both (half the staging); 0 = an item
+                                   per target plane (twice the items, for workloads
+                                   too small to fill the GPU otherwise); -1 (default)
+                                   = 1 when the paired items number at least 8 per
+                                   compute unit, else 0.  With autotune and -1 the
+                                   fastest shape is also tried with the other value.
+                                   Results agree to rounding (the sums' order differs). */
 } fmmg_options;
 
 /* Stages of one solve, in launch order. */
@@ -189,6 +199,7 @@ typedef struct {
     int32_t launch_streams;     /* streams of the per-sub-grid launch model, or 0      */
     int32_t use_graph;          /* 1 if solves are captured and replayed as a hipGraph */
     int32_t xcd_queues;         /* persistent launch: 1 = one item queue per XCD        */
+    int32_t plane_pairs;        /* 1 if a refined-target item takes two target planes  */
 } fmmg_launch_shape;
 
 typedef struct {

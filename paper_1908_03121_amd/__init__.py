@@ -51,7 +51,8 @@ class fmmg_options(C.Structure):
                 ("angular_correction", C.c_int32), ("use_graph", C.c_int32),
                 ("persistent", C.c_int32), ("timing", C.c_int32), ("plane_groups", C.c_int32),
                 ("blocks_per_cu", C.c_int32), ("autotune", C.c_int32), ("tuning_cache", C.c_char_p),
-                ("overlap", C.c_int32), ("launch_streams", C.c_int32), ("xcd_queues", C.c_int32)]
+                ("overlap", C.c_int32), ("launch_streams", C.c_int32), ("xcd_queues", C.c_int32),
+                ("plane_pairs", C.c_int32)]
 
 
 class fmmg_timings(C.Structure):
@@ -62,14 +63,14 @@ class fmmg_launch_shape(C.Structure):
     _fields_ = [("persistent", C.c_int32), ("plane_groups", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("from_cache", C.c_int32), ("tuned_ms", C.c_double), ("overlap", C.c_int32),
                 ("split_level", C.c_int32), ("launch_streams", C.c_int32), ("use_graph", C.c_int32),
-                ("xcd_queues", C.c_int32)]
+                ("xcd_queues", C.c_int32), ("plane_pairs", C.c_int32)]
 
     def as_dict(self):
         return {"persistent": int(self.persistent), "plane_groups": int(self.plane_groups),
                 "blocks_per_cu": int(self.blocks_per_cu), "overlap": int(self.overlap),
                 "split_level": int(self.split_level), "launch_streams": int(self.launch_streams),
                 "from_cache": int(self.from_cache), "use_graph": int(self.use_graph),
-                "xcd_queues": int(self.xcd_queues),
+                "xcd_queues": int(self.xcd_queues), "plane_pairs": int(self.plane_pairs),
                 "tuned_ms": float(self.tuned_ms)}
 
 
@@ -280,7 +281,8 @@ class Plan:
                  G: float = 1.0, angular_correction: bool = True, use_graph: bool | None = None,
                  persistent: bool = False, timing: bool = False, plane_groups: int = 0,
                  blocks_per_cu: int = 0, autotune: bool = False, tuning_cache: str | None = None,
-                 overlap: int = 1, launch_streams: int = 0, xcd_queues: bool = True, stream=None):
+                 overlap: int = 1, launch_streams: int = 0, xcd_queues: bool = True,
+                 plane_pairs: bool | None = None, stream=None):
         opt = fmmg_default_options()
         opt.precision = {"fp64": FMMG_FP64, "mixed": FMMG_MIXED, "mixed_f32": FMMG_MIXED_F32}[precision]
         opt.top_mode = {"full": FMMG_TOP_FULL, "stencil": FMMG_TOP_STENCIL_ONLY}[top_mode]
@@ -298,6 +300,8 @@ class Plan:
         opt.overlap = int(overlap)  # 0, 1 (True) or 2
         opt.launch_streams = int(launch_streams)
         opt.xcd_queues = int(bool(xcd_queues))
+        # None: the library's choice (paired refined-target items when they fill the GPU)
+        opt.plane_pairs = -1 if plane_pairs is None else int(bool(plane_pairs))
         self._h = fmmg_plan_create(trees, opt, stream)
         self.n_leaves = fmmg_plan_n_leaves(self._h)
 

@@ -255,9 +255,17 @@ void build_runs(fmmg_plan* p) {
     for (const Keyed& k : v) p->runs.push_back(k.r);
 }
 
-fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int overlap, int queues,
+// plane_pairs -1 (automatic): paired refined-target items when they number
+// at least 8 per compute unit
+int resolve_pairs(const fmmg_plan* p, int pairs, int groups) {
+    if (pairs >= 0) return pairs;
+    return int64_t(p->hp.mp_ref.size()) * (NS / 2) * groups >= 8 * int64_t(p->n_cu) ? 1 : 0;
+}
+
+fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int overlap, int queues, int pairs,
                         hipStream_t st) {
     if (queues != 0 && queues != 1) return fail(FMMG_EINVAL, "xcd_queues must be 0 or 1");
+    if (pairs != 0 && pairs != 1) return fail(FMMG_EINVAL, "plane_pairs must be -1, 0 or 1");
     if (groups < 1 || groups > p->max_groups)
         return fail(FMMG_EINVAL, "plane_groups must be 1.." + std::to_string(p->max_groups) + " for this plan");
     if (bpc < 0) return fail(FMMG_EINVAL, "blocks_per_cu must be >= 0");
@@ -265,8 +273,8 @@ fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int o
     if (overlap < 0 || overlap > 2) return fail(FMMG_EINVAL, "overlap must be 0, 1 or 2");
     // without overlap every class is one launch (no coarse branch)
     const bool split = overlap > 0 && p->hp.split_natural > 0;
-    if (groups != p->hp.ngroups || split != (p->hp.split > 0)) {
-        build_items(&p->hp, groups, split);
+    if (groups != p->hp.ngroups || split != (p->hp.split > 0) || pairs != p->hp.pairs) {
+        build_items(&p->hp, groups, split, pairs);
         if (p->hp.items_class.size() > p->items_capacity) return fail(FMMG_EINVAL, "work-item capacity exceeded");
         if (!p->hp.items_class.empty()) {
             HIP_TRY(hipMemcpyAsync(p->d_items_class, p->hp.items_class.data(),
@@ -281,7 +289,7 @@ fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int o
     }
     if (p->hp.split == 0) overlap = 0;
     if (p->shape.persistent != persistent || p->shape.plane_groups != groups || p->shape.blocks_per_cu != bpc ||
-        p->shape.overlap != overlap || p->shape.xcd_queues != queues)
+        p->shape.overlap != overlap || p->shape.xcd_queues != queues || p->shape.plane_pairs != pairs)
         drop_graph(p);
     p->shape.persistent = persistent;
     p->shape.plane_groups = groups;
@@ -291,6 +299,7 @@ fmmg_status apply_shape(fmmg_plan* p, int persistent, int groups, int bpc, int o
     p->shape.launch_streams = int32_t(p->pool.size());
     p->shape.use_graph = p->opt.use_graph ? 1 : 0;
     p->shape.xcd_queues = queues;
+    p->shape.plane_pairs = pairs;
     return FMMG_OK;
 }
 
@@ -495,9 +504,9 @@ std::string signature(const fmmg_plan* p) {
 
 // Cache file: a JSON object, one entry per line:
 //   "signature": {"persistent": P, "plane_groups": G, "blocks_per_cu": B, "overlap": O,
-//                 "xcd_queues": Q, "ms": T},
+//                 "xcd_queues": Q, "plane_pairs": R, "ms": T},
 bool cache_lookup(const char* path, const std::string& sig, int* pers, int* groups, int* bpc, int* ovl,
-                  int* queues) {
+                  int* queues, int* pairs) {
     if (!path) return false;
     std::ifstream f(path);
     if (!f) return false;
@@ -505,19 +514,21 @@ bool cache_lookup(const char* path, const std::string& sig, int* pers, int* grou
     while (std::getline(f, line)) {
         size_t at = line.find(key);
         if (at == std::string::npos) continue;
-        int a = -1, b = -1, c = -1, d = -1, q = -1;
+        int a = -1, b = -1, c = -1, d = -1, q = -1, r = -1;
         const char* s = line.c_str() + at + key.size();
         if (std::sscanf(s,
                         " {\"persistent\": %d, \"plane_groups\": %d, \"blocks_per_cu\": %d, \"overlap\": %d, "
-                        "\"xcd_queues\": %d",
-                        &a, &b, &c, &d, &q) == 5 &&
-            (a == 0 || a == 1) && b >= 1 && b <= MAX_GROUPS && c >= 0 && d >= 0 && d <= 2 && (q == 0 || q == 1)) {
+                        "\"xcd_queues\": %d, \"plane_pairs\": %d",
+                        &a, &b, &c, &d, &q, &r) == 6 &&
+            (a == 0 || a == 1) && b >= 1 && b <= MAX_GROUPS && c >= 0 && d >= 0 && d <= 2 && (q == 0 || q == 1) &&
+            (r == 0 || r == 1)) {
             // (a group count above the plan's buffers is rejected by apply_shape)
             *pers = a;
             *groups = b;
             *bpc = c;
             *ovl = d;
             *queues = q;
+            *pairs = r;
             return true;
         }
     }
@@ -525,7 +536,7 @@ bool cache_lookup(const char* path, const std::string& sig, int* pers, int* grou
 }
 
 void cache_store(const char* path, const std::string& sig, int pers, int groups, int bpc, int ovl, int queues,
-                 double ms) {
+                 int pairs, double ms) {
     if (!path) return;
     std::vector<std::string> keep;
     {
@@ -541,8 +552,8 @@ void cache_store(const char* path, const std::string& sig, int pers, int groups,
     char buf[512];
     std::snprintf(buf, sizeof(buf),
                   "  \"%s\": {\"persistent\": %d, \"plane_groups\": %d, \"blocks_per_cu\": %d, \"overlap\": %d, "
-                  "\"xcd_queues\": %d, \"ms\": %.6f}",
-                  sig.c_str(), pers, groups, bpc, ovl, queues, ms);
+                  "\"xcd_queues\": %d, \"plane_pairs\": %d, \"ms\": %.6f}",
+                  sig.c_str(), pers, groups, bpc, ovl, queues, pairs, ms);
     keep.push_back(buf);
     std::string tmp = std::string(path) + ".tmp";
     {
@@ -556,25 +567,26 @@ void cache_store(const char* path, const std::string& sig, int pers, int groups,
 }
 
 fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStream_t st) {
-    int pers = 0, groups = 0, bpc = 0, ovl = 0, queues = 1;
+    int pers = 0, groups = 0, bpc = 0, ovl = 0, queues = 1, pairs = 0;
     const std::string sig = signature(p);
-    if (cache_lookup(p->opt.tuning_cache, sig, &pers, &groups, &bpc, &ovl, &queues)) {
-        fmmg_status s = apply_shape(p, pers, groups, bpc, ovl, queues, st);
+    if (cache_lookup(p->opt.tuning_cache, sig, &pers, &groups, &bpc, &ovl, &queues, &pairs)) {
+        fmmg_status s = apply_shape(p, pers, groups, bpc, ovl, queues, pairs, st);
         if (s != FMMG_OK) return s;
         p->shape.from_cache = 1;
         p->tuned = true;
         return FMMG_OK;
     }
-    struct Cand { int pers, groups, bpc, ovl, queues; };
+    struct Cand { int pers, groups, bpc, ovl, queues, pairs; };
     std::vector<Cand> cands;
     const int max_ov = p->hp.split_natural > 0 ? p->opt.overlap : 0;
     for (int ov = 0; ov <= max_ov; ++ov)
         for (int gr : {1, 2, 3, 5}) {
             if (gr > p->max_groups) continue;
-            cands.push_back({0, gr, 0, ov, p->opt.xcd_queues});
+            const int pr = resolve_pairs(p, p->opt.plane_pairs, gr);
+            cands.push_back({0, gr, 0, ov, p->opt.xcd_queues, pr});
             if (ov == 2) continue;  // the third stream applies to per-class launches only
             for (int b = 1; b <= p->max_bpc; ++b)
-                for (int q : {1, 0}) cands.push_back({1, gr, b, ov, q});
+                for (int q : {1, 0}) cands.push_back({1, gr, b, ov, q, pr});
         }
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
@@ -597,8 +609,12 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
     // each candidate runs the way the plan will: graph replays when the plan
     // uses graphs, else eager launches; it is timed as the best of 3 runs of
     // enough solves to last about 1 ms
-    for (const Cand& c : cands) {
-        status = apply_shape(p, c.pers, c.groups, c.bpc, c.ovl, c.queues, st);
+    // after the candidates above, the fastest is tried once more with the
+    // other item form when the plan leaves it to the tuner
+    const size_t n_first = cands.size();
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+        const Cand c = cands[ci];
+        status = apply_shape(p, c.pers, c.groups, c.bpc, c.ovl, c.queues, c.pairs, st);
         if (status != FMMG_OK) break;
         hipGraph_t cg = nullptr;
         hipGraphExec_t ce = nullptr;
@@ -654,6 +670,11 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
         }
         if (e != hipSuccess) { status = hip_fail(e, "tuning run"); break; }
         if (better) { best = t; bc = c; }
+        if (ci + 1 == n_first && p->opt.plane_pairs < 0) {
+            Cand f = bc;
+            f.pairs = 1 - bc.pairs;
+            cands.push_back(f);
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -662,7 +683,7 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
         if (best_cg) (void)hipGraphDestroy(best_cg);
     };
     if (status != FMMG_OK) { drop_best(); return status; }
-    status = apply_shape(p, bc.pers, bc.groups, bc.bpc, bc.ovl, bc.queues, st);
+    status = apply_shape(p, bc.pers, bc.groups, bc.bpc, bc.ovl, bc.queues, bc.pairs, st);
     if (status != FMMG_OK) { drop_best(); return status; }
     if (best_ce) {
         drop_graph(p);
@@ -677,7 +698,7 @@ fmmg_status tune(fmmg_plan* p, const double* rho, double* phi, double* g, hipStr
     p->shape.tuned_ms = best;
     p->tuned = true;
     cache_store(p->opt.tuning_cache, sig, bc.pers, bc.groups, p->shape.blocks_per_cu, p->shape.overlap, bc.queues,
-                best);
+                bc.pairs, best);
     return FMMG_OK;
 }
 
@@ -705,6 +726,7 @@ void fmmg_default_options(fmmg_options* opt) {
     opt->tuning_cache = nullptr;
     opt->overlap = 1;
     opt->xcd_queues = 1;
+    opt->plane_pairs = -1;
 }
 
 fmmg_status fmmg_count_pairs(const fmmg_tree_desc* trees, int32_t n_trees, fmmg_top_mode top_mode,
@@ -761,6 +783,7 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         else if (o.launch_streams && o.timing) bad = "timing needs launch_streams = 0";
         else if (o.launch_streams && o.autotune) bad = "autotune needs launch_streams = 0";
         else if (o.xcd_queues != 0 && o.xcd_queues != 1) bad = "xcd_queues must be 0 or 1";
+        else if (o.plane_pairs < -1 || o.plane_pairs > 1) bad = "plane_pairs must be -1, 0 or 1";
         if (!bad.empty()) { release(p); return fail(FMMG_EINVAL, bad); }
         hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
         hipError_t e = hipGetDevice(&p->device);
@@ -783,7 +806,7 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         // partial buffers and item capacity for the plane-group counts this plan may use
         p->max_groups = (o.plane_groups > 0 && !o.autotune) ? o.plane_groups : MAX_GROUPS;
         if (!o.autotune && o.plane_groups == 0) p->max_groups = 2;
-        build_items(&hp, p->max_groups, true);
+        build_items(&hp, p->max_groups, true, 0);  // the larger item form
         p->items_capacity = hp.items_class.size();
         fmmg_status s;
 #define UP(dst, src, cap, what) if ((s = dev_upload(&(dst), (src), (cap), st, what)) != FMMG_OK) { release(p); return s; }
@@ -863,8 +886,11 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
         }
         p->hp.ngroups = 0;  // force the first item upload
         memset(&p->shape, 0, sizeof(p->shape));
-        s = apply_shape(p, o.persistent ? 1 : 0, o.plane_groups ? o.plane_groups : 2, o.blocks_per_cu,
-                        o.overlap, o.xcd_queues, st);
+        {
+            const int gr = o.plane_groups ? o.plane_groups : 2;
+            s = apply_shape(p, o.persistent ? 1 : 0, gr, o.blocks_per_cu, o.overlap, o.xcd_queues,
+                            resolve_pairs(p, o.plane_pairs, gr), st);
+        }
         if (s != FMMG_OK) { release(p); return s; }
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) { release(p); return hip_fail(e, "plan upload"); }

@@ -94,7 +94,8 @@ constexpr int NQUEUE = 8;       // persistent-launch queues: one per XCD of the 
 struct Item {
     int32_t kind;
     int32_t sub;   // target sub-grid (IT_TOP: index into the top items)
-    int32_t a;     // IT_MP_REF: target plane along the sweep axis;
+    int32_t a;     // IT_MP_REF: 2 pz in bits 0..3 for the parent plane pz along
+                   // the sweep axis, bit 4: target plane 2 pz, bit 5: 2 pz + 1;
                    // IT_MP_LEAF: neighbour slots [a & 255, a >> 8)
     int32_t b;     // IT_MP_REF: plane group in bits 0..2, sweep in bit 3
                    // (0: planes along z, lanes on (x, y); 1: along y, lanes on (x, z));

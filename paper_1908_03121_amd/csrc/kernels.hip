@@ -675,20 +675,22 @@ __device__ __forceinline__ void swap_yz_o(T* o) {
     o[6] = -o1 - o5;
 }
 
-// Refined-target item: 64 target cells (one plane of refined sub-grid sid)
-// against the source planes of one group of canonical plane offsets.  All 4
-// waves hold the same 64 targets and split each plane's entry list: every
-// existing source over the far entries, leaf sources also over the near
-// entries (classes 1 + 2).
-// The sweep frame (u, v, w) puts the target plane at w = zt and the lanes on
-// (u, v): sweep 0 is (x, y, z); sweep 1 is (x, z, y), chosen by the planner
-// for targets whose sources lie mostly beside them in y, so that whole source
-// planes without sources are skipped.  x, the fastest index in memory, stays
-// in the plane either way (coalesced staging), and the stencil is symmetric
-// under the swap, so one set of tables serves both: records are swapped into
-// the frame when staged and the results swapped back before they are stored.
+// Refined-target item: target planes of refined sub-grid sid among the two
+// planes 2 pz and 2 pz + 1 (the children of one plane of parent cells)
+// against one group of their source planes.  The two planes have the same
+// parent plane, so the interaction rule reaches the same 10 source planes
+// from both (2 pz - 4 .. 2 pz + 5: staged plane j is canonical offset j - 4
+// of the even plane and 5 - j of the odd one), and one staged window serves
+// both.  An item of both planes gives waves 0 and 1 the 64 targets of the
+// even plane and waves 2 and 3 those of the odd plane, the two waves of a
+// plane splitting its entry list; an item of one plane gives all 4 waves its
+// 64 targets, splitting the entry list four ways (twice the items, for
+// workloads too small to fill the GPU otherwise).  The entries: every
+// existing source over the far ones, leaf sources also over the near ones
+// (classes 1 + 2).
+// The sweep frame (u, v, w) puts the target planes at w = 2 pz, 2 pz + 1 and the lanes on
 template <int PR, int SWEEP>
-__device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int group, unsigned char* smem) {
+__device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int group, unsigned char* smem) {
     // P: staged source data; PA: the pair terms' partial sums
     using P = typename std::conditional<PR == PR_F32, float, double>::type;
     using PA = typename std::conditional<PR == PR_F64, double, float>::type;
@@ -701,6 +703,13 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
 
     const int t = item_tid(), lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index: uniform
+    // planes: 2 pz in bits 0..3, the target planes in bits 4 (even) and 5
+    // (odd).  The wave's target plane (0: even, 1: odd), the number of waves
+    // on it and the wave's share of its entries
+    const int zt0 = planes & 15, both = (planes >> 4) == 3;
+    const int wp = both ? w >> 1 : (planes >> 5) & 1;
+    const int nsplit = both ? 2 : 4, wi = both ? w & 1 : w;
+    const int zt = zt0 + wp;
     // y runs fastest over the lanes: with the window row stride of 20 cells,
     // the 32 lanes of each LDS pass then hit distinct banks for every offset
     const int x = lane >> 3, y = lane & 7, cl = y * 8 + x;
@@ -715,7 +724,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     constexpr int VS = SWEEP ? 64 : 8, WS = SWEEP ? 8 : 64;
     constexpr int VN = SWEEP ? 1 : 3, WN = SWEEP ? 3 : 1;
     const int q = zt * WS + y * VS + x;
-    const int sx = 1 - 2 * (x & 1), sy = 1 - 2 * (y & 1), sz = 1 - 2 * (zt & 1);
+    const int sx = 1 - 2 * (x & 1), sy = 1 - 2 * (y & 1);
 
     // target data
     P oa[9];
@@ -737,7 +746,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     const bool use_corr = cx.corr != 0;
     const bool do_near = (T.flags & 1) != 0;
     const int ng = cx.ngroups;
-    const int i0 = group * NDZ / ng, i1 = (group + 1) * NDZ / ng;
+    const int j0 = group * NDZ / ng, j1 = (group + 1) * NDZ / ng;
 
     Acc<double> acc;
     acc.zero();
@@ -752,9 +761,12 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     const int lbase = ((y + REACH) * MP_PRS + (x + REACH)) * 16;
     const short2_t sxy = {short(sx), short(sy)};
 
-    for (int gi = i0; gi < i1; ++gi) {
-        const int dz = sz * (DZ0 + gi);
-        const int zs = zt + dz;
+    static_assert(DZ0 + NDZ - 1 == 1 - DZ0, "the odd plane's canonical offsets mirror the even plane's");
+    for (int j = j0; j < j1; ++j) {
+        // staged plane: canonical offset DZ0 + j of the even plane, mirrored
+        // (sz = -1) DZ0 + NDZ - 1 - j of the odd one
+        const int zs = zt0 + DZ0 + j;
+        const int gi = wp ? NDZ - 1 - j : j;
         const int oz = zs < 0 ? -1 : (zs >= NS ? 1 : 0);
         // a source plane whose nine neighbour sub-grids at its offset are all
         // absent is skipped (uniform over the block)
@@ -842,16 +854,26 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
             pair_any<true, PR>(X, Y, Z, src, oa, acc, part);
         };
         const int fb = c_tab.mp_far_begin[gi], fe = fb + c_tab.mp_far_count[gi];
-        // two independent pairs per iteration: two dependency chains per wave
-        int e = fb + w;
-        for (; e + 4 < fe; e += 8) {
-            one(e);
-            one(e + 4);
+        // the wave's far entries fb + wi + k nsplit, k < nk: two independent
+        // pairs per iteration, two dependency chains per wave.  FP32 forms
+        // with two waves on the plane flush the partial sums once more, after
+        // about half of them, so that no partial sums more pairs than with
+        // four waves on the plane
+        const int nk = fe - fb > wi ? (fe - fb - wi + nsplit - 1) / nsplit : 0;
+        const int kflush = (PR != PR_F64 && both) ? (nk >> 2) << 1 : -1;
+        int k = 0;
+        for (; k + 1 < nk; k += 2) {
+            if (PR != PR_F64 && k == kflush && k > 0) {
+                acc.add(part, true, PR == PR_F32);
+                part.zero();
+            }
+            one(fb + wi + k * nsplit);
+            one(fb + wi + (k + 1) * nsplit);
         }
-        if (e < fe) one(e);
+        if (k < nk) one(fb + wi + k * nsplit);
         if (do_near) {
             const int nbg = c_tab.mp_near_begin[gi], ne = nbg + c_tab.mp_near_count[gi];
-            for (int e = nbg + w; e < ne; e += 4) {
+            for (int e = nbg + wi; e < ne; e += nsplit) {
                 if (!leafflag[addr(e) >> 4]) continue;
                 one(e);
             }
@@ -859,7 +881,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
         if (PR != PR_F64) acc.add(part, true, PR == PR_F32);
     }
 
-    // combine the 4 waves' partial sums in a fixed order
+    // combine the partial sums of each plane's waves in a fixed order
     __syncthreads();
     double* red = reinterpret_cast<double*>(smem);
     {
@@ -880,15 +902,23 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int zt, int grou
     __syncthreads();
     const double G = cx.G;
     const double gs = use_corr ? 3.0 * G : 0.0;  // dg = 3G S
-    auto sum4 = [&](int k, int l) {
-        return red[(0 * NLOC + k) * 64 + l] + red[(1 * NLOC + k) * 64 + l] +
-               red[(2 * NLOC + k) * 64 + l] + red[(3 * NLOC + k) * 64 + l];
-    };
-    // reduction slot l = v*8 + u holds target cell zt*WS + v*VS + u
-    double* out = cx.Lp + size_t(group) * size_t(cx.part_stride) + size_t(tidx) * NLOC * NCELL + zt * WS;
-    for (int i = t; i < NLOC * 64; i += 256) {
-        const int k = i >> 6, l = i & 63;
-        out[k * NCELL + (l >> 3) * VS + (l & 7)] = (k >= T_S ? gs : -G) * sum4(k, l);
+    // reduction slot l = v*8 + u of plane p holds target cell
+    // (2 pz + p)*WS + v*VS + u
+    double* out = cx.Lp + size_t(group) * size_t(cx.part_stride) + size_t(tidx) * NLOC * NCELL + zt0 * WS;
+    if (both) {
+        for (int i = t; i < 2 * NLOC * 64; i += 256) {
+            const int p = i >= NLOC * 64, r = i - p * (NLOC * 64);
+            const int k = r >> 6, l = r & 63;
+            const double v = red[((2 * p) * NLOC + k) * 64 + l] + red[((2 * p + 1) * NLOC + k) * 64 + l];
+            out[p * WS + k * NCELL + (l >> 3) * VS + (l & 7)] = (k >= T_S ? gs : -G) * v;
+        }
+    } else {
+        for (int i = t; i < NLOC * 64; i += 256) {
+            const int k = i >> 6, l = i & 63;
+            const double v = red[(0 * NLOC + k) * 64 + l] + red[(1 * NLOC + k) * 64 + l] +
+                             red[(2 * NLOC + k) * 64 + l] + red[(3 * NLOC + k) * 64 + l];
+            out[wp * WS + k * NCELL + (l >> 3) * VS + (l & 7)] = (k >= T_S ? gs : -G) * v;
+        }
     }
 }
 

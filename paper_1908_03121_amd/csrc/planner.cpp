@@ -444,15 +444,16 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
             }
         }
     }
-    build_items(&P, 1, true);
+    build_items(&P, 1, true, 0);
     return 0;
 }
 
-void build_items(HostPlan* Pp, int ngroups, bool split) {
+void build_items(HostPlan* Pp, int ngroups, bool split, int pairs) {
     HostPlan& P = *Pp;
     if (ngroups < 1) ngroups = 1;
     if (ngroups > MAX_GROUPS) ngroups = MAX_GROUPS;
     P.ngroups = ngroups;
+    P.pairs = pairs ? 1 : 0;
     StencilTables tab;
     build_stencil_tables(&tab);
     // estimated cost of an item, in refined-pair units, and its level
@@ -490,10 +491,21 @@ void build_items(HostPlan* Pp, int ngroups, bool split) {
         const bool nearc = (S.flags & 1) != 0;
         const int sw = best_sweep(S, nearc);
         P.sweep_y_targets += sw;
-        for (int zt = 0; zt < NS; ++zt)
+        // per plane of parent cells (target planes 2 pz, 2 pz + 1) and group
+        // of staged source planes j (canonical offsets j of the even plane and
+        // NDZ - 1 - j of the odd one): one item of both planes, or one per plane
+        for (int pz = 0; pz < NS / 2; ++pz)
             for (int g = 0; g < ngroups; ++g) {
-                const double n = visited(S, sw, zt, g * NDZ / ngroups, (g + 1) * NDZ / ngroups, nearc);
-                all.push_back({Item{IT_MP_REF, s, zt, g | (sw << 3)}, 64.0 * n + 2000.0, S.level});
+                const int j0 = g * NDZ / ngroups, j1 = (g + 1) * NDZ / ngroups;
+                const double ne = visited(S, sw, 2 * pz, j0, j1, nearc);
+                const double no = visited(S, sw, 2 * pz + 1, NDZ - j1, NDZ - j0, nearc);
+                const int b = g | (sw << 3);
+                if (P.pairs) {
+                    all.push_back({Item{IT_MP_REF, s, 2 * pz | 3 << 4, b}, 64.0 * (ne + no) + 3000.0, S.level});
+                } else {
+                    all.push_back({Item{IT_MP_REF, s, 2 * pz | 1 << 4, b}, 64.0 * ne + 2000.0, S.level});
+                    all.push_back({Item{IT_MP_REF, s, 2 * pz | 2 << 4, b}, 64.0 * no + 2000.0, S.level});
+                }
             }
     }
     // class-4 items: cost of their (target parent, source parent) steps of

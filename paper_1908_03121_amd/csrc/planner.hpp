@@ -59,6 +59,7 @@ struct HostPlan {
     // same-level work items for a given number of plane groups, in two
     // branches: 0 = levels >= split (fine), 1 = levels < split (coarse)
     int ngroups = 1;
+    int pairs = 0;                     // 1: a refined-target item takes both planes of a parent plane
     int split = 0;                     // split level of the current lists (0: one branch)
     int split_natural = 0;             // split level the estimates give
     int32_t sweep_y_targets = 0;       // refined targets whose plane items run along y
@@ -87,11 +88,13 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
                     HostPlan* out, std::string* err);
 
 // (Re)builds the work-item lists with ngroups (1..MAX_GROUPS) plane groups
-// per refined-target plane item.  The natural split level is the largest
-// s <= max_level whose levels below s carry at most a fifth of the estimated
-// same-level work (0: none); the lists use it when split is true (a coarse
-// branch for the overlapped solve), else split = 0 (every class one list).
-void build_items(HostPlan* P, int ngroups, bool split);
+// per refined-target plane item, an item taking both target planes of a
+// parent plane (pairs = 1) or one (pairs = 0).  The natural split level is
+// the largest s <= max_level whose levels below s carry at most a fifth of
+// the estimated same-level work (0: none); the lists use it when split is
+// true (a coarse branch for the overlapped solve), else split = 0 (every
+// class one list).
+void build_items(HostPlan* P, int ngroups, bool split, int pairs);
 
 // Fills the canonical stencil tables.
 void build_stencil_tables(StencilTables* t);

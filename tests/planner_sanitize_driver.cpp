@@ -45,8 +45,34 @@ int main(int argc, char** argv) {
                 return 1;
             }
             for (int g = 1; g <= MAX_GROUPS; ++g)
-                for (int split = 0; split < 2; ++split) {
-                    build_items(&hp, g, split != 0);
+                for (int split = 0; split < 2; ++split)
+                for (int pairs = 0; pairs < 2; ++pairs) {
+                    build_items(&hp, g, split != 0, pairs);
+                    // the refined-target items cover every (target, plane,
+                    // group) once, each with both planes of its parent plane
+                    // when paired and one plane otherwise
+                    {
+                        std::vector<int> cover(hp.subs.size() * NS * size_t(g), 0);
+                        bool ok = true;
+                        size_t n_ref_items = 0;
+                        for (const Item& it : hp.items_class) {
+                            if (it.kind != IT_MP_REF) continue;
+                            ++n_ref_items;
+                            const int zt0 = it.a & 15, m = it.a >> 4, grp = it.b & 7;
+                            ok = ok && zt0 % 2 == 0 && zt0 < NS && grp < g && (pairs ? m == 3 : (m == 1 || m == 2));
+                            for (int pl = 0; pl < 2 && ok; ++pl)
+                                if (m >> pl & 1) ++cover[(size_t(it.sub) * NS + size_t(zt0 + pl)) * size_t(g) + size_t(grp)];
+                        }
+                        for (int32_t sref : hp.mp_ref)
+                            for (int z = 0; z < NS; ++z)
+                                for (int gg = 0; gg < g; ++gg)
+                                    ok = ok && cover[(size_t(sref) * NS + size_t(z)) * size_t(g) + size_t(gg)] == 1;
+                        ok = ok && n_ref_items == hp.mp_ref.size() * size_t(NS / (pairs ? 2 : 1) * g);
+                        if (!ok) {
+                            printf("%s refined-target items wrong (groups %d split %d pairs %d)\n", name, g, split, pairs);
+                            return 1;
+                        }
+                    }
                     // the persistent queues of each branch partition it, and
                     // hold the same items as the per-class lists
                     for (int b = 0; b < 2; ++b) {
@@ -68,7 +94,8 @@ int main(int argc, char** argv) {
                         std::sort(x.begin(), x.end());
                         std::sort(c.begin(), c.end());
                         if (!ok || a != c || x != c) {
-                            printf("%s persistent queues wrong (groups %d split %d branch %d)\n", name, g, split, b);
+                            printf("%s persistent queues wrong (groups %d split %d pairs %d branch %d)\n", name, g, split,
+                                   pairs, b);
                             return 1;
                         }
                     }

@@ -101,7 +101,10 @@ SHAPES = {"per_class_g1": dict(plane_groups=1), "per_class_g2": dict(plane_group
           "persistent_g1": dict(persistent=True, plane_groups=1),
           "per_class_g3": dict(plane_groups=3),
           "persistent_g5": dict(persistent=True, plane_groups=5),
-          "persistent_g1_bpc1": dict(persistent=True, plane_groups=1, blocks_per_cu=1)}
+          "persistent_g1_bpc1": dict(persistent=True, plane_groups=1, blocks_per_cu=1),
+          "per_class_g2_pairs": dict(plane_groups=2, plane_pairs=True),
+          "persistent_g1_pairs": dict(persistent=True, plane_groups=1, plane_pairs=True),
+          "persistent_g3_single": dict(persistent=True, plane_groups=3, plane_pairs=False)}
 
 
 @pytest.mark.parametrize("shape", list(SHAPES))
@@ -537,7 +540,7 @@ def test_mixed_c2_against_the_oracle_and_the_truncation_error(precision):
 
 
 @pytest.mark.parametrize("precision", ["mixed", "mixed_f32"])
-@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2"])
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g2", "persistent_g1_pairs"])
 def test_mixed_amr_error_bounds(shape, precision):
     W = wl.small_amr(3)
     t = W.trees[0]
@@ -565,7 +568,7 @@ def flat_forest(seed):
     return t, rng.lognormal(0.0, 1.0, (t.n_leaves, 8, 8, 8))
 
 
-@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g1", "per_class_g3"])
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g1", "per_class_g3", "persistent_g1_pairs"])
 def test_y_sweep_targets_fp64(shape):
     t, rho = flat_forest(7)
     n_y = fm.fmmg_count_pairs([t])["sweep_y_targets"]
@@ -589,6 +592,50 @@ def test_y_sweep_targets_mixed(precision):
     f, tq = residuals(t, rho, g, centre=(0.75, 0.0625, 0.75))
     print(f"  {precision} errors {errs} force {f:.3e} torque {tq:.3e}", flush=True)
     check_form("amr", precision, errs, f, tq)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_f32"])
+def test_plane_pair_and_single_plane_items_against_the_oracle(precision):
+    """Refined-target items of both target planes of a parent plane (each
+    staged source plane serving 128 targets, two waves per plane) and of one
+    plane (four waves): each against the oracle, on a random AMR tree and on
+    the forest whose plane items run along y, in one and in three plane
+    groups, with the choice reported in the launch shape."""
+    cases = [(*wl.small_amr(3).trees, wl.small_amr(3).rho, (0.5, 0.5, 0.5))]
+    t, rho = flat_forest(8)
+    cases.append((t, rho, (0.75, 0.0625, 0.75)))
+    for t, rho, centre in cases:
+        pr, gr = oracle.solve(t, rho)
+        r = torch.tensor(rho, dtype=torch.float64, device=DEV)
+        for groups in (1, 3):
+            for pairs in (True, False):
+                with fm.Plan([t], precision=precision, persistent=True, plane_groups=groups,
+                             plane_pairs=pairs) as p:
+                    assert p.launch_shape()["plane_pairs"] == int(pairs)
+                    phi, g = p.solve(r)
+                    torch.cuda.synchronize()
+                errs = field_errors(phi.cpu().numpy(), g.cpu().numpy(), pr, gr)
+                f, tq = residuals(t, rho, g.cpu().numpy(), centre=centre)
+                print(f"  groups {groups} pairs {pairs}: errors {errs} force {f:.3e} torque {tq:.3e}",
+                      flush=True)
+                if precision == "fp64":
+                    assert max(errs) < TOL64 and f < 1e-13 and tq < 1e-13
+                else:
+                    check_form("amr", precision, errs, f, tq)
+
+
+def test_plane_pairs_default_follows_the_item_count():
+    """By default refined-target items are paired when the paired items
+    number at least 8 per compute unit: on the 16-tree batch, not on the
+    uniform level-3 tree."""
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    for W, groups in ((c4_workload(), 1), (wl.c1(), 2)):
+        n_ref = sum(int(t.refined_mask().sum()) - int(((t.level == 0) & t.refined_mask()).sum())
+                    for t in W.trees)
+        with fm.Plan(W.trees, plane_groups=groups) as p:
+            got = p.launch_shape()["plane_pairs"]
+        print(f"  {W.name}: {n_ref} refined non-top targets, plane_pairs {got}", flush=True)
+        assert got == int(n_ref * 4 * groups >= 8 * n_cu)
 
 
 # ---------------------------------------------------------------------------
@@ -757,7 +804,7 @@ def test_autotune_picks_a_shape_and_caches_it(tmp_path):
         torch.cuda.synchronize()
         sh2 = p2.launch_shape()
     assert sh2["from_cache"] == 1
-    for k in ("persistent", "plane_groups", "blocks_per_cu", "overlap", "split_level", "xcd_queues"):
+    for k in ("persistent", "plane_groups", "blocks_per_cu", "overlap", "split_level", "xcd_queues", "plane_pairs"):
         assert sh2[k] == sh[k]
     assert max(field_errors(phi2.cpu().numpy(), g2.cpu().numpy(), pr, gr)) < TOL64
     # shapes timed as graph replays, or with a larger overlap allowance, are

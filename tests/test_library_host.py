@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(fm.EXPORTED)
     for n in names:
         assert hasattr(L, n), n
-    assert fm.fmmg_version() == 4
+    assert fm.fmmg_version() == 5
 
 
 def test_default_options():
@@ -35,11 +35,12 @@ def test_default_options():
     assert o.G == 1.0 and o.angular_correction == 1
     assert o.overlap == 1 and o.launch_streams == 0 and o.use_graph == -1 and o.persistent == 0
     assert o.xcd_queues == 1
+    assert o.plane_pairs == -1
 
 
 @pytest.mark.parametrize("bad", [
     {"launch_streams": 129}, {"launch_streams": -1}, {"launch_streams": 4, "timing": 1},
-    {"launch_streams": 4, "autotune": 1}, {"overlap": 3}, {"plane_groups": 6}, {"xcd_queues": 2},
+    {"launch_streams": 4, "autotune": 1}, {"overlap": 3}, {"plane_groups": 6}, {"xcd_queues": 2}, {"plane_pairs": 2},
     {"timing": 1, "use_graph": 1}, {"timing": 1, "autotune": 1}, {"blocks_per_cu": -1},
     {"precision": 3},
 ])
