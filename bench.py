@@ -125,6 +125,8 @@ def stage_times(fm, torch, trees, rho_np, precision, steps, warmup, shape):
     rho = torch.tensor(rho_np, dtype=torch.float64, device=dev)
     with fm.Plan(trees, precision=precision, timing=True, persistent=bool(shape["persistent"]),
                  plane_groups=shape["plane_groups"], blocks_per_cu=shape["blocks_per_cu"],
+                 xcd_queues=bool(shape.get("xcd_queues", 1)),
+                 plane_pairs=bool(shape["plane_pairs"]) if "plane_pairs" in shape else None,
                  overlap=0) as plan:
         phi, g = plan.solve(rho)
         for _ in range(warmup):
