@@ -147,7 +147,7 @@ typedef struct {
                                    persistent and overlap are then ignored; timing and
                                    autotune are not allowed.  Results are bitwise equal
                                    to those of the default shapes with the same
-                                   plane_groups.                                        */
+                                   plane_groups and plane_pairs.                        */
     int32_t xcd_queues;         /* persistent launch: 1 (default) = one item queue per
                                    XCD, each a compact region of the octrees (items in
                                    space-filling-curve order, cut into runs of equal
