@@ -447,6 +447,15 @@ def main():
                    "frac_fp64_peak_whole_solve": head["frac_peak"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        # context only (other hardware, another workload): the paper's node-level
+        # FMM figures (Sec. 6.1 table), GFLOP/s by its nominal convention of 12
+        # flop per monopole and 455 per multipole interaction, FP64
+        "paper_context": {
+            "workload": "V1309 merger model at level 14 (10,928 sub-grids), several time steps",
+            "piz_daint_p100_gflops": 973, "piz_daint_p100_frac_fp64_peak": 0.21,
+            "best_node_2x_v100_gflops": 5188, "best_node_frac_fp64_peak": 0.37,
+            "this_run_paper_convention_gflops": head["paper_convention_gflops"],
+        },
         "forms": forms,
     }
     print(json.dumps(out), flush=True)
