@@ -950,6 +950,7 @@ __device__ __forceinline__ void c4_item(const Ctx& cx, int sid, int o0, int o1, 
     const int c = lane & 7, tc = lane >> 3;
     const SubDev& T = cx.subs[sid];
     const double h = T.h;
+    const double* tmass = cx.mass + size_t(T.idx) * NCELL;
     const double sfac = cx.corr ? 3.0 : 0.0;  // dg = 3G S
     for (int i = t; i < NLEAF * NCELL; i += 256) tot[i] = 0.0;
     const P oa[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // leaf targets carry no octupole
@@ -993,6 +994,10 @@ __device__ __forceinline__ void c4_item(const Ctx& cx, int sid, int o0, int o1, 
             const int tx = 2 * (pt >> 4) + (tc >> 2), ty = 2 * ((pt >> 2) & 3) + ((tc >> 1) & 1);
             const int tz = 2 * (pt & 3) + (tc & 1);
             const P X0 = P(h * tx), Y0 = P(h * ty), Z0 = P(h * tz);
+            // the target's mass, loaded before the steps (its latency hidden
+            // by them) for the correction's switch after them
+            const int q = (tz * NS + ty) * NS + tx;
+            const double mq = tmass[q];
             // two steps per iteration, each into its own sums: two
             // independent dependency chains per wave
             Acc<double> acc, acc2;
@@ -1035,9 +1040,8 @@ __device__ __forceinline__ void c4_item(const Ctx& cx, int sid, int o0, int o1, 
 #pragma unroll
             for (int k = 0; k < 7; ++k) v[k] = sum8_lanes(v[k]);
             if (c == 0) {
-                const int q = (tz * NS + ty) * NS + tx;
                 // a target without mass gets no correction term
-                const double sf = cx.mass[size_t(T.idx) * NCELL + q] > 0 ? sfac : 0.0;
+                const double sf = mq > 0 ? sfac : 0.0;
                 tot[q] += v[0];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) tot[(1 + a) * NCELL + q] += fma(sf, v[4 + a], v[1 + a]);
