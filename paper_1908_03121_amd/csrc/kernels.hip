@@ -703,6 +703,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int 
 
     const int t = item_tid(), lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);  // wave index: uniform
+    sid = __builtin_amdgcn_readfirstlane(sid);  // one item per block: uniform
     // planes: 2 pz in bits 0..3, the target planes in bits 4 (even) and 5
     // (odd).  The wave's target plane (0: even, 1: odd), the number of waves
     // on it and the wave's share of its entries
@@ -762,18 +763,25 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int 
     const short2_t sxy = {short(sx), short(sy)};
 
     static_assert(DZ0 + NDZ - 1 == 1 - DZ0, "the odd plane's canonical offsets mirror the even plane's");
+    // the neighbour offsets along the sweep axis (-1, 0, 1) with at least one
+    // existing sub-grid among their nine: a source plane at an offset without
+    // any is skipped (uniform over the block)
+    unsigned use_w = 0;
+#pragma unroll
+    for (int o = 0; o < 27; ++o)
+        if (T.nbr[(o % 3) * 9 + ((o / 3) % 3) * VN + (o / 9) * WN] >= 0) use_w |= 1u << (o / 9);
+    const int32_t* tab = c_tab.mp_entry;
     for (int j = j0; j < j1; ++j) {
         // staged plane: canonical offset DZ0 + j of the even plane, mirrored
         // (sz = -1) DZ0 + NDZ - 1 - j of the odd one
         const int zs = zt0 + DZ0 + j;
         const int gi = wp ? NDZ - 1 - j : j;
         const int oz = zs < 0 ? -1 : (zs >= NS ? 1 : 0);
-        // a source plane whose nine neighbour sub-grids at its offset are all
-        // absent is skipped (uniform over the block)
-        bool any = false;
-#pragma unroll
-        for (int o = 0; o < 9; ++o) any |= T.nbr[(o / 3) * 9 + (o % 3) * VN + (oz + 1) * WN] >= 0;
-        if (!any) continue;
+        if (!((use_w >> (oz + 1)) & 1)) continue;
+        // the plane's entry ranges, read before the barrier so that their
+        // latency overlaps it
+        const int fb = c_tab.mp_far_begin[gi], fe = fb + c_tab.mp_far_count[gi];
+        const int nbg = c_tab.mp_near_begin[gi], ne = nbg + c_tab.mp_near_count[gi];
         __syncthreads();
         // stage the 18x18 source window of plane zs: each thread takes up to
         // two cells and issues the loads of both at once (record and mass
@@ -833,7 +841,6 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int 
         Acc<PA> part_store;
         Acc<PA>& part = PR != PR_F64 ? part_store : *reinterpret_cast<Acc<PA>*>(&acc);
         if (PR != PR_F64) part.zero();
-        const int32_t* tab = c_tab.mp_entry;
         // byte offset of an entry's source cell for this lane: the entry's
         // canonical offsets (dx, dy) scaled to bytes, in two signed 16-bit
         // halves, dotted with the lane's mirror signs (one instruction)
@@ -853,7 +860,6 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int 
             const P Z = tw - src[R_DZ];
             pair_any<true, PR>(X, Y, Z, src, oa, acc, part);
         };
-        const int fb = c_tab.mp_far_begin[gi], fe = fb + c_tab.mp_far_count[gi];
         // the wave's far entries fb + wi + k nsplit, k < nk: two independent
         // pairs per iteration, two dependency chains per wave.  FP32 forms
         // with two waves on the plane flush the partial sums once more, after
@@ -872,7 +878,6 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int 
         }
         if (k < nk) one(fb + wi + k * nsplit);
         if (do_near) {
-            const int nbg = c_tab.mp_near_begin[gi], ne = nbg + c_tab.mp_near_count[gi];
             for (int e = nbg + wi; e < ne; e += nsplit) {
                 if (!leafflag[addr(e) >> 4]) continue;
                 one(e);
