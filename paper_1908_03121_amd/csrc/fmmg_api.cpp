@@ -119,7 +119,7 @@ struct fmmg_plan {
     int32_t* d_leaf_sub = nullptr;
     int32_t* d_ref_by_level = nullptr;
     int32_t* d_top_leaf = nullptr;
-    int32_t* d_l2l_tasks = nullptr;
+    L2LTask* d_l2l_tasks = nullptr;
     int32_t* d_top_src = nullptr;
     TopItem* d_top_items = nullptr;
     TopReduce* d_top_reduce = nullptr;

@@ -102,6 +102,20 @@ struct Item {
                    // IT_MP_LEAF: its Lf3 slot
 };
 
+// Downward-pass task: child slot e of a refined parent sub-grid, with what
+// the kernel needs of both, so that a block reads one record instead of the
+// task, then the parent's and then the child's sub-grid entries in turn.
+struct L2LTask {
+    int32_t pidx;   // parent: index into the refined arrays
+    int32_t pred;   // parent: its TopReduce index (top level under the all-pairs rule), else -1
+    int32_t cidx;   // child: index into the leaf or the refined arrays
+    int32_t flags;  // child kind in bit 0 (1 refined), child slot e = ex*4 + ey*2 + ez in
+                    // bits 1..3, the child's number of Lf3 slots from bit 4
+    int32_t slot3;  // leaf child: its first Lf3 slot
+    int32_t psub;   // parent sub-grid id
+    double ch;      // child cell edge
+};
+
 // Leaf targets with refined sources (class 4) are grouped by target parent
 // cell: the rule selects a leaf target's partners by the offset D of the two
 // parent cells alone (|D|^2 <= 8), so the 8 children of one parent cell share

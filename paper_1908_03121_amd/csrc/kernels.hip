@@ -953,14 +953,17 @@ __device__ __forceinline__ void c4_item(const Ctx& cx, int sid, int o0, int o1, 
     const int t = item_tid(), lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int c = lane & 7, tc = lane >> 3;
+    sid = __builtin_amdgcn_readfirstlane(sid);  // one item per block: uniform
     const SubDev& T = cx.subs[sid];
     const double h = T.h;
     const double* tmass = cx.mass + size_t(T.idx) * NCELL;
     const double sfac = cx.corr ? 3.0 : 0.0;  // dg = 3G S
     for (int i = t; i < NLEAF * NCELL; i += 256) tot[i] = 0.0;
     const P oa[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // leaf targets carry no octupole
+    // the 27 neighbour codes, one per lane, loaded once (not once per slot)
+    const int nbc = lane < 27 ? T.nbr[lane] : -1;
     for (int o = o0; o < o1; ++o) {
-        const int code = T.nbr[o];
+        const int code = __builtin_amdgcn_readlane(nbc, o);
         if (o == 13 || code < 0 || !(code & 1)) continue;
         const int ox = o / 9 - 1, oy = (o / 3) % 3 - 1, oz = o % 3 - 1;
         const int sl = c_tab.c4_slab[o];
@@ -1175,6 +1178,7 @@ __device__ __forceinline__ void mono_item(const Ctx& cx, int sid, unsigned char*
     P* box = reinterpret_cast<P*>(smem);
     int* nb = reinterpret_cast<int*>(smem + NB);
     const int t = item_tid();
+    sid = __builtin_amdgcn_readfirstlane(sid);  // one item per block: uniform
     const SubDev& T = cx.subs[sid];
     if (t < 27) nb[t] = T.nbr[t];
     __syncthreads();
@@ -1445,8 +1449,8 @@ __global__ __launch_bounds__(256, 3) void k_persist(Ctx cx, const Item* __restri
 // Total expansion of a top-level target under the all-pairs rule: the sum of
 // its partial slots in a fixed order, scaled by -G (the correction sums S
 // by 3G).
-__device__ __forceinline__ double top_total(const Ctx& cx, const SubDev& T, int k, int q) {
-    const TopReduce R = cx.top_reds[T.red];
+__device__ __forceinline__ double top_total(const Ctx& cx, int red, int k, int q) {
+    const TopReduce R = cx.top_reds[red];
     const double* base = cx.part + (size_t(R.part_begin) * NLOC + k) * NCELL + q;
     double v = 0;
 #pragma unroll
@@ -1467,19 +1471,17 @@ __device__ __forceinline__ double top_total(const Ctx& cx, const SubDev& T, int 
 // Refined children: Lr = shifted parent (their own terms join when they act
 // as parents, so this step does not wait for them).
 // Leaf children: phi = own + o0,  g = own - o1 + dg.
-// grid: one block of 512 per task (parent sub-grid * 8 + child slot).
+// grid: one block of 512 per task (a child slot of a refined parent).
 template <int NG>
-__global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__ tasks, int parent_mode,
+__global__ __launch_bounds__(512) void k_l2l(Ctx cx, const L2LTask* __restrict__ tasks, int parent_mode,
                                              double* __restrict__ phi, double* __restrict__ gout) {
     __shared__ double obuf[4][NCELL];
     __shared__ double par[NLOC + 3][64];  // the octant's 64 parent cells: L (19), COM offset (3)
     rho_flag_out(cx);
     // (dealt to the XCDs in turn, not in runs: this bandwidth-bound pass is
     // 7 % faster with neighbouring tasks spread over all XCDs)
-    const int task = tasks[blockIdx.x];
-    const SubDev& Ps = cx.subs[task >> 3];
-    const int e = task & 7;
-    const SubDev& Cs = cx.subs[Ps.child[e]];
+    const L2LTask tk = tasks[blockIdx.x];
+    const int e = (tk.flags >> 1) & 7;
     const int q = threadIdx.x;
     const int x = q & 7, y = (q >> 3) & 7, z = q >> 6;
     const int ex = 4 * (e >> 2), ey = 4 * ((e >> 1) & 1), ez = 4 * (e & 1);
@@ -1496,11 +1498,11 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
         v[r] = 0.0;
         if (i >= (NLOC + 3) * 64) continue;
         if (k >= NLOC) {
-            v[r] = cx.com[(size_t(Ps.idx) * 3 + (k - NLOC)) * NCELL + pq];
+            v[r] = cx.com[(size_t(tk.pidx) * 3 + (k - NLOC)) * NCELL + pq];
         } else if (parent_mode == PARENT_TOP_PARTS) {
-            v[r] = top_total(cx, Ps, k, pq);
+            v[r] = top_total(cx, tk.pred, k, pq);
         } else {
-            const size_t base = (size_t(Ps.idx) * NLOC + k) * NCELL + pq;
+            const size_t base = (size_t(tk.pidx) * NLOC + k) * NCELL + pq;
             if (parent_mode == PARENT_TOTAL) v[r] = cx.Lr[base];
 #pragma unroll
             for (int gg = 0; gg < NG; ++gg) t[r][gg] = cx.Lp[size_t(gg) * size_t(cx.part_stride) + base];
@@ -1527,11 +1529,11 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
     double o[7];
     for (int k = 0; k < 7; ++k) o[k] = L[T_L3 + k];
     const double sgx = L[T_S], sgy = L[T_S + 1], sgz = L[T_S + 2];
-    const double hc = Cs.h;
+    const double hc = tk.ch;
     double cdx = 0, cdy = 0, cdz = 0;
-    const bool cref = Cs.kind == 1;
+    const bool cref = (tk.flags & 1) != 0;
     if (cref) {
-        const double* cr = cx.com + size_t(Cs.idx) * 3 * NCELL + q;
+        const double* cr = cx.com + size_t(tk.cidx) * 3 * NCELL + q;
         cdx = cr[0];
         cdy = cr[NCELL];
         cdz = cr[2 * NCELL];
@@ -1567,14 +1569,15 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
         sh[T_S] = sgx;
         sh[T_S + 1] = sgy;
         sh[T_S + 2] = sgz;
-        const size_t base = size_t(Cs.idx) * NLOC * NCELL + q;
+        const size_t base = size_t(tk.cidx) * NLOC * NCELL + q;
 #pragma unroll
         for (int k = 0; k < NLOC; ++k) cx.Lr[base + k * NCELL] = sh[k];
     } else {
-        const double* F = cx.Lf + size_t(Cs.idx) * NLEAF * NCELL + q;
+        const double* F = cx.Lf + size_t(tk.cidx) * NLEAF * NCELL + q;
         double f0 = F[0], f1 = F[1 * NCELL], f2 = F[2 * NCELL], f3 = F[3 * NCELL];
-        for (int j = 0; j < Cs.n3; ++j) {  // class-4 slots, in order
-            const double* F3 = cx.Lf3 + size_t(Cs.slot3 + j) * NLEAF * NCELL + q;
+        const int n3 = tk.flags >> 4;
+        for (int j = 0; j < n3; ++j) {  // class-4 slots, in order
+            const double* F3 = cx.Lf3 + size_t(tk.slot3 + j) * NLEAF * NCELL + q;
             f0 += F3[0];
             f1 += F3[1 * NCELL];
             f2 += F3[2 * NCELL];
@@ -1588,8 +1591,8 @@ __global__ __launch_bounds__(512) void k_l2l(Ctx cx, const int32_t* __restrict__
     }
     if (!cref) {
         __syncthreads();
-        phi[size_t(Cs.idx) * NCELL + q] = obuf[0][q];
-        double* g = gout + size_t(Cs.idx) * 3 * NCELL + q;
+        phi[size_t(tk.cidx) * NCELL + q] = obuf[0][q];
+        double* g = gout + size_t(tk.cidx) * 3 * NCELL + q;
         g[0] = obuf[1][q];
         g[NCELL] = obuf[2][q];
         g[2 * NCELL] = obuf[3][q];
@@ -1607,9 +1610,9 @@ __global__ __launch_bounds__(512) void k_leaf_out(Ctx cx, const int32_t* __restr
     const int q = threadIdx.x;
     const int io = io_index(q);
     if (S.red >= 0) {
-        obuf[0][io] = top_total(cx, S, T_L0, q);
+        obuf[0][io] = top_total(cx, S.red, T_L0, q);
         for (int a = 0; a < 3; ++a)
-            obuf[1 + a][io] = -top_total(cx, S, T_L1 + a, q) + top_total(cx, S, T_S + a, q);
+            obuf[1 + a][io] = -top_total(cx, S.red, T_L1 + a, q) + top_total(cx, S.red, T_S + a, q);
     } else {
         const double* F = cx.Lf + size_t(S.idx) * NLEAF * NCELL + q;
         for (int k = 0; k < 4; ++k) {
@@ -1695,7 +1698,7 @@ int persist_blocks_per_cu(int prec) {
     return e == hipSuccess ? nb : 0;
 }
 
-void launch_l2l(const Ctx& a, const int32_t* tasks, int n, int parent_mode, double* phi, double* g) {
+void launch_l2l(const Ctx& a, const L2LTask* tasks, int n, int parent_mode, double* phi, double* g) {
     if (n <= 0) return;
     switch (a.ngroups) {
         case 1: hipLaunchKernelGGL(k_l2l<1>, dim3(n), dim3(512), 0, a.st, a, tasks, parent_mode, phi, g); break;

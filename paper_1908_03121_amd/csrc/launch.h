@@ -58,7 +58,7 @@ struct Queues {
 // ctr: NQUEUE + 1 ints, zero before the first launch and re-armed by each launch
 void launch_persist(const Ctx& a, const Item* items, const Queues& qs, int grid, int* ctr);
 int persist_blocks_per_cu(int prec);
-void launch_l2l(const Ctx& a, const int32_t* tasks, int n, int parent_mode, double* phi, double* g);
+void launch_l2l(const Ctx& a, const L2LTask* tasks, int n, int parent_mode, double* phi, double* g);
 void launch_leaf_out(const Ctx& a, const int32_t* list, int n, double* phi, double* g);
 void launch_check_density(const double* rho, int64_t n, unsigned long long* bad, hipStream_t st);
 void launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st);

@@ -394,7 +394,20 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
             for (const auto& v : lane) longest = std::max(longest, v.size());
             for (size_t r = 0; r < longest; ++r)
                 for (const auto& v : lane)
-                    if (r < v.size()) P.l2l_tasks.push_back(v[r]);
+                    if (r < v.size()) {
+                        const SubDev& Ps = P.subs[size_t(v[r] >> 3)];
+                        const int e = v[r] & 7;
+                        const SubDev& Cs = P.subs[size_t(Ps.child[e])];
+                        L2LTask tk;
+                        tk.pidx = Ps.idx;
+                        tk.pred = -1;  // set below, with the top level's reductions
+                        tk.cidx = Cs.idx;
+                        tk.flags = Cs.kind | (e << 1) | (Cs.n3 << 4);
+                        tk.slot3 = Cs.slot3;
+                        tk.psub = v[r] >> 3;
+                        tk.ch = Cs.h;
+                        P.l2l_tasks.push_back(tk);
+                    }
         }
     }
     P.l2l_begin[size_t(2 * P.max_level)] = int32_t(P.l2l_tasks.size());
@@ -444,6 +457,7 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
             }
         }
     }
+    for (L2LTask& tk : P.l2l_tasks) tk.pred = P.subs[size_t(tk.psub)].red;
     build_items(&P, 1, true, 0);
     return 0;
 }

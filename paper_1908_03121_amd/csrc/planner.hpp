@@ -50,7 +50,7 @@ struct HostPlan {
     // downward tasks, parent sub id * 8 + child slot, grouped by parent level
     // and child kind: level l's refined children are [l2l_begin[2l],
     // l2l_begin[2l+1]), its leaf children [l2l_begin[2l+1], l2l_begin[2l+2])
-    std::vector<int32_t> l2l_tasks;
+    std::vector<L2LTask> l2l_tasks;
     std::vector<int32_t> l2l_begin;
     int32_t n_slot3 = 0;               // Lf3 slots: one per class-4 item
     struct C4Chunk { int32_t sub, o_begin, o_end, slot, steps; };
