@@ -117,7 +117,7 @@ struct fmmg_plan {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join_mono = nullptr;
     SubDev* d_subs = nullptr;
     int32_t* d_leaf_sub = nullptr;
-    int32_t* d_ref_by_level = nullptr;
+    M2MTask* d_m2m_tasks = nullptr;
     int32_t* d_top_leaf = nullptr;
     L2LTask* d_l2l_tasks = nullptr;
     int32_t* d_top_src = nullptr;
@@ -170,7 +170,7 @@ void drop_graph(fmmg_plan* p) {
 void release(fmmg_plan* p) {
     if (!p) return;
     drop_graph(p);
-    void* bufs[] = {p->d_subs, p->d_leaf_sub, p->d_ref_by_level, p->d_top_leaf, p->d_l2l_tasks,
+    void* bufs[] = {p->d_subs, p->d_leaf_sub, p->d_m2m_tasks, p->d_top_leaf, p->d_l2l_tasks,
                     p->d_top_src, p->d_top_items, p->d_top_reduce, p->d_items_class, p->d_items_lpt, p->d_items_xcd,
                     p->ws.counter, p->ws.mass, p->ws.rec, p->ws.com, p->ws.Lp, p->ws.Lr, p->ws.Lf, p->ws.Lf3,
                     p->ws.part, p->d_bad, p->d_rho_bad};
@@ -338,9 +338,9 @@ int64_t enqueue_solve(fmmg_plan* p, const fmmg_ws& w, const double* rho, double*
     auto m2m = [&](const Ctx& x, int l) {
         const int b = hp.level_ref_begin[size_t(l)], m = hp.level_leafpar_end[size_t(l)],
                   e = hp.level_ref_begin[size_t(l) + 1];
-        launch_m2m_leafpar(x, p->d_ref_by_level + b, m - b);
+        launch_m2m_leafpar(x, p->d_m2m_tasks + b, m - b);
         cnt(m - b);
-        launch_m2m(x, p->d_ref_by_level + m, e - m);
+        launch_m2m(x, p->d_m2m_tasks + m, e - m);
         cnt(e - m);
     };
     const int kinds[IT_KINDS] = {IT_TOP, IT_MONO, IT_MP_REF, IT_MP_LEAF};
@@ -812,7 +812,7 @@ fmmg_status fmmg_plan_create(fmmg_plan** out, const fmmg_tree_desc* trees, int32
 #define UP(dst, src, cap, what) if ((s = dev_upload(&(dst), (src), (cap), st, what)) != FMMG_OK) { release(p); return s; }
         UP(p->d_subs, hp.subs, 0, "sub-grid table");
         UP(p->d_leaf_sub, hp.leaf_sub, 0, "leaf list");
-        UP(p->d_ref_by_level, hp.ref_by_level, 0, "level lists");
+        UP(p->d_m2m_tasks, hp.m2m_tasks, 0, "upward tasks");
         UP(p->d_top_leaf, hp.top_leaf, 0, "top leaf list");
         UP(p->d_l2l_tasks, hp.l2l_tasks, 0, "downward tasks");
         UP(p->d_top_src, hp.top_src, 0, "top source list");

@@ -102,6 +102,15 @@ struct Item {
                    // IT_MP_LEAF: its Lf3 slot
 };
 
+// Upward-pass task: a refined parent sub-grid with what the kernels need of
+// it and its 8 children, read as one record per block.
+struct M2MTask {
+    int32_t pidx;     // parent: index into the refined arrays
+    int32_t ckinds;   // bit e: child e is refined
+    int32_t cidx[8];  // child e: index into the leaf or the refined arrays
+    double ph;        // parent cell edge
+};
+
 // Downward-pass task: child slot e of a refined parent sub-grid, with what
 // the kernel needs of both, so that a block reads one record instead of the
 // task, then the parent's and then the child's sub-grid entries in turn.

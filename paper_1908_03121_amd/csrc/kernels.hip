@@ -481,23 +481,24 @@ __device__ __forceinline__ void leaf_octet(const double (&mc)[2][2][2], double h
 //   M2 = S2 - m d d,   M3 = S3 - sym(S2 d) + 2 m d d d,
 // and stored trace-free (children's trace parts only feed trace parts).
 // grid: (refined sub-grids of the level) x 8 octants, 512 threads.
-__global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__ list) {
+__global__ __launch_bounds__(512) void k_m2m(Ctx cx, const M2MTask* __restrict__ list) {
     __shared__ double red[4][16][20];
     __shared__ double rin[NCELL + NCELL / 8];  // leaf densities, I/O order, one pad per z-row
-    const SubDev& Ps = cx.subs[list[blockIdx.x >> 3]];
+    const M2MTask& tk = list[blockIdx.x >> 3];
     const int e = blockIdx.x & 7;
-    const SubDev& Cs = cx.subs[Ps.child[e]];
+    const int cidx = tk.cidx[e], pidx = tk.pidx;
+    const bool cref = ((tk.ckinds >> e) & 1) != 0;
     const int q = threadIdx.x;
-    if (Cs.kind == 0) {
-        const double v = cx.rho[size_t(Cs.idx) * NCELL + q];  // coalesced
-        check_rho(cx, v, size_t(Cs.idx) * NCELL + q, true);
+    if (!cref) {
+        const double v = cx.rho[size_t(cidx) * NCELL + q];  // coalesced
+        check_rho(cx, v, size_t(cidx) * NCELL + q, true);
         rin[q + (q >> 3)] = v;
         __syncthreads();
     }
     const int x = q & 7, y = (q >> 3) & 7, z = q >> 6;
-    const double hc = Cs.h;
+    const double hc = 0.5 * tk.ph;
     double v[20];
-    if (Cs.kind == 0) {
+    if (!cref) {
         // leaf child: point masses at the cell centres, r0 = s a with sign
         // vector s in {-1, 1}^3 and a = h/2, so the sums need only the 8
         // signed mass sums M, S_i = sum s_i m, S_ij = sum s_i s_j m (i != j),
@@ -505,7 +506,7 @@ __global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__
         const double h3 = hc * hc * hc;
         {
             const int io = io_index(q);
-            cx.mass[size_t(Cs.idx) * NCELL + q] = rin[io + (io >> 3)] * h3;
+            cx.mass[size_t(cidx) * NCELL + q] = rin[io + (io >> 3)] * h3;
         }
         if ((x | y | z) & 1) return;
         double mc[2][2][2];
@@ -521,7 +522,7 @@ __global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__
         leaf_octet(mc, hc, v);
     } else {
         double r[NREC];
-        load_rec(cx.rec, size_t(Cs.idx) * NCELL + q, r);
+        load_rec(cx.rec, size_t(cidx) * NCELL + q, r);
         const double w = r[R_M];
         const double dx = r[R_DX], dy = r[R_DY], dz = r[R_DZ];
         const double qxx = r[R_Q + 0], qyy = r[R_Q + 1], qxy = r[R_Q + 2];
@@ -572,7 +573,7 @@ __global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__
     }
     const int ex = e >> 2, ey = (e >> 1) & 1, ez = e & 1;
     const int pq = ((4 * ez + (z >> 1)) * NS + (4 * ey + (y >> 1))) * NS + (4 * ex + (x >> 1));
-    m2m_store(v, cx.rec + (size_t(Ps.idx) * NCELL + pq) * NREC, cx.com + size_t(Ps.idx) * 3 * NCELL + pq);
+    m2m_store(v, cx.rec + (size_t(pidx) * NCELL + pq) * NREC, cx.com + size_t(pidx) * 3 * NCELL + pq);
 }
 
 // A refined sub-grid whose 8 children are all leaves: one block per parent.
@@ -581,15 +582,15 @@ __global__ __launch_bounds__(512) void k_m2m(Ctx cx, const int32_t* __restrict__
 // order, and each thread forms one parent cell from its 8 point masses, so
 // that the record is written whole (coalesced per component).
 // grid: (such parents of the level), 512 threads.
-__global__ __launch_bounds__(512) void k_m2m_leafpar(Ctx cx, const int32_t* __restrict__ list) {
+__global__ __launch_bounds__(512) void k_m2m_leafpar(Ctx cx, const M2MTask* __restrict__ list) {
     __shared__ double rin[8][NCELL + NCELL / 8];  // per child, I/O order, one pad per z-row
-    const SubDev& Ps = cx.subs[list[blockIdx.x]];
+    const M2MTask& tk = list[blockIdx.x];
     const int q = threadIdx.x;
     double rv[8];
     size_t cb[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-        cb[e] = size_t(cx.subs[Ps.child[e]].idx) * NCELL;
+        cb[e] = size_t(tk.cidx[e]) * NCELL;
         rv[e] = cx.rho[cb[e] + q];  // coalesced
     }
 #pragma unroll
@@ -598,7 +599,7 @@ __global__ __launch_bounds__(512) void k_m2m_leafpar(Ctx cx, const int32_t* __re
         rin[e][q + (q >> 3)] = rv[e];
     }
     __syncthreads();
-    const double hc = 0.5 * Ps.h, h3 = hc * hc * hc;
+    const double hc = 0.5 * tk.ph, h3 = hc * hc * hc;
     const int io = io_index(q);
 #pragma unroll
     for (int e = 0; e < 8; ++e) cx.mass[cb[e] + q] = rin[e][io + (io >> 3)] * h3;
@@ -619,7 +620,7 @@ __global__ __launch_bounds__(512) void k_m2m_leafpar(Ctx cx, const int32_t* __re
             }
     double v[20];
     leaf_octet(mc, hc, v);
-    m2m_store(v, cx.rec + (size_t(Ps.idx) * NCELL + q) * NREC, cx.com + size_t(Ps.idx) * 3 * NCELL + q);
+    m2m_store(v, cx.rec + (size_t(tk.pidx) * NCELL + q) * NREC, cx.com + size_t(tk.pidx) * 3 * NCELL + q);
 }
 
 // ---------------------------------------------------------------------------
@@ -1654,11 +1655,11 @@ void launch_p2m_top(const Ctx& a, const int32_t* list, int n) {
     if (n > 0) hipLaunchKernelGGL(k_p2m_top, dim3(n), dim3(512), 0, a.st, a, list);
 }
 
-void launch_m2m(const Ctx& a, const int32_t* list, int n) {
+void launch_m2m(const Ctx& a, const M2MTask* list, int n) {
     if (n > 0) hipLaunchKernelGGL(k_m2m, dim3(n * 8), dim3(512), 0, a.st, a, list);
 }
 
-void launch_m2m_leafpar(const Ctx& a, const int32_t* list, int n) {
+void launch_m2m_leafpar(const Ctx& a, const M2MTask* list, int n) {
     if (n > 0) hipLaunchKernelGGL(k_m2m_leafpar, dim3(n), dim3(512), 0, a.st, a, list);
 }
 

@@ -46,9 +46,9 @@ enum { PARENT_TOTAL = 0, PARENT_TOP_PARTS = 1, PARENT_OWN_PARTS = 2 };
 
 hipError_t upload_tables(const StencilTables* t, hipStream_t st);
 void launch_p2m_top(const Ctx& a, const int32_t* list, int n);
-void launch_m2m(const Ctx& a, const int32_t* list, int n);
+void launch_m2m(const Ctx& a, const M2MTask* list, int n);
 // parents whose 8 children are all leaves: one block per parent
-void launch_m2m_leafpar(const Ctx& a, const int32_t* list, int n);
+void launch_m2m_leafpar(const Ctx& a, const M2MTask* list, int n);
 void launch_class(const Ctx& a, int kind, const Item* items, int n);
 // The item queues of a persistent launch: queue q is items [begin[q],
 // begin[q + 1]) (offsets into the launch's list; begin[0] = 0).

@@ -369,6 +369,20 @@ int build_host_plan(const TreeIn* trees, int n_trees, int top_full, int top_chun
         }
     }
     P.level_ref_begin[size_t(P.max_level) + 1] = int32_t(P.ref_by_level.size());
+    P.m2m_tasks.clear();
+    for (int32_t s : P.ref_by_level) {
+        const SubDev& Ps = P.subs[size_t(s)];
+        M2MTask tk;
+        tk.pidx = Ps.idx;
+        tk.ckinds = 0;
+        for (int e = 0; e < 8; ++e) {
+            const SubDev& Cs = P.subs[size_t(Ps.child[e])];
+            tk.cidx[e] = Cs.idx;
+            tk.ckinds |= Cs.kind << e;
+        }
+        tk.ph = Ps.h;
+        P.m2m_tasks.push_back(tk);
+    }
     P.level_leaves.assign(size_t(P.max_level) + 1, 0);
     for (const SubDev& S : P.subs)
         if (S.kind == 0) P.level_leaves[size_t(S.level)]++;

@@ -43,6 +43,7 @@ struct HostPlan {
     std::vector<int32_t> mp_leaf;      // leaf targets with a refined neighbour
     std::vector<int32_t> level_ref_begin;  // refined sub ids sorted by level: [l, l+1)
     std::vector<int32_t> ref_by_level;
+    std::vector<M2MTask> m2m_tasks;          // the upward pass's record of each, same order
     std::vector<int32_t> level_leafpar_end;  // level l's parents with 8 leaf children:
                                              // [level_ref_begin[l], level_leafpar_end[l])
     std::vector<int32_t> top_leaf;     // top-level leaves (output straight from own terms)
