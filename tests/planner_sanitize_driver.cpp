@@ -44,6 +44,37 @@ int main(int argc, char** argv) {
                 printf("%s top_full=%d error %d %s\n", name, top_full, rc, err.c_str());
                 return 1;
             }
+            // the upward and downward passes' task records agree with the
+            // sub-grid table they summarise
+            {
+                size_t n_ref = 0;
+                for (const SubDev& S : hp.subs) n_ref += S.kind == 1;
+                // every refined sub-grid is a parent once upward and 8 times downward
+                bool ok = hp.m2m_tasks.size() == hp.ref_by_level.size() && hp.ref_by_level.size() == n_ref &&
+                          hp.l2l_tasks.size() == 8 * n_ref;
+                for (size_t i = 0; ok && i < hp.m2m_tasks.size(); ++i) {
+                    const M2MTask& tk = hp.m2m_tasks[i];
+                    const SubDev& Ps = hp.subs[size_t(hp.ref_by_level[i])];
+                    ok = tk.pidx == Ps.idx && tk.ph == Ps.h;
+                    for (int e = 0; ok && e < 8; ++e) {
+                        const SubDev& Cs = hp.subs[size_t(Ps.child[e])];
+                        ok = tk.cidx[e] == Cs.idx && ((tk.ckinds >> e) & 1) == Cs.kind && Cs.h == 0.5 * Ps.h;
+                    }
+                }
+                for (size_t i = 0; ok && i < hp.l2l_tasks.size(); ++i) {
+                    const L2LTask& tk = hp.l2l_tasks[i];
+                    const SubDev& Ps = hp.subs[size_t(tk.psub)];
+                    const int e = (tk.flags >> 1) & 7;
+                    const SubDev& Cs = hp.subs[size_t(Ps.child[e])];
+                    ok = Ps.kind == 1 && tk.pidx == Ps.idx && tk.pred == Ps.red && tk.cidx == Cs.idx &&
+                         (tk.flags & 1) == Cs.kind && (tk.flags >> 4) == Cs.n3 && tk.slot3 == Cs.slot3 &&
+                         tk.ch == Cs.h;
+                }
+                if (!ok) {
+                    printf("%s top_full=%d pass task records wrong\n", name, top_full);
+                    return 1;
+                }
+            }
             for (int g = 1; g <= MAX_GROUPS; ++g)
                 for (int split = 0; split < 2; ++split)
                 for (int pairs = 0; pairs < 2; ++pairs) {
