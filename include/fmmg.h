@@ -54,7 +54,7 @@
 extern "C" {
 #endif
 
-#define FMMG_VERSION 5
+#define FMMG_VERSION 6
 
 typedef struct fmmg_plan fmmg_plan; /* opaque; owns device tables and workspaces */
 
@@ -215,6 +215,7 @@ typedef struct {
     int32_t max_level;
     int32_t n_trees;
     int32_t sweep_y_targets;  /* refined targets whose plane items run along y     */
+    int32_t sweep_x_targets;  /* refined targets whose plane items run along x     */
 } fmmg_stats;
 
 /* Fills *opt with the defaults listed above (interface convention; no
@@ -320,7 +321,7 @@ const char* fmmg_last_error(void);
 /* Host-only: validates the trees and counts the ordered pairs per class that
  * a solve with this top_mode evaluates under the interaction rule of Sec. 4.3
  * (no device is touched).  stats->pairs, pairs_top, paper_flops, n_leaves,
- * n_refined, max_level, n_trees and sweep_y_targets are filled; the launch
+ * n_refined, max_level, n_trees, sweep_y_targets and sweep_x_targets are filled; the launch
  * counters are zero. */
 fmmg_status fmmg_count_pairs(const fmmg_tree_desc* trees, int32_t n_trees,
                              fmmg_top_mode top_mode, fmmg_stats* stats);

@@ -78,7 +78,7 @@ class fmmg_stats(C.Structure):
     _fields_ = [("pairs", C.c_int64 * 4), ("pairs_top", C.c_int64), ("launches", C.c_int64),
                 ("solves", C.c_int64), ("paper_flops", C.c_double), ("n_leaves", C.c_int64),
                 ("n_refined", C.c_int64), ("max_level", C.c_int32), ("n_trees", C.c_int32),
-                ("sweep_y_targets", C.c_int32)]
+                ("sweep_y_targets", C.c_int32), ("sweep_x_targets", C.c_int32)]
 
     def as_dict(self):
         return {"pairs": list(self.pairs), "pairs_top": int(self.pairs_top),
@@ -86,6 +86,7 @@ class fmmg_stats(C.Structure):
                 "paper_flops": float(self.paper_flops), "n_leaves": int(self.n_leaves),
                 "n_refined": int(self.n_refined), "max_level": int(self.max_level),
                 "n_trees": int(self.n_trees), "sweep_y_targets": int(self.sweep_y_targets),
+                "sweep_x_targets": int(self.sweep_x_targets),
                 "total_pairs": int(sum(self.pairs) + self.pairs_top)}
 
 

@@ -749,6 +749,7 @@ fmmg_status fmmg_count_pairs(const fmmg_tree_desc* trees, int32_t n_trees, fmmg_
         stats->max_level = hp.max_level;
         stats->n_trees = n_trees;
         stats->sweep_y_targets = hp.sweep_y_targets;
+        stats->sweep_x_targets = hp.sweep_x_targets;
         return FMMG_OK;
     } catch (const std::bad_alloc&) {
         return fail(FMMG_ENOMEM, "host allocation failed");
@@ -1076,6 +1077,7 @@ fmmg_status fmmg_get_stats(const fmmg_plan* p, fmmg_stats* s) {
     s->max_level = p->hp.max_level;
     s->n_trees = p->hp.n_trees;
     s->sweep_y_targets = p->hp.sweep_y_targets;
+    s->sweep_x_targets = p->hp.sweep_x_targets;
     return FMMG_OK;
 }
 

@@ -97,8 +97,9 @@ struct Item {
     int32_t a;     // IT_MP_REF: 2 pz in bits 0..3 for the parent plane pz along
                    // the sweep axis, bit 4: target plane 2 pz, bit 5: 2 pz + 1;
                    // IT_MP_LEAF: neighbour slots [a & 255, a >> 8)
-    int32_t b;     // IT_MP_REF: plane group in bits 0..2, sweep in bit 3
-                   // (0: planes along z, lanes on (x, y); 1: along y, lanes on (x, z));
+    int32_t b;     // IT_MP_REF: plane group in bits 0..2, sweep in bits 3..4
+                   // (0: planes along z, lanes on (x, y); 1: along y, lanes on
+                   // (x, z); 2: along x, lanes on (z, y));
                    // IT_MP_LEAF: its Lf3 slot
 };
 

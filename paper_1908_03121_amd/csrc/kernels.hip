@@ -675,6 +675,52 @@ __device__ __forceinline__ void swap_yz_o(T* o) {
     o[5] = -o2 - o6;
     o[6] = -o1 - o5;
 }
+// The same for a swap of the x and z axes (xx <- zz, xy <- yz, yz <- xy;
+// xxx <- zzz, xxy <- yzz, xxz <- xzz, xyy <- yyz, yyz <- xyy).
+template <typename T>
+__device__ __forceinline__ void swap_xz_q(T* q) {
+    const T q0 = q[0], q1 = q[1], q2 = q[2];
+    q[0] = -q0 - q1;
+    q[2] = q[4];
+    q[4] = q2;
+}
+template <typename T>
+__device__ __forceinline__ void swap_xz_o(T* o) {
+    const T o0 = o[0], o1 = o[1], o2 = o[2], o3 = o[3], o5 = o[5], o6 = o[6];
+    o[0] = -o2 - o6;
+    o[1] = -o1 - o5;
+    o[2] = -o0 - o3;
+    o[3] = o6;
+    o[6] = o3;
+}
+
+// Sweep frames (u, v, w): (x, y, z) for sweep 0, (x, z, y) for sweep 1,
+// (z, y, x) for sweep 2; the cell-index strides of u, v and w and the
+// neighbour-code strides of their sub-grid offsets (code (ox+1)*9 +
+// (oy+1)*3 + (oz+1)), and the maps of a record or of the Taylor components
+// into the frame and back (each its own inverse).
+template <int SWEEP>
+struct Frame {
+    static constexpr int US = SWEEP == 2 ? 64 : 1, VS = SWEEP == 1 ? 64 : 8;
+    static constexpr int WS = SWEEP == 0 ? 64 : (SWEEP == 1 ? 8 : 1);
+    static constexpr int UN = SWEEP == 2 ? 1 : 9, VN = SWEEP == 1 ? 1 : 3;
+    static constexpr int WN = SWEEP == 0 ? 1 : (SWEEP == 1 ? 3 : 9);
+    template <typename T>
+    __device__ static void vec(T& x, T& y, T& z) {
+        if (SWEEP == 1) swap_yz(y, z);
+        if (SWEEP == 2) swap_yz(x, z);
+    }
+    template <typename T>
+    __device__ static void quad(T* q) {
+        if (SWEEP == 1) swap_yz_q(q);
+        if (SWEEP == 2) swap_xz_q(q);
+    }
+    template <typename T>
+    __device__ static void oct(T* o) {
+        if (SWEEP == 1) swap_yz_o(o);
+        if (SWEEP == 2) swap_xz_o(o);
+    }
+};
 
 // Refined-target item: target planes of refined sub-grid sid among the two
 // planes 2 pz and 2 pz + 1 (the children of one plane of parent cells)
@@ -689,7 +735,14 @@ __device__ __forceinline__ void swap_yz_o(T* o) {
 // workloads too small to fill the GPU otherwise).  The entries: every
 // existing source over the far ones, leaf sources also over the near ones
 // (classes 1 + 2).
-// The sweep frame (u, v, w) puts the target planes at w = 2 pz, 2 pz + 1 and the lanes on
+// The sweep frame (u, v, w) puts the target planes at w = 2 pz, 2 pz + 1 and
+// the lanes on (u, v): sweep 0 is (x, y, z); sweep 1 is (x, z, y) and sweep 2
+// (z, y, x), chosen by the planner for targets whose sources lie mostly beside
+// them in y or in x, so that whole source planes without sources are
+// skipped.  A record is 16 contiguous values in any frame (staging stays
+// coalesced per cell), and the stencil is symmetric under the axis swaps, so
+// one set of tables serves all three: records are swapped into the frame when
+// staged and the results swapped back before they are stored.
 template <int PR, int SWEEP>
 __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int group, unsigned char* smem) {
     // P: staged source data; PA: the pair terms' partial sums
@@ -723,9 +776,9 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int 
     const int tidx = T.idx;
     // cell index strides of the frame's v and w, and neighbour-code strides
     // of their sub-grid offsets (x: stride 1, code stride 9, in both frames)
-    constexpr int VS = SWEEP ? 64 : 8, WS = SWEEP ? 8 : 64;
-    constexpr int VN = SWEEP ? 1 : 3, WN = SWEEP ? 3 : 1;
-    const int q = zt * WS + y * VS + x;
+    using F = Frame<SWEEP>;
+    constexpr int US = F::US, VS = F::VS, WS = F::WS, UN = F::UN, VN = F::VN, WN = F::WN;
+    const int q = zt * WS + y * VS + x * US;
     const int sx = 1 - 2 * (x & 1), sy = 1 - 2 * (y & 1);
 
     // target data
@@ -738,10 +791,8 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int 
         const double os = mA > 0 ? 1.0 / (2.0 * mA) : 0.0;
 #pragma unroll
         for (int k = 0; k < 7; ++k) oa[k] = P(rt[R_O + k] * os);
-        if (SWEEP) {
-            swap_yz(dAy, dAz);
-            swap_yz_o(oa);
-        }
+        F::vec(dAx, dAy, dAz);
+        F::oct(oa);
         oa[7] = -oa[0] - oa[3];
         oa[8] = -oa[1] - oa[5];
     }
@@ -770,7 +821,7 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int 
     unsigned use_w = 0;
 #pragma unroll
     for (int o = 0; o < 27; ++o)
-        if (T.nbr[(o % 3) * 9 + ((o / 3) % 3) * VN + (o / 9) * WN] >= 0) use_w |= 1u << (o / 9);
+        if (T.nbr[(o % 3) * UN + ((o / 3) % 3) * VN + (o / 9) * WN] >= 0) use_w |= 1u << (o / 9);
     const int32_t* tab = c_tab.mp_entry;
     for (int j = j0; j < j1; ++j) {
         // staged plane: canonical offset DZ0 + j of the even plane, mirrored
@@ -798,8 +849,8 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int 
                     const int lx = wx - REACH, ly = wy - REACH;
                     const int ox = lx < 0 ? -1 : (lx >= NS ? 1 : 0);
                     const int oy = ly < 0 ? -1 : (ly >= NS ? 1 : 0);
-                    const int code = nb[(ox + 1) * 9 + (oy + 1) * VN + (oz + 1) * WN];
-                    const int cq = lz * WS + (ly - NS * oy) * VS + (lx - NS * ox);
+                    const int code = nb[(ox + 1) * UN + (oy + 1) * VN + (oz + 1) * WN];
+                    const int cq = lz * WS + (ly - NS * oy) * VS + (lx - NS * ox) * US;
                     const int kind = code < 0 ? -1 : (code & 1), nidx = code >> 1;
                     // leaf and absent cells read the zero record; a leaf
                     // cell's mass then replaces its zero mass
@@ -808,11 +859,9 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int 
                     load_rec(cx.rec, kind == 1 ? size_t(nidx) * NCELL + cq : size_t(cx.rec_zero), v);
                     const double mm = *mp;
                     if (kind == 0) v[R_M] = mm;
-                    if (SWEEP) {
-                        swap_yz(v[R_DY], v[R_DZ]);
-                        swap_yz_q(v + R_Q);
-                        swap_yz_o(v + R_O);
-                    }
+                    F::vec(v[R_DX], v[R_DY], v[R_DZ]);
+                    F::quad(v + R_Q);
+                    F::oct(v + R_O);
                     // the COM offset becomes a position (frame coordinates of the
                     // cell centre plus the offset); moments scaled by stage_scale
                     const double pos[3] = {double(lx), double(ly), double(zs)};
@@ -896,12 +945,11 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int 
         // carry no mass either, so no momentum is involved)
         if (!(mA > 0)) acc.s[0] = acc.s[1] = acc.s[2] = 0.0;
         acc.out(v);
-        if (SWEEP) {  // back from the frame
-            swap_yz(v[T_L1 + 1], v[T_L1 + 2]);
-            swap_yz_q(v + T_L2);
-            swap_yz_o(v + T_L3);
-            swap_yz(v[T_S + 1], v[T_S + 2]);
-        }
+        // back from the frame
+        F::vec(v[T_L1], v[T_L1 + 1], v[T_L1 + 2]);
+        F::quad(v + T_L2);
+        F::oct(v + T_L3);
+        F::vec(v[T_S], v[T_S + 1], v[T_S + 2]);
 #pragma unroll
         for (int k = 0; k < NLOC; ++k) red[(w * NLOC + k) * 64 + cl] = v[k];
     }
@@ -909,21 +957,21 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int 
     const double G = cx.G;
     const double gs = use_corr ? 3.0 * G : 0.0;  // dg = 3G S
     // reduction slot l = v*8 + u of plane p holds target cell
-    // (2 pz + p)*WS + v*VS + u
+    // (2 pz + p)*WS + v*VS + u*US
     double* out = cx.Lp + size_t(group) * size_t(cx.part_stride) + size_t(tidx) * NLOC * NCELL + zt0 * WS;
     if (both) {
         for (int i = t; i < 2 * NLOC * 64; i += 256) {
             const int p = i >= NLOC * 64, r = i - p * (NLOC * 64);
             const int k = r >> 6, l = r & 63;
             const double v = red[((2 * p) * NLOC + k) * 64 + l] + red[((2 * p + 1) * NLOC + k) * 64 + l];
-            out[p * WS + k * NCELL + (l >> 3) * VS + (l & 7)] = (k >= T_S ? gs : -G) * v;
+            out[p * WS + k * NCELL + (l >> 3) * VS + (l & 7) * US] = (k >= T_S ? gs : -G) * v;
         }
     } else {
         for (int i = t; i < NLOC * 64; i += 256) {
             const int k = i >> 6, l = i & 63;
             const double v = red[(0 * NLOC + k) * 64 + l] + red[(1 * NLOC + k) * 64 + l] +
                              red[(2 * NLOC + k) * 64 + l] + red[(3 * NLOC + k) * 64 + l];
-            out[wp * WS + k * NCELL + (l >> 3) * VS + (l & 7)] = (k >= T_S ? gs : -G) * v;
+            out[wp * WS + k * NCELL + (l >> 3) * VS + (l & 7) * US] = (k >= T_S ? gs : -G) * v;
         }
     }
 }
@@ -1388,7 +1436,8 @@ template <int PR>
 __device__ __forceinline__ void run_item(const Ctx& cx, const Item& it, unsigned char* smem) {
     switch (it.kind) {
         case IT_MP_REF:
-            if (it.b >> 3) mp_item<PR, 1>(cx, it.sub, it.a, it.b & 7, smem);
+            if ((it.b >> 3) == 1) mp_item<PR, 1>(cx, it.sub, it.a, it.b & 7, smem);
+            else if ((it.b >> 3) == 2) mp_item<PR, 2>(cx, it.sub, it.a, it.b & 7, smem);
             else mp_item<PR, 0>(cx, it.sub, it.a, it.b & 7, smem);
             break;
         case IT_MP_LEAF: c4_item<PR>(cx, it.sub, it.a & 255, it.a >> 8, it.b, smem); break;
@@ -1405,7 +1454,8 @@ __global__ __launch_bounds__(256) void k_class(Ctx cx, const Item* __restrict__ 
     __shared__ __attribute__((aligned(16))) unsigned char smem[L::BYTES];
     const Item it = items[xcd_run_index()];
     if (KIND == IT_MP_REF) {
-        if (it.b >> 3) mp_item<PR, 1>(cx, it.sub, it.a, it.b & 7, smem);
+        if ((it.b >> 3) == 1) mp_item<PR, 1>(cx, it.sub, it.a, it.b & 7, smem);
+        else if ((it.b >> 3) == 2) mp_item<PR, 2>(cx, it.sub, it.a, it.b & 7, smem);
         else mp_item<PR, 0>(cx, it.sub, it.a, it.b & 7, smem);
     }
     else if (KIND == IT_MP_LEAF) c4_item<PR>(cx, it.sub, it.a & 255, it.a >> 8, it.b, smem);

@@ -488,13 +488,15 @@ void build_items(HostPlan* Pp, int ngroups, bool split, int pairs) {
     struct Costed { Item it; double cost; int level; };
     std::vector<Costed> all;
     // a source plane with no usable neighbour among the 9 at its offset along
-    // the sweep axis (z for sweep 0, y for sweep 1) is skipped by the kernels;
-    // the estimates count the planes they visit
+    // the sweep axis (z for sweep 0, y for sweep 1, x for sweep 2) is skipped
+    // by the kernels; the estimates count the planes they visit.  Neighbour-
+    // code strides of the frame axes (u, v, w): (x, y, z), (x, z, y), (z, y, x)
     auto plane_used = [&](const SubDev& S, int sweep, int ws) {
         const int ow = ws < 0 ? -1 : (ws >= NS ? 1 : 0);
-        const int VN = sweep ? 1 : 3, WN = sweep ? 3 : 1;
+        const int UN = sweep == 2 ? 1 : 9, VN = sweep == 1 ? 1 : 3;
+        const int WN = sweep == 0 ? 1 : (sweep == 1 ? 3 : 9);
         for (int o = 0; o < 9; ++o)
-            if (S.nbr[(o / 3) * 9 + (o % 3) * VN + (ow + 1) * WN] >= 0) return true;
+            if (S.nbr[(o / 3) * UN + (o % 3) * VN + (ow + 1) * WN] >= 0) return true;
         return false;
     };
     // stencil entries that target plane zt visits over the canonical plane
@@ -506,19 +508,25 @@ void build_items(HostPlan* Pp, int ngroups, bool split, int pairs) {
                 n += tab.mp_far_count[i] + (nearc ? tab.mp_near_count[i] : 0);
         return n;
     };
-    // the sweep of a target: the frame that visits fewer entries (z on a tie)
+    // the sweep of a target: the frame that visits the fewest entries (on a
+    // tie the first of z, y, x)
     auto best_sweep = [&](const SubDev& S, bool nearc) {
-        double n[2] = {0, 0};
-        for (int sw = 0; sw < 2; ++sw)
+        double n[3] = {0, 0, 0};
+        for (int sw = 0; sw < 3; ++sw)
             for (int zt = 0; zt < NS; ++zt) n[sw] += visited(S, sw, zt, 0, NDZ, nearc);
-        return n[1] < n[0] ? 1 : 0;
+        int best = 0;
+        for (int sw = 1; sw < 3; ++sw)
+            if (n[sw] < n[best]) best = sw;
+        return best;
     };
     P.sweep_y_targets = 0;
+    P.sweep_x_targets = 0;
     for (int32_t s : P.mp_ref) {
         const SubDev& S = P.subs[size_t(s)];
         const bool nearc = (S.flags & 1) != 0;
         const int sw = best_sweep(S, nearc);
-        P.sweep_y_targets += sw;
+        P.sweep_y_targets += sw == 1;
+        P.sweep_x_targets += sw == 2;
         // per plane of parent cells (target planes 2 pz, 2 pz + 1) and group
         // of staged source planes j (canonical offsets j of the even plane and
         // NDZ - 1 - j of the odd one): one item of both planes, or one per plane

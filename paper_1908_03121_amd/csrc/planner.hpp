@@ -64,6 +64,7 @@ struct HostPlan {
     int split = 0;                     // split level of the current lists (0: one branch)
     int split_natural = 0;             // split level the estimates give
     int32_t sweep_y_targets = 0;       // refined targets whose plane items run along y
+    int32_t sweep_x_targets = 0;       // refined targets whose plane items run along x
     std::vector<Item> items_class;     // grouped by branch, then kind, in list order
     int32_t class_begin[2][IT_KINDS + 1] = {{0, 0, 0, 0, 0}, {0, 0, 0, 0, 0}};
     // persistent lists, branch 0 then branch 1 (the same items per branch in

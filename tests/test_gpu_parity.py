@@ -552,14 +552,18 @@ def test_mixed_amr_error_bounds(shape, precision):
     check_form("amr", precision, errs, f, tq)
 
 
-def flat_forest(seed):
+def flat_forest(seed, axis=1):
     """A 3 x 1 x 3 forest of refined level-0 sub-grids (level 1 is 6 x 2 x 6
     sub-grids, one side in y always absent), a few level-1 sub-grids refined
     once more: refined targets whose sources lie beside them in y, the case
-    where plane items run along y, and leaf targets beside refined ones."""
+    where plane items run along y, and leaf targets beside refined ones.
+    axis = 0: the same with x as the thin axis (1 x 3 x 3, plane items along
+    x)."""
     rng = np.random.default_rng(seed)
-    subs = [(0, x, 0, z) for x in range(3) for z in range(3)]
-    l1 = [(1, x, y, z) for x in range(6) for y in range(2) for z in range(6)]
+    n0 = [3, 3, 3]
+    n0[axis] = 1
+    subs = [(0, x, y, z) for x in range(n0[0]) for y in range(n0[1]) for z in range(n0[2])]
+    l1 = [(1, x, y, z) for x in range(2 * n0[0]) for y in range(2 * n0[1]) for z in range(2 * n0[2])]
     subs += l1
     for k in rng.choice(len(l1), 5, replace=False):
         _, x, y, z = l1[k]
@@ -636,6 +640,33 @@ def test_plane_pairs_default_follows_the_item_count():
             got = p.launch_shape()["plane_pairs"]
         print(f"  {W.name}: {n_ref} refined non-top targets, plane_pairs {got}", flush=True)
         assert got == int(n_ref * 4 * groups >= 8 * n_cu)
+
+
+@pytest.mark.parametrize("shape", ["per_class_g2", "persistent_g1", "persistent_g1_pairs", "persistent_g3_single"])
+def test_x_sweep_targets_fp64(shape):
+    t, rho = flat_forest(7, axis=0)
+    n_x = fm.fmmg_count_pairs([t])["sweep_x_targets"]
+    phi, g, st = run([t], rho, **SHAPES[shape])
+    pr, gr, ost = oracle.solve(t, rho, with_stats=True)
+    errs = field_errors(phi, g, pr, gr)
+    f, tq = residuals(t, rho, g, centre=(0.0625, 0.75, 0.75))
+    print(f"  {n_x} x-sweep targets, errors {errs}, force {f:.3e} torque {tq:.3e}", flush=True)
+    assert n_x >= 3 and st["pairs"][3] > 0
+    assert max(errs) < TOL64
+    assert st["pairs"] == ost["cls"]
+    assert f < 1e-13 and tq < 1e-13
+
+
+@pytest.mark.parametrize("precision", ["mixed", "mixed_f32"])
+def test_x_sweep_targets_mixed(precision):
+    t, rho = flat_forest(9, axis=0)
+    assert fm.fmmg_count_pairs([t])["sweep_x_targets"] >= 3
+    phi, g, _ = run([t], rho, precision=precision, persistent=True, plane_pairs=True)
+    pr, gr = oracle.solve(t, rho)
+    errs = field_errors(phi, g, pr, gr)
+    f, tq = residuals(t, rho, g, centre=(0.0625, 0.75, 0.75))
+    print(f"  {precision} errors {errs} force {f:.3e} torque {tq:.3e}", flush=True)
+    check_form("amr", precision, errs, f, tq)
 
 
 # ---------------------------------------------------------------------------

@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(fm.EXPORTED)
     for n in names:
         assert hasattr(L, n), n
-    assert fm.fmmg_version() == 5
+    assert fm.fmmg_version() == 6
 
 
 def test_default_options():
@@ -124,8 +124,9 @@ def test_malformed_trees_are_rejected():
 def _plane_visits(usable, sweep, near, far_by_w, near_by_w):
     """Stencil entries the plane items of one target visit in a sweep frame:
     a source plane is visited iff one of the 9 neighbour sub-grids at its
-    offset along the sweep axis (z: sweep 0, y: sweep 1) is usable."""
-    axis = 2 if sweep == 0 else 1
+    offset along the sweep axis (z: sweep 0, y: sweep 1, x: sweep 2) is
+    usable."""
+    axis = (2, 1, 0)[sweep]
     n = 0
     for t in range(8):
         s = 1 - 2 * (t & 1)
@@ -139,9 +140,9 @@ def _plane_visits(usable, sweep, near, far_by_w, near_by_w):
 
 @pytest.mark.parametrize("name", ["c2", "amr3"])
 def test_planner_sweep_choice(name):
-    """The planner runs a refined target's plane items along y exactly when
-    that frame visits fewer stencil entries than the z frame; recounted here
-    from the interaction rule and the tree alone."""
+    """The planner runs a refined target's plane items along the axis (z, y
+    or x) whose frame visits the fewest stencil entries, z before y before x
+    on a tie; recounted here from the interaction rule and the tree alone."""
     import itertools
     W = wl.c2() if name == "c2" else wl.small_amr(3, max_level=3, p_refine=0.3)
     t = W.trees[0]
@@ -153,7 +154,7 @@ def test_planner_sweep_choice(name):
     assert far.sum() == 651 and near.sum() == 92
     ref = t.refined_mask()
     key = {(int(l), *map(int, c)): i for i, (l, c) in enumerate(zip(t.level, t.coord))}
-    n_y = 0
+    n_y = n_x = 0
     for s in range(t.n_subgrids):
         lv, c = int(t.level[s]), t.coord[s]
         if lv == 0:
@@ -168,11 +169,13 @@ def test_planner_sweep_choice(name):
         if not ref[s]:
             continue                      # leaf targets are grouped by parent cell, not by plane
         usable, near_on = nb >= 0, bool((others == 0).any())
-        v = [_plane_visits(usable, sw, near_on, far, near) for sw in (0, 1)]
-        n_y += v[1] < v[0]
+        v = [_plane_visits(usable, sw, near_on, far, near) for sw in (0, 1, 2)]
+        best = min(range(3), key=lambda k: (v[k], k))
+        n_y += best == 1
+        n_x += best == 2
     st = fm.fmmg_count_pairs([t])
-    print(f"  {name}: {n_y} targets along y", flush=True)
-    assert st["sweep_y_targets"] == n_y and n_y > 0
+    print(f"  {name}: {n_y} targets along y, {n_x} along x", flush=True)
+    assert st["sweep_y_targets"] == n_y and st["sweep_x_targets"] == n_x and n_y > 0 and n_x > 0
 
 
 def test_bench_refuses_more_than_one_gpu():
