@@ -774,8 +774,8 @@ __device__ __forceinline__ void mp_item(const Ctx& cx, int sid, int planes, int 
     if (t < 27) nb[t] = T.nbr[t];
     const double h = T.h;
     const int tidx = T.idx;
-    // cell index strides of the frame's v and w, and neighbour-code strides
-    // of their sub-grid offsets (x: stride 1, code stride 9, in both frames)
+    // cell-index strides of the frame's axes u, v, w and neighbour-code
+    // strides of their sub-grid offsets
     using F = Frame<SWEEP>;
     constexpr int US = F::US, VS = F::VS, WS = F::WS, UN = F::UN, VN = F::VN, WN = F::WN;
     const int q = zt * WS + y * VS + x * US;
